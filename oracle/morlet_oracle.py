@@ -1,0 +1,464 @@
+"""FP64 CPU oracle for the Morlet wavelet transform and Gaussian smoothing by
+SFT / ASFT evaluated as kernel integrals (Yamashita & Wakahara, arXiv 2110.11866).
+
+TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import this module. The product path never calls it, and it
+shares no code with the HIP library (it does not import the package, and the
+package does not import it).
+
+Everything here is plain numpy/scipy in float64, written to be checked against
+the paper by eye. Notation follows the paper with one renaming, because the
+paper uses K for the half width of the summation window while the library API
+uses K for the number of Fourier terms:
+
+    L      half width of the window [-L, L]         (the paper's K)
+    beta   pi / L                                   (Sec. II-A, "Let beta = pi/K")
+    K      number of Fourier terms                  (the paper's P+1 for the
+                                                     Gaussian, P_D for Morlet)
+    P_S    lowest Fourier order of the direct method (Sec. III-A)
+    gamma  1 / (2 sigma^2)                          (Sec. II)
+    n0     ASFT output shift, alpha = 2 gamma n0 = n0 / sigma^2  (eq. siftGauss)
+
+Readings of passages that are garbled or ambiguous in the paper (all of them
+are listed, with evidence, in the design notes of the repository):
+  * the dilated discrete Morlet wavelet carries C_xi / (pi^(1/4) sqrt(sigma))
+    and the sample index n in the carrier (Sec. III, discrete psi);
+  * xi is given in rad/sample; the dimensionless xi of the continuous wavelet
+    is xi0 = xi * sigma and feeds C_xi and kappa_xi;
+  * ASFT uses the causal weight e^{-alpha k} for k >= 0 (older samples decay,
+    as the text under eq. asp says), so the extraction prefactor is e^{+alpha L}
+    and the output is read n0 samples earlier (eqs. asfiir12K, GsASFT);
+  * the Morlet ASFT formula of Sec. III-A is completed with the carrier phase
+    e^{i xi n0} that the shift of eq. siftGauss introduces;
+  * x is zero outside [0, N-1] (one of the two extensions Sec. II names).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.signal import lfilter
+
+__all__ = [
+    "gaussian", "morlet", "Plan", "plan_morlet", "plan_gauss", "fit_morlet", "fit_gauss",
+    "select_PS", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
+    "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
+    "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
+]
+
+
+# --------------------------------------------------------------------------
+# Kernels (Sec. II: Gaussian; Sec. III: Morlet wavelet)
+# --------------------------------------------------------------------------
+def gaussian(sigma: float, k: np.ndarray) -> np.ndarray:
+    """G[k] = sqrt(gamma/pi) exp(-gamma k^2), gamma = 1/(2 sigma^2) (Sec. II).
+
+    Not renormalised on the integers."""
+    gamma = 1.0 / (2.0 * sigma * sigma)
+    k = np.asarray(k, dtype=np.float64)
+    return math.sqrt(gamma / math.pi) * np.exp(-gamma * k * k)
+
+
+def _morlet_consts(xi0: float) -> tuple[float, float]:
+    """C_xi and kappa_xi of the mother wavelet (Sec. III)."""
+    C = (1.0 + math.exp(-xi0 * xi0) - 2.0 * math.exp(-0.75 * xi0 * xi0)) ** -0.5
+    kappa = math.exp(-0.5 * xi0 * xi0)
+    return C, kappa
+
+
+def morlet(sigma: float, xi: float, k: np.ndarray) -> np.ndarray:
+    """Dilated discrete Morlet wavelet psi_{sigma,xi}[k] (Sec. III).
+
+    psi[k] = C/(pi^(1/4) sqrt(sigma)) e^{-k^2/(2 sigma^2)} (e^{i xi k} - kappa),
+    xi in rad/sample, xi0 = xi*sigma the dimensionless carrier."""
+    xi0 = xi * sigma
+    C, kappa = _morlet_consts(xi0)
+    k = np.asarray(k, dtype=np.float64)
+    env = C / (math.pi ** 0.25 * math.sqrt(sigma)) * np.exp(-k * k / (2.0 * sigma * sigma))
+    return env * (np.exp(1j * xi * k) - kappa)
+
+
+def dpsi_dtheta(sigma: float, xi: float, k: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """Analytic partial derivatives d psi / d sigma and d psi / d xi of morlet().
+
+    Written out from the product rule on the Sec. III formula with xi0 = xi*sigma:
+      psi = A(xi0) sigma^{-1/2} E(k, sigma) (e^{i xi k} - kappa(xi0)),
+      A = C(xi0) pi^{-1/4},  E = exp(-k^2 / (2 sigma^2)).
+    """
+    k = np.asarray(k, dtype=np.float64)
+    xi0 = xi * sigma
+    C, kappa = _morlet_consts(xi0)
+    # dC/dxi0 from C = D^{-1/2}, D = 1 + e^{-xi0^2} - 2 e^{-3 xi0^2 / 4}
+    dD = -2.0 * xi0 * math.exp(-xi0 * xi0) + 3.0 * xi0 * math.exp(-0.75 * xi0 * xi0)
+    D = 1.0 + math.exp(-xi0 * xi0) - 2.0 * math.exp(-0.75 * xi0 * xi0)
+    dC = -0.5 * D ** -1.5 * dD
+    dkappa = -xi0 * kappa
+    A = C / math.pi ** 0.25
+    dA = dC / math.pi ** 0.25
+    E = np.exp(-k * k / (2.0 * sigma * sigma))
+    dE_dsigma = E * (k * k / sigma ** 3)
+    car = np.exp(1j * xi * k) - kappa
+    s = sigma ** -0.5
+    ds = -0.5 * sigma ** -1.5
+    # d/dsigma: xi0 depends on sigma (dxi0/dsigma = xi); the carrier e^{i xi k} does not.
+    d_sigma = (dA * xi) * s * E * car + A * ds * E * car + A * s * dE_dsigma * car \
+        + A * s * E * (-dkappa * xi)
+    # d/dxi: xi0 depends on xi (dxi0/dxi = sigma); the carrier gives i k e^{i xi k}.
+    d_xi = (dA * sigma) * s * E * car + A * s * E * (1j * k * np.exp(1j * xi * k) - dkappa * sigma)
+    return d_sigma, d_xi
+
+
+# --------------------------------------------------------------------------
+# Plan: the truncated Fourier fits (eqs. aproGauss, mmse; Sec. III-A)
+# --------------------------------------------------------------------------
+@dataclass
+class Plan:
+    kind: str                 # "morlet" or "gauss"
+    sigma: float
+    xi: float                 # rad/sample (0 for the Gaussian)
+    K: int                    # number of Fourier terms
+    L: int                    # window half width
+    P_S: int                  # lowest order (0 for the Gaussian)
+    mode: str = "sft"         # "sft" or "asft"
+    n0: int = 0               # ASFT shift
+    cos_coef: np.ndarray = field(default_factory=lambda: np.zeros(0))  # m_p or a_p
+    sin_coef: np.ndarray = field(default_factory=lambda: np.zeros(0))  # l_p (zeros for Gauss)
+
+    @property
+    def beta(self) -> float:
+        return math.pi / self.L
+
+    @property
+    def orders(self) -> np.ndarray:
+        return np.arange(self.P_S, self.P_S + self.K)
+
+    @property
+    def alpha(self) -> float:
+        return self.n0 / (self.sigma * self.sigma) if self.mode == "asft" else 0.0
+
+
+def _basis(L: int, orders: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """k = -L..L and the columns cos(beta p k), sin(beta p k) (eqs. cp, sp)."""
+    k = np.arange(-L, L + 1, dtype=np.float64)
+    # exact argument reduction: beta p k = pi * ((p k) mod 2L) / L
+    pk = np.mod(np.outer(k.astype(np.int64), orders.astype(np.int64)), 2 * L).astype(np.float64)
+    ang = math.pi * pk / L
+    return k, np.cos(ang), np.sin(ang)
+
+
+def _lstsq(B: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Minimum-squared-error coefficients (eq. mmse), columns that vanish on the
+    integer grid (sin of order 0 or L) get coefficient 0."""
+    coef = np.zeros(B.shape[1])
+    keep = np.linalg.norm(B, axis=0) > 1e-9 * math.sqrt(B.shape[0])
+    if keep.any():
+        coef[keep] = np.linalg.lstsq(B[:, keep], y, rcond=None)[0]
+    return coef
+
+
+def fit_morlet(sigma: float, xi: float, K: int, L: int, P_S: int) -> tuple[np.ndarray, np.ndarray]:
+    """Direct method (Sec. III-A): psi[k] ~ sum_p m_p cos(beta p k) + i l_p sin(beta p k)
+    for p = P_S..P_S+K-1 on k in [-L, L]; m and l by MMSE, fitted to Re and Im
+    separately (the two parts of the squared error decouple)."""
+    orders = np.arange(P_S, P_S + K)
+    k, Bc, Bs = _basis(L, orders)
+    psi = morlet(sigma, xi, k)
+    return _lstsq(Bc, psi.real), _lstsq(Bs, psi.imag)
+
+
+def fit_gauss(sigma: float, K: int, L: int) -> np.ndarray:
+    """eq. aproGauss with orders 0..K-1, coefficients a_p by MMSE (eq. mmse)."""
+    k, Bc, _ = _basis(L, np.arange(K))
+    return _lstsq(Bc, gaussian(sigma, k))
+
+
+def _ps_range(xi: float, K: int, L: int) -> range:
+    """Candidate lowest orders. Orders alias modulo 2L, so P_S + K - 1 <= L.
+    The carrier sits at order xi L / pi; windows that start more than K orders
+    above it only lose carrier energy, so the search stops there."""
+    hi = min(L - K + 1, int(math.ceil(xi * L / math.pi)) + K)
+    return range(0, max(hi, 0) + 1)
+
+
+def kernel_relrmse(approx: np.ndarray, exact: np.ndarray) -> float:
+    return float(np.linalg.norm(approx - exact) / np.linalg.norm(exact))
+
+
+def select_PS(sigma: float, xi: float, K: int, L: int) -> int:
+    """P_S minimising the relative RMSE of the fitted wavelet on [-L, L]
+    (Sec. V-A, the optimum P_S of Fig. MSE2); ties go to the smallest P_S."""
+    k = np.arange(-L, L + 1, dtype=np.float64)
+    psi = morlet(sigma, xi, k)
+    best, best_err = 0, math.inf
+    for ps in _ps_range(xi, K, L):
+        m, l = fit_morlet(sigma, xi, K, L, ps)
+        err = kernel_relrmse(_kterm(m, l, ps, L), psi)
+        if err < best_err * (1.0 - 1e-12):
+            best, best_err = ps, err
+    return best
+
+
+def default_n0(sigma: float) -> int:
+    return max(1, int(round(sigma / 8.0)))
+
+
+def plan_morlet(sigma: float, xi: float, K: int, L: int, mode: str = "sft",
+                n0: int | None = None, P_S: int | None = None) -> Plan:
+    if P_S is None:
+        P_S = select_PS(sigma, xi, K, L)
+    m, l = fit_morlet(sigma, xi, K, L, P_S)
+    if mode == "asft" and n0 is None:
+        n0 = default_n0(sigma)
+    return Plan("morlet", sigma, xi, K, L, P_S, mode, int(n0 or 0) if mode == "asft" else 0, m, l)
+
+
+def plan_gauss(sigma: float, K: int, L: int, mode: str = "sft", n0: int | None = None) -> Plan:
+    a = fit_gauss(sigma, K, L)
+    if mode == "asft" and n0 is None:
+        n0 = default_n0(sigma)
+    return Plan("gauss", sigma, 0.0, K, L, 0, mode, int(n0 or 0) if mode == "asft" else 0,
+                a, np.zeros(K))
+
+
+# --------------------------------------------------------------------------
+# The K-term kernels as explicit taps (plain definitions the method equals)
+# --------------------------------------------------------------------------
+def _kterm(cos_coef, sin_coef, P_S, L) -> np.ndarray:
+    orders = np.arange(P_S, P_S + len(cos_coef))
+    _, Bc, Bs = _basis(L, orders)
+    return Bc @ cos_coef + 1j * (Bs @ sin_coef)
+
+
+def kterm_morlet(plan: Plan) -> np.ndarray:
+    """psi_hat[k], k = -L..L (Sec. III-A)."""
+    return _kterm(plan.cos_coef, plan.sin_coef, plan.P_S, plan.L)
+
+
+def kterm_gauss(plan: Plan) -> np.ndarray:
+    """G_hat[k], k = -L..L (eq. aproGauss); real."""
+    return _kterm(plan.cos_coef, plan.sin_coef, plan.P_S, plan.L).real
+
+
+def asft_kernel(plan: Plan) -> np.ndarray:
+    """Taps h[k], k = -L..L, of the ASFT result written as a plain convolution
+    y[n] = sum_k h[k] x[n - n0 - k]:
+      h[k] = e^{i xi n0} e^{-n0^2/(2 sigma^2)} e^{-alpha k} khat[k]
+    (eqs. siftGauss and GsASFT, Sec. III-A; alpha^2/(4 gamma) = n0^2/(2 sigma^2))."""
+    k = np.arange(-plan.L, plan.L + 1, dtype=np.float64)
+    base = kterm_morlet(plan) if plan.kind == "morlet" else kterm_gauss(plan).astype(np.complex128)
+    scale = math.exp(-plan.n0 ** 2 / (2.0 * plan.sigma ** 2))
+    ph = np.exp(1j * plan.xi * plan.n0) if plan.kind == "morlet" else 1.0
+    return ph * scale * np.exp(-plan.alpha * k) * base
+
+
+# --------------------------------------------------------------------------
+# Plain convolution, x zero outside [0, N-1] (eqs. xG..xGDD)
+# --------------------------------------------------------------------------
+def conv_same(x: np.ndarray, h: np.ndarray, L: int, shift: int = 0) -> np.ndarray:
+    """y[n] = sum_{k=-L}^{L} h[k] x[n - shift - k], n = 0..N-1."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    if N == 0:
+        return np.zeros(0, dtype=np.result_type(h, np.float64))
+    full = np.convolve(x, h)            # full[i] = sum_k h[k+L] x[i - (k+L)]
+    idx = np.arange(N) - shift + L      # index of n - shift in 'full'
+    out = np.zeros(N, dtype=full.dtype)
+    ok = (idx >= 0) & (idx < full.shape[0])
+    out[ok] = full[idx[ok]]
+    return out
+
+
+def conv_same_at(x: np.ndarray, h: np.ndarray, L: int, ns: np.ndarray, shift: int = 0) -> np.ndarray:
+    """conv_same evaluated only at the outputs ns, one direct sum per output."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    out = np.zeros(len(ns), dtype=np.result_type(h, np.float64))
+    k = np.arange(-L, L + 1)
+    for i, n in enumerate(ns):
+        j = n - shift - k
+        ok = (j >= 0) & (j < N)
+        out[i] = np.sum(h[ok] * x[j[ok]])
+    return out
+
+
+# --------------------------------------------------------------------------
+# Kernel integral (Sec. II-B) and its attenuated version (Sec. II-D)
+# --------------------------------------------------------------------------
+def phase(p: int, j: np.ndarray, L: int) -> np.ndarray:
+    """e^{i beta p j}, with the argument reduced exactly: beta p j = pi ((p j) mod 2L) / L."""
+    r = np.mod(np.asarray(j, dtype=np.int64) * int(p), 2 * L).astype(np.float64)
+    return np.exp(1j * math.pi * r / L)
+
+
+def sft_component(x: np.ndarray, p: int, L: int) -> np.ndarray:
+    """Z_p[n] = c_p[n] - i s_p[n] = sum_{k=-L}^{L} x[n-k] e^{-i beta p k} (eqs. cp, sp)
+    computed the paper's way:
+      u[n]   = u[n-1] + x[n] e^{i beta p n}               (eqs. kernel, kernelZenka)
+      u_w[n] = u[n] - u[n-2L-1]                           (eqs. kernelInt, kernelInter)
+      c_p[n] - i s_p[n] = e^{-i beta p n} u_w[n+L]        (SFT from the kernel integral)
+    with x zero outside [0, N-1], so u is held constant beyond N-1 and is 0 below 0."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    j = np.arange(N)
+    u = np.cumsum(x * phase(p, j, L))               # u[0..N-1]
+
+    def U(idx):                                      # u extended: 0 below 0, held above N-1
+        idx = np.asarray(idx)
+        out = np.zeros(idx.shape, dtype=np.complex128)
+        pos = idx >= 0
+        out[pos] = u[np.minimum(idx[pos], N - 1)]
+        return out
+
+    n = np.arange(N)
+    uw = U(n + L) - U(n - L - 1)
+    return np.conj(phase(p, n, L)) * uw
+
+
+def asft_component(x: np.ndarray, p: int, L: int, alpha: float, q: np.ndarray) -> np.ndarray:
+    """Attenuated component Zt_p[q] = sum_{k=-L}^{L} x[q-k] e^{-alpha k} e^{-i beta p k}
+    (eqs. acp, asp with the causal weight) computed by the attenuated kernel integral:
+      ut[j] = e^{-alpha} ut[j-1] + x[j] e^{i beta p j}      (eq. iir1A, modulated frame)
+      Zt[q] = e^{alpha L} e^{-i beta p q} (ut[q+L] - e^{-alpha(2L+1)} ut[q-L-1])
+    (eq. aiir12K with the prefactor of eq. asfiir12K). Beyond N-1 the input is
+    zero, so ut keeps decaying: ut[j] = ut[N-1] e^{-alpha (j-N+1)}; below 0 it is 0.
+    Evaluated at the requested positions q (any integers)."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    j = np.arange(N)
+    ut = lfilter([1.0], [1.0, -math.exp(-alpha)], x * phase(p, j, L))
+
+    def U(idx):
+        idx = np.asarray(idx)
+        out = np.zeros(idx.shape, dtype=np.complex128)
+        inr = (idx >= 0) & (idx < N)
+        out[inr] = ut[idx[inr]]
+        hi = idx >= N
+        out[hi] = ut[N - 1] * np.exp(-alpha * (idx[hi] - (N - 1)))
+        return out
+
+    q = np.asarray(q, dtype=np.int64)
+    diff = U(q + L) - math.exp(-alpha * (2 * L + 1)) * U(q - L - 1)
+    return math.exp(alpha * L) * np.conj(phase(p, q, L)) * diff
+
+
+def forward(x: np.ndarray, plan: Plan) -> np.ndarray:
+    """Method result.
+
+    Morlet, SFT:  x_M[n] = sum_p m_p c_p[n] + i l_p s_p[n]            (Sec. III-A)
+    Morlet, ASFT: x_M[n] = e^{i xi n0} e^{-n0^2/(2 sigma^2)}
+                           sum_p m_p ct_p[n-n0] + i l_p st_p[n-n0]
+    Gauss,  SFT:  x_G[n] = sum_p a_p c_p[n]                            (eq. GsSFT)
+    Gauss,  ASFT: x_G[n] = e^{-n0^2/(2 sigma^2)} sum_p a_p ct_p[n-n0]  (eq. GsASFT)
+    with c - i s = Z, so c = Re Z and s = -Im Z."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    acc = np.zeros(N, dtype=np.complex128)
+    if N == 0:
+        return acc if plan.kind == "morlet" else acc.real
+    for i, p in enumerate(plan.orders):
+        if plan.mode == "sft":
+            Z = sft_component(x, int(p), plan.L)
+        else:
+            Z = asft_component(x, int(p), plan.L, plan.alpha, np.arange(N) - plan.n0)
+        acc += plan.cos_coef[i] * Z.real - 1j * plan.sin_coef[i] * Z.imag
+    if plan.mode == "asft":
+        acc *= math.exp(-plan.n0 ** 2 / (2.0 * plan.sigma ** 2))
+        if plan.kind == "morlet":
+            acc *= np.exp(1j * plan.xi * plan.n0)
+    return acc if plan.kind == "morlet" else acc.real
+
+
+def forward_direct(x: np.ndarray, sigma: float, xi: float | None, L: int) -> np.ndarray:
+    """Truncated direct convolution with the exact kernel on [-L, L] (eq. xG; the
+    comparison method of Sec. V-B uses the window [-3 sigma, 3 sigma])."""
+    k = np.arange(-L, L + 1)
+    h = gaussian(sigma, k) if xi is None else morlet(sigma, xi, k)
+    return conv_same(x, h, L)
+
+
+# --------------------------------------------------------------------------
+# Differentiation (no counterpart in the paper; derived from the forward map)
+# --------------------------------------------------------------------------
+def _taps_and_shift(plan: Plan) -> tuple[np.ndarray, int]:
+    if plan.mode == "asft":
+        return asft_kernel(plan), plan.n0
+    base = kterm_morlet(plan) if plan.kind == "morlet" else kterm_gauss(plan)
+    return base, 0
+
+
+def adjoint(g: np.ndarray, plan: Plan) -> np.ndarray:
+    """Transpose of the real-input forward map W = A x for a real-valued loss.
+
+    With W[n] = sum_k h[k] x[n - s - k] and g = dLoss/dRe W + i dLoss/dIm W,
+      dLoss/dx[j] = Re sum_n conj(g[n]) h[n - s - j] = Re sum_k conj(h[k]) g[j + s + k].
+    Written as a plain sum over the taps."""
+    h, s = _taps_and_shift(plan)
+    g = np.asarray(g, dtype=np.complex128)
+    N = g.shape[0]
+    out = np.zeros(N)
+    L = plan.L
+    for idx, k in enumerate(range(-L, L + 1)):
+        # contribution conj(h[k]) g[j + s + k] for every j with 0 <= j + s + k < N
+        lo = max(0, -(s + k))
+        hi = min(N, N - (s + k))
+        if hi > lo:
+            out[lo:hi] += (np.conj(h[idx]) * g[lo + s + k: hi + s + k]).real
+    return out
+
+
+def _jacobian(plan: Plan) -> np.ndarray:
+    """d(cos_coef, sin_coef)/d(sigma, xi) for the frozen basis (L, P_S, K fixed):
+    the MMSE coefficients are linear in the target, c = pinv(B) target, so
+    dc/dtheta = pinv(B) dtarget/dtheta. Returns array [2K, 2] (rows: m then l)."""
+    k, Bc, Bs = _basis(plan.L, plan.orders)
+    if plan.kind == "morlet":
+        ds, dx = dpsi_dtheta(plan.sigma, plan.xi, k)
+        cols = []
+        for d in (ds, dx):
+            cols.append(np.concatenate([_lstsq(Bc, d.real), _lstsq(Bs, d.imag)]))
+        return np.stack(cols, axis=1)
+    # Gaussian: dG/dsigma = G (k^2/sigma^3 - 1/sigma); no xi
+    G = gaussian(plan.sigma, k)
+    dG = G * (k * k / plan.sigma ** 3 - 1.0 / plan.sigma)
+    return np.stack([np.concatenate([_lstsq(Bc, dG), np.zeros(plan.K)]),
+                     np.zeros(2 * plan.K)], axis=1)
+
+
+def param_grads(x: np.ndarray, g: np.ndarray, plan: Plan) -> np.ndarray:
+    """[dLoss/dsigma, dLoss/dxi] with (L, P_S, n0, K) frozen, for a real loss with
+    complex cotangent g = dLoss/dRe W + i dLoss/dIm W:
+        dLoss/dtheta = Re sum_n conj(g[n]) dW[n]/dtheta,
+    where W is a plain convolution whose taps depend on theta through the fitted
+    coefficients and, for ASFT, through alpha = n0/sigma^2, the scale
+    e^{-n0^2/(2 sigma^2)} and the phase e^{i xi n0}."""
+    J = _jacobian(plan)
+    K, L = plan.K, plan.L
+    k = np.arange(-L, L + 1, dtype=np.float64)
+    g = np.asarray(g, dtype=np.complex128)
+    out = np.zeros(2)
+    for t in range(2):
+        dcos, dsin = J[:K, t], J[K:, t]
+        dbase = _kterm(dcos, dsin, plan.P_S, L)
+        if plan.kind == "gauss":
+            dbase = dbase.real.astype(np.complex128)
+        if plan.mode == "asft":
+            base = kterm_morlet(plan) if plan.kind == "morlet" else kterm_gauss(plan).astype(np.complex128)
+            n0, sig = plan.n0, plan.sigma
+            scale = math.exp(-n0 ** 2 / (2 * sig ** 2))
+            ph = np.exp(1j * plan.xi * n0) if plan.kind == "morlet" else 1.0
+            att = np.exp(-plan.alpha * k)
+            dh = ph * scale * att * dbase
+            if t == 0:   # sigma also moves alpha = n0/sigma^2 and the scale
+                dalpha = -2.0 * n0 / sig ** 3
+                dscale = scale * (n0 ** 2 / sig ** 3)
+                dh = dh + ph * dscale * att * base + ph * scale * (-k * dalpha) * att * base
+            elif plan.kind == "morlet":   # xi moves the phase
+                dh = dh + (1j * n0) * ph * scale * att * base
+            dW = conv_same(x, dh, L, shift=n0)
+        else:
+            dW = conv_same(x, dbase, L)
+            if plan.kind == "gauss":
+                dW = dW.real
+        out[t] = np.sum((np.conj(g) * dW).real)
+    return out
