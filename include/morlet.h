@@ -1,0 +1,136 @@
+/*
+ * morlet.h - C ABI of the MI355X (gfx950) library for the Morlet wavelet transform and
+ * Gaussian smoothing computed by the sliding Fourier transform (SFT) and the attenuated
+ * SFT (ASFT) evaluated as kernel integrals (Yamashita & Wakahara, arXiv 2110.11866).
+ *
+ * Problem statement (Sec. II, Sec. III): a real signal x[n], n = 0..N-1, zero outside
+ * that interval, is filtered by a kernel on the window [-L, L] (the paper calls the half
+ * width K; here K is the number of Fourier terms):
+ *
+ *   Morlet, direct method (Sec. III-A):
+ *     psi_hat[k] = sum_{p=P_S}^{P_S+K-1} m_p cos(beta p k) + i l_p sin(beta p k),  beta = pi/L,
+ *     with m, l fitted to the dilated Morlet wavelet by minimum squared error (eq. mmse);
+ *     SFT : W[n] = sum_{k=-L}^{L} psi_hat[k] x[n-k]
+ *     ASFT: W[n] = e^{i xi n0} e^{-n0^2/(2 sigma^2)} sum_{k=-L}^{L} e^{-alpha k} psi_hat[k] x[n-n0-k],
+ *           alpha = n0 / sigma^2 (eqs. acp, asfiir12K, siftGauss, GsASFT; the weight decays
+ *           for older samples and the output is read n0 samples earlier);
+ *   Gaussian (eqs. aproGauss, GsSFT, GsASFT): the same with orders 0..K-1 and the fitted
+ *     Gaussian G_hat[k] = sum_p a_p cos(beta p k); the result is real.
+ *
+ * The library never forms the 2L+1 taps on the device. Each term is a kernel integral
+ * (eqs. kernel..kernelInter) evaluated by one fused prefix-scan kernel per call.
+ *
+ * Conventions for every call below
+ *  - Host vs device: plan handles and the arrays documented "host" live in host memory;
+ *    x, W, y, gW, gx, gparams and the workspace are device pointers on the device that
+ *    was current when the plan was created.
+ *  - Layout: real arrays are contiguous; complex arrays are interleaved (re, im) float32
+ *    pairs (complex64), contiguous, 8-byte aligned.
+ *  - Ownership: the caller owns every array it passes. A plan owns its host data and a
+ *    small device table allocated when it is created; morlet_destroy frees both.
+ *  - Streams: every launch goes on the given hipStream_t (passed as void*, NULL = the
+ *    default stream). Calls are asynchronous and allocate nothing, so they may be
+ *    captured in a HIP graph.
+ *  - Workspace: forward and backward calls need a device workspace of at least the size
+ *    that morlet_workspace_size returns, zero-filled once before its first use
+ *    (morlet_workspace_init, or any zero fill). After that it needs no clearing: calls
+ *    leave it ready for the next call. Calls that overlap in time must not share one.
+ *  - Errors: invalid arguments are reported synchronously, before anything is launched,
+ *    with no side effect. A failed HIP launch returns MORLET_ERR_HIP. Asynchronous faults
+ *    show up at the caller's next synchronisation. morlet_last_error() returns a message
+ *    for the calling thread's last failure.
+ */
+#ifndef MORLET_H_
+#define MORLET_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct morlet_plan_s* morlet_plan_t;
+
+typedef enum {
+  MORLET_OK = 0,
+  MORLET_ERR_INVALID_ARG = 1,
+  MORLET_ERR_UNSUPPORTED = 2,
+  MORLET_ERR_ALLOC = 3,
+  MORLET_ERR_WORKSPACE = 4,
+  MORLET_ERR_HIP = 5
+} morlet_status;
+
+/* Storage type of the input signal; arithmetic is float32 (or float64, see below). */
+typedef enum { MORLET_F32 = 0, MORLET_F16 = 1, MORLET_BF16 = 2 } morlet_dtype;
+
+/* Transform: plain SFT (Sec. II-A/B) or attenuated SFT (Sec. II-D/E). */
+typedef enum { MORLET_SCAN_SFT = 0, MORLET_SCAN_ASFT = 1 } morlet_scan;
+
+/* Scan accumulation: float32 throughout, or compensated (the scan state, its carries and
+ * the K-term combination held in float64 while the input and output stay 32-bit). */
+typedef enum { MORLET_ACC_F32 = 0, MORLET_ACC_COMPENSATED = 1 } morlet_accum;
+
+/* Maximum number of Fourier terms a plan may use. */
+#define MORLET_MAX_TERMS 12
+
+/* Create a Morlet plan for signals of length N (Sec. III-A, direct method).
+ *   sigma > 0   : dilation of the wavelet (standard deviation of its Gaussian), samples
+ *   xi    > 0   : carrier in rad/sample (the dimensionless carrier is xi*sigma)
+ *   K           : number of Fourier terms, 1..MORLET_MAX_TERMS
+ *   L           : window half width, K <= L <= 2^30; or 0 to choose the L of smallest
+ *                 kernel error on the grid L = round(c sigma), c = 1.50, 1.52, ..., 5.00
+ *                 (Sec. V-A chooses the window by minimum error)
+ * The lowest order P_S is the one of smallest kernel relative RMSE (Sec. V-A, Fig. MSE2)
+ * among 0..min(L-K+1, ceil(xi L / pi) + K); ties go to the smallest P_S.
+ * Defaults: SFT, float32 accumulation, n0 = max(1, round(sigma/8)) for ASFT.
+ * N >= 0 (N = 0 makes every call a no-op). Allocates the plan's device table on the
+ * current device. Errors: MORLET_ERR_INVALID_ARG, MORLET_ERR_ALLOC, MORLET_ERR_HIP. */
+morlet_status morlet_plan(morlet_plan_t* out, int64_t N, double sigma, double xi, int32_t K,
+                          int64_t L);
+
+/* Create a Gaussian-smoothing plan (eq. aproGauss, orders 0..K-1; eq. GsSFT / GsASFT).
+ * Same argument rules as morlet_plan without xi; K <= L + 1. */
+morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int32_t K,
+                                int64_t L);
+
+/* Select SFT or ASFT, the ASFT shift n0 (0 = default; 1 <= n0 <= L otherwise) and the
+ * accumulation precision. Rebuilds the device table (synchronously). */
+morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,
+                              morlet_accum accum);
+
+/* Plan parameters (host outputs; any pointer may be NULL).
+ *   cos_coef[K]: m_p (Morlet) or a_p (Gaussian); sin_coef[K]: l_p (0 for Gaussian);
+ *   jac[4*K]: d(cos_coef)/dsigma, d(cos_coef)/dxi, d(sin_coef)/dsigma, d(sin_coef)/dxi
+ *             for the frozen (L, P_S, K), each K long;
+ *   kernel_relrmse: ||fit - kernel|| / ||kernel|| on [-L, L]. */
+morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int64_t* n0,
+                               double* alpha, double* cos_coef, double* sin_coef, double* jac,
+                               double* kernel_relrmse);
+
+/* Device workspace bytes needed by forward/backward calls on this plan. */
+morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes);
+
+/* Zero-fill a workspace on the stream (needed once, before its first use). */
+morlet_status morlet_workspace_init(void* ws, size_t ws_bytes, void* stream);
+
+/* Morlet transform: W[n], n = 0..N-1, complex64 (device), from x (device, N elements of
+ * the given dtype). Returns MORLET_ERR_INVALID_ARG for a Gaussian plan or NULL pointers,
+ * MORLET_ERR_WORKSPACE if ws_bytes is too small. */
+morlet_status morlet_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Gaussian smoothing: y[n] float32 (device). Needs a Gaussian plan. */
+morlet_status gauss_smooth(morlet_plan_t plan, const void* x, morlet_dtype dtype, float* y,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Destroy a plan (NULL is ignored). Not stream-ordered: no call using it may be pending. */
+void morlet_destroy(morlet_plan_t plan);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char* morlet_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MORLET_H_ */

@@ -1,0 +1,120 @@
+"""ctypes binding of libmorlet.so (include/morlet.h): the same entry points, argument
+marshalling only. Device memory and streams come from PyTorch; every step of the
+transform runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmorlet.so")
+
+MORLET_OK = 0
+MORLET_ERR_INVALID_ARG = 1
+MORLET_ERR_UNSUPPORTED = 2
+MORLET_ERR_ALLOC = 3
+MORLET_ERR_WORKSPACE = 4
+MORLET_ERR_HIP = 5
+
+MORLET_F32, MORLET_F16, MORLET_BF16 = 0, 1, 2
+MORLET_SCAN_SFT, MORLET_SCAN_ASFT = 0, 1
+MORLET_ACC_F32, MORLET_ACC_COMPENSATED = 0, 1
+MORLET_MAX_TERMS = 12
+
+# every symbol include/morlet.h declares, with (restype, argtypes)
+_i64, _i32, _dbl, _vp, _sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+_P = ctypes.POINTER
+SIGNATURES = {
+    "morlet_plan": (ctypes.c_int, [_P(_vp), _i64, _dbl, _dbl, _i32, _i64]),
+    "morlet_plan_gauss": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64]),
+    "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
+    "morlet_plan_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i32), _P(_i64), _P(_dbl), _P(_dbl), _P(_dbl),
+                                        _P(_dbl), _P(_dbl)]),
+    "morlet_workspace_size": (ctypes.c_int, [_vp, _P(_sz)]),
+    "morlet_workspace_init": (ctypes.c_int, [_vp, _sz, _vp]),
+    "morlet_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "gauss_smooth": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "morlet_destroy": (None, [_vp]),
+    "morlet_last_error": (ctypes.c_char_p, []),
+}
+
+_LIB = None
+
+
+class MorletError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"morlet status {status}: {msg}")
+        self.status = status
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built (there is no fallback path)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2110_11866_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def check(status: int) -> None:
+    if status != MORLET_OK:
+        raise MorletError(status, lib().morlet_last_error().decode())
+
+
+# ----------------------------------------------------------------- same-name wrappers
+def morlet_plan(N: int, sigma: float, xi: float, K: int, L: int) -> int:
+    h = ctypes.c_void_p()
+    check(lib().morlet_plan(ctypes.byref(h), N, sigma, xi, K, L))
+    return h.value
+
+
+def morlet_plan_gauss(N: int, sigma: float, K: int, L: int) -> int:
+    h = ctypes.c_void_p()
+    check(lib().morlet_plan_gauss(ctypes.byref(h), N, sigma, K, L))
+    return h.value
+
+
+def morlet_plan_set(plan: int, mode: int, n0: int, accum: int) -> None:
+    check(lib().morlet_plan_set(plan, mode, n0, accum))
+
+
+def morlet_plan_info(plan: int, K: int) -> dict:
+    L, ps, n0 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    alpha, rel = ctypes.c_double(), ctypes.c_double()
+    cc, sc, jac = (ctypes.c_double * K)(), (ctypes.c_double * K)(), (ctypes.c_double * (4 * K))()
+    check(lib().morlet_plan_info(plan, ctypes.byref(L), ctypes.byref(ps), ctypes.byref(n0), ctypes.byref(alpha),
+                                 cc, sc, jac, ctypes.byref(rel)))
+    return {"L": L.value, "P_S": ps.value, "n0": n0.value, "alpha": alpha.value, "cos_coef": list(cc),
+            "sin_coef": list(sc), "jac": list(jac), "kernel_relrmse": rel.value}
+
+
+def morlet_workspace_size(plan: int) -> int:
+    n = ctypes.c_size_t()
+    check(lib().morlet_workspace_size(plan, ctypes.byref(n)))
+    return n.value
+
+
+def morlet_workspace_init(ws_ptr: int, nbytes: int, stream: int) -> None:
+    check(lib().morlet_workspace_init(ws_ptr, nbytes, stream))
+
+
+def morlet_forward(plan: int, x_ptr: int, dtype: int, W_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    check(lib().morlet_forward(plan, x_ptr, dtype, W_ptr, ws_ptr, ws_bytes, stream))
+
+
+def gauss_smooth(plan: int, x_ptr: int, dtype: int, y_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    check(lib().gauss_smooth(plan, x_ptr, dtype, y_ptr, ws_ptr, ws_bytes, stream))
+
+
+def morlet_destroy(plan: int) -> None:
+    lib().morlet_destroy(plan)
+
+
+def morlet_last_error() -> str:
+    return lib().morlet_last_error().decode()

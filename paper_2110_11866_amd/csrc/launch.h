@@ -1,0 +1,31 @@
+// Launch descriptors between the C ABI layer and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "layout.h"
+
+namespace mk {
+
+struct ScanLaunch {
+  int K, R, wide, kind;         // kind: 0 Morlet (complex64 out), 1 Gaussian (float32 out)
+  const void* x;                // signal(s)
+  int dtype;                    // 0 f32, 1 f16, 2 bf16
+  void* out;                    // complex64 or float32
+  Row row0;                     // the only row when nrows == 1
+  const Row* rows;              // device rows when nrows > 1
+  int nrows;
+  const int32_t* tile_row;      // device: row of every tile when nrows > 1
+  int64_t ntiles;
+  const unsigned char* tabs;    // device constant tables, one per scale
+  int64_t tab_stride;
+  int64_t f32_bytes;            // offset of the float64 half of a table
+  void* ws;                     // workspace (header + tile states)
+  int grid;                     // persistent grid size
+};
+
+hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s);
+// Resident blocks per CU of the forward kernel for this configuration (0 if unsupported).
+int scan_forward_occupancy(int K, int R, int wide, int kind);
+hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace mk

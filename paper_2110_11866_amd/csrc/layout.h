@@ -1,0 +1,86 @@
+// Internal layouts shared by the host plan code and the gfx950 kernels: the per-scale
+// constant table, the scan rows, the workspace header and the per-tile look-back state.
+#pragma once
+#include <stdint.h>
+#include <stddef.h>
+
+#if defined(__HIP__)
+#define MK_HD __host__ __device__
+#else
+#define MK_HD
+#endif
+
+namespace mk {
+
+constexpr int kWave = 64;        // gfx950 wavefront
+constexpr int kThreads = 256;    // threads per block of the scan kernels
+constexpr int kWaves = kThreads / kWave;
+constexpr int kMaxTerms = 12;
+constexpr int kLookback = 64;    // predecessors inspected per look-back step (one per lane)
+
+// ---------------------------------------------------------------------------------
+// Per-scale constant table. Every constant is a power of the per-term rotation
+//   a_p = e^{-alpha} e^{-i beta p}
+// at a fixed distance, so the same table serves every tile of every row that uses
+// the scale. Complex entry e, term i is stored as re at [(2e) K + i], im at
+// [(2e+1) K + i]; the K values of one entry are contiguous (one scalar load).
+// The table exists twice: float32 entries, then float64 entries.
+// ---------------------------------------------------------------------------------
+struct TabLayout {
+  int K, R;
+  // complex entries
+  MK_HD int eA() const { return 0; }                    // a_p
+  MK_HD int eP1(int r) const { return 1 + r; }          // a_p^{R-1-r}, r in [0, R): chunk sum weights
+  MK_HD int eTR(int d) const { return 1 + R + d; }      // a_p^{R 2^d}, d in [0, 6): wave scan
+  MK_HD int eLANE(int l) const { return 7 + R + l; }    // a_p^{R l}, l in [0, 64): per-lane carry phase
+  MK_HD int eWV(int w) const { return 71 + R + w; }     // a_p^{64 R w}, w in [0, kWaves]: per-wave carry; w = kWaves gives a^T
+  MK_HD int eLB(int k) const { return 72 + R + kWaves + k; }  // a_p^{T k}, k in [0, 64]: look-back weights
+  MK_HD int nComplex() const { return 72 + R + kWaves + 65; }
+  // real entries, after the complex ones (index in units of K values)
+  MK_HD int rMW() const { return 2 * nComplex(); }      // (-1)^p m_p e^{alpha L}
+  MK_HD int rLW() const { return 2 * nComplex() + 1; }  // (-1)^p l_p e^{alpha L}
+  MK_HD int nKRows() const { return 2 * nComplex() + 2; }
+  // scalars, after the K-rows
+  MK_HD int sCX() const { return nKRows() * K + 0; }    // sum_p (-1)^p m_p e^{-alpha L}
+  MK_HD int sD() const { return nKRows() * K + 1; }     // e^{-2 alpha L}: trailing-edge weight
+  MK_HD int sGre() const { return nKRows() * K + 2; }   // output factor e^{i xi n0} e^{-n0^2/(2 sigma^2)}
+  MK_HD int sGim() const { return nKRows() * K + 3; }
+  MK_HD int nValues() const { return nKRows() * K + 4; }
+  MK_HD size_t f32Bytes() const { return ((size_t)nValues() * 4 + 255) / 256 * 256; }
+  MK_HD size_t f64Bytes() const { return ((size_t)nValues() * 8 + 255) / 256 * 256; }
+  MK_HD size_t bytes() const { return f32Bytes() + f64Bytes(); }
+};
+
+// One scan row: one signal filtered at one scale. Scan positions j = 0 .. jend-1;
+// position j produces output n = j - jout0 when 0 <= n < N.
+struct Row {
+  int64_t x_off;     // element offset of the signal in the input array
+  int64_t w_off;     // element offset of the output row (complex or real elements)
+  int64_t N;         // signal length
+  int64_t L;         // window half width
+  int64_t jout0;     // L - n0
+  int64_t jend;      // N + L - n0
+  int64_t tile0;     // index of the row's first tile in the launch
+  int32_t scale;     // table index
+  int32_t ntiles;
+};
+
+// Workspace: a header followed by the tile states.
+struct WsHeader {
+  uint32_t ticket;   // next tile to claim
+  uint32_t done;     // blocks finished in the current launch
+  uint64_t epoch;    // launches completed on this workspace; tags the tile flags
+  uint64_t pad[6];
+};
+static_assert(sizeof(WsHeader) == 64, "header size");
+
+// Tile state: flag word, then K complex float64 aggregates, then K complex inclusive
+// prefixes. flag = (epoch + 1) << 2 | status.
+enum : uint64_t { kEmpty = 0, kAggregate = 1, kInclusive = 2 };
+MK_HD inline size_t tile_state_bytes(int K) { return ((size_t)(8 + 32 * K) + 63) / 64 * 64; }
+
+inline size_t workspace_bytes(int K, int64_t ntiles) {
+  return sizeof(WsHeader) + tile_state_bytes(K) * (size_t)(ntiles > 0 ? ntiles : 0);
+}
+
+}  // namespace mk

@@ -1,0 +1,56 @@
+// Host-side plan object and the host math behind it (fits, order search, tables).
+#pragma once
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "layout.h"
+
+struct morlet_plan_s {
+  int kind = 0;           // 0 Morlet, 1 Gaussian
+  int64_t N = 0;
+  double sigma = 0, xi = 0;
+  int K = 0;
+  int64_t L = 0;
+  int P_S = 0;
+  int mode = 0;           // 0 SFT, 1 ASFT
+  int64_t n0 = 0;         // ASFT shift (0 for SFT)
+  int64_t n0_asft = 0;    // shift used when ASFT is selected
+  int accum = 0;          // 0 float32, 1 compensated (float64)
+  std::vector<double> cc, sc;   // cos / sin coefficients (m, l) or (a, 0)
+  std::vector<double> jac;      // [4K]: dcc/dsigma, dcc/dxi, dsc/dsigma, dsc/dxi
+  double relrmse = 0;
+  int R = 16;             // samples per thread
+  int device = 0;
+  int num_cus = 256;
+  void* d_tab = nullptr;  // device copy of the constant table
+  size_t tab_bytes = 0;
+  std::vector<unsigned char> h_tab;
+};
+
+namespace mk {
+
+struct Fit {
+  std::vector<double> cc, sc;
+  double relrmse;
+};
+
+// Kernel samples on k = -L..L (index k + L).
+void morlet_taps(double sigma, double xi, int64_t L, std::vector<double>& re, std::vector<double>& im);
+void gauss_taps(double sigma, int64_t L, std::vector<double>& g);
+
+// MMSE fit of the given real targets on orders P_S..P_S+K-1 (cos part to `even`,
+// sin part to `odd`); relrmse against the combined complex target.
+Fit fit_orders(const std::vector<double>& tre, const std::vector<double>& tim, int64_t L, int P_S, int K);
+
+int select_ps(double sigma, double xi, int K, int64_t L, double* best_err);
+int64_t select_L(double sigma, double xi, int K, bool gauss);
+
+void jacobian(morlet_plan_s* p);
+// Fill p->h_tab for the plan's current mode and R; returns false on bad parameters.
+bool build_table(morlet_plan_s* p, std::string* err);
+// Fill one table for arbitrary parameters (used by the scalogram plans as well).
+void fill_table(unsigned char* dst, int kind, int K, int R, int64_t L, int P_S, double sigma, double xi,
+                int mode, int64_t n0, const std::vector<double>& cc, const std::vector<double>& sc);
+
+}  // namespace mk

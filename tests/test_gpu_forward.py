@@ -1,0 +1,158 @@
+"""Forward parity of the HIP path (through the C ABI) against the FP64 oracle on the same
+seeded inputs. Floating-point bar: relative L2 error <= 1e-5 (float32 scan); the
+compensated (float64 scan) mode is held to 1e-6."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import morlet_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "compensated": 1e-6}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_11866_amd  # noqa: F401  (loads libmorlet.so; raises if it is missing)
+    yield
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def _announce(*args):
+    print("[case]", *args, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(x32, kind, sigma, K, L, mode="sft", n0=0, accum="f32", dtype=torch.float32, xi=None, repeats=1):
+    import paper_2110_11866_amd as M
+    N = len(x32)
+    xt = torch.from_numpy(np.ascontiguousarray(x32)).to("cuda").to(dtype)
+    if kind == "morlet":
+        plan = M.MorletPlan(N, sigma, xi if xi is not None else 6.0 / sigma, K, L, mode=mode, n0=n0, accum=accum)
+    else:
+        plan = M.GaussPlan(N, sigma, K, L, mode=mode, n0=n0, accum=accum)
+    outs = []
+    for _ in range(repeats):
+        outs.append(plan.forward(xt).cpu().numpy())
+    torch.cuda.synchronize()
+    info = plan.info()
+    x_used = xt.double().cpu().numpy()        # the values the kernel actually read
+    return outs, info, x_used
+
+
+def oracle_of(x, kind, sigma, K, L, info, mode, xi=None):
+    if kind == "morlet":
+        xi = xi if xi is not None else 6.0 / sigma
+        p = O.plan_morlet(sigma, xi, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None)
+        assert p.P_S == info["P_S"]
+    else:
+        p = O.plan_gauss(sigma, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None)
+    return O.forward(x, p), p
+
+
+MODES = [("sft", "f32"), ("asft", "f32"), ("sft", "compensated"), ("asft", "compensated")]
+
+
+@pytest.mark.parametrize("mode,accum", MODES)
+@pytest.mark.parametrize("kind", ["morlet", "gauss"])
+def test_small_config_parity(kind, mode, accum):
+    # N = 1024, sigma = 16, K = 4, L = 64 (one tile), i.i.d. N(0, 1)
+    _announce("small", kind, mode, accum)
+    x = workloads.small_signal().astype(np.float32)
+    (got,), info, xu = run_gpu(x, kind, 16.0, 4, 64, mode=mode, accum=accum)
+    want, _ = oracle_of(xu, kind, 16.0, 4, 64, info, mode)
+    assert got.shape == want.shape
+    assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
+
+
+@pytest.mark.parametrize("mode,accum", MODES)
+@pytest.mark.parametrize("N,sigma,K,L", [(50000, 300.0, 6, 1200), (4096 * 3, 40.0, 5, 160), (77777, 2000.0, 3, 8000),
+                                         (9000, 1.5, 12, 12)])
+def test_multi_tile_parity(N, sigma, K, L, mode, accum):
+    _announce("multi", N, sigma, K, L, mode, accum)
+    x = np.random.default_rng(N + K).standard_normal(N).astype(np.float32)
+    (got,), info, xu = run_gpu(x, "morlet", sigma, K, L, mode=mode, accum=accum)
+    want, _ = oracle_of(xu, "morlet", sigma, K, L, info, mode)
+    assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
+
+
+@pytest.mark.parametrize("N", [1, 2, 7, 63, 64, 65, 129, 4095, 4096, 4097, 8191])
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_edge_lengths(N, mode):
+    # signals shorter than the window, exactly one tile, one past a tile, ragged tails
+    _announce("edge", N, mode)
+    sigma, K, L = 16.0, 4, 64
+    x = np.random.default_rng(N).standard_normal(N).astype(np.float32)
+    for kind in ("morlet", "gauss"):
+        (got,), info, xu = run_gpu(x, kind, sigma, K, L, mode=mode)
+        want, _ = oracle_of(xu, kind, sigma, K, L, info, mode)
+        assert got.shape == (N,)
+        assert rel_l2(got, want) <= 1e-5, (kind, rel_l2(got, want))
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_half_inputs(dtype, mode):
+    _announce("half", dtype, mode)
+    N, sigma, K, L = 30000, 200.0, 6, 800
+    x = (np.cumsum(np.random.default_rng(9).standard_normal(N)) / 30).astype(np.float32)
+    (got,), info, xu = run_gpu(x, "morlet", sigma, K, L, mode=mode, dtype=dtype)
+    want, _ = oracle_of(xu, "morlet", sigma, K, L, info, mode)   # oracle sees the stored half values
+    assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
+
+
+@pytest.mark.parametrize("mode,accum", MODES)
+def test_paper_scale_parity(mode, accum):
+    # N = 102400, sigma = 8192, xi = 6/sigma, K = 6, L = 32768; three sinusoids plus noise
+    _announce("paper-scale", mode, accum)
+    x = workloads.paper_scale_signal()
+    (got,), info, xu = run_gpu(x, "morlet", 8192.0, 6, 32768, mode=mode, accum=accum)
+    want, p = oracle_of(xu, "morlet", 8192.0, 6, 32768, info, mode)
+    assert info["P_S"] == 5
+    assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
+
+
+def test_long_row_lookback_and_repeat_determinism():
+    # 2^20 samples: 256+ tiles in one row, look-back windows longer than 64 predecessors;
+    # three calls on one workspace must give identical bits (workspace re-armed by the kernel)
+    _announce("long-row")
+    N, sigma, K, L = 1 << 20, 512.0, 5, 2048
+    x = np.random.default_rng(21).standard_normal(N).astype(np.float32)
+    outs, info, xu = run_gpu(x, "morlet", sigma, K, L, repeats=3)
+    want, _ = oracle_of(xu, "morlet", sigma, K, L, info, "sft")
+    assert rel_l2(outs[0], want) <= 1e-5, rel_l2(outs[0], want)
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+    assert np.array_equal(outs[0].view(np.uint32), outs[2].view(np.uint32))
+
+
+def test_impulse_response_on_gpu():
+    _announce("impulse")
+    N, sigma, K, L, c = 3000, 50.0, 6, 200, 1400
+    x = np.zeros(N, np.float32)
+    x[c] = 1.0
+    (got,), info, xu = run_gpu(x, "morlet", sigma, K, L)
+    p = O.plan_morlet(sigma, 6 / sigma, K, L)
+    want = np.zeros(N, np.complex128)
+    want[c - L:c + L + 1] = O.kterm_morlet(p)
+    assert rel_l2(got, want) <= 1e-5
+
+
+def test_kterm_bound_against_direct_convolution():
+    # the K-term result is as far from the direct transform as the oracle says, no further
+    _announce("direct-bound")
+    N, sigma, K, L = 20000, 100.0, 6, 400
+    x = np.random.default_rng(4).standard_normal(N).astype(np.float32)
+    (got,), info, xu = run_gpu(x, "morlet", sigma, K, L)
+    direct = O.forward_direct(xu, sigma, 6 / sigma, L)
+    want, _ = oracle_of(xu, "morlet", sigma, K, L, info, "sft")
+    assert np.linalg.norm(got - direct) <= np.linalg.norm(want - direct) + 1e-5 * np.linalg.norm(want)
