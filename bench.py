@@ -1,17 +1,23 @@
 """Benchmark of the SFT/ASFT kernel-integral Morlet transform on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scalogram|paper_scale]
 
-Prints one JSON line. A step is one pass of the transform over the workload's batch,
-with inputs resident in HBM. The dominant kernel is timed with HIP events on the
-stream it is launched on, and its algorithmic bytes per launch give the roofline figure.
+Prints one JSON line. A step is one pass of the transform over the workload's whole
+batch, with the inputs resident in HBM. The dominant kernel is timed with HIP events on
+the stream it is launched on; its algorithmic bytes per launch give the roofline figure.
 The FP64 oracle is timed on the host cores on a bounded sample for the CPU baseline.
+
+Workloads (seeded, synthetic):
+  scalogram   : 256 pink-noise float32 signals, lengths log-uniform in [4096, 262144],
+                32 scales sigma = 4..4096 (geometric), xi = 6/sigma, K = 5, error-optimal
+                windows, ASFT; complex64 output [signal][scale][n]        (default)
+  paper_scale : one float32 signal, N = 102400 (three sinusoids + noise), sigma = 8192,
+                xi = 6/sigma, K = 6, L = 32768, ASFT
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,31 +33,137 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="paper_scale", choices=["paper_scale"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="scalogram", choices=["scalogram", "paper_scale"])
     ap.add_argument("--mode", default="asft", choices=["sft", "asft"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tile", type=int, default=16, choices=[8, 16], help="samples per thread")
     return ap.parse_args()
 
 
-def cpu_baseline_paper_scale(x, info, mode):
-    """FP64 oracle (numpy kernel-integral recurrences) on the same signal, one transform."""
+def _timed(torch, fn, steps, warmup):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        fn()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = [a.elapsed_time(b) for a, b in ev]
+    return wall * 1e3 / steps, float(np.mean(kern))
+
+
+def _cpu_oracle_rows(x, offs, lengths, rows, plan_of, budget_s=12.0):
+    """Time the FP64 oracle over (signal, scale) rows until the budget is spent."""
     from oracle import morlet_oracle as O
-    p = O.plan_morlet(8192.0, 6.0 / 8192.0, 6, 32768, mode=mode, n0=info["n0"] if mode == "asft" else None,
-                      P_S=info["P_S"])
-    xd = x.astype(np.float64)
-    O.forward(xd, p)                     # warm-up
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        O.forward(xd, p)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 50:
+    done_samples, t0, used = 0, time.perf_counter(), 0
+    for (b, s) in rows:
+        p = plan_of(s)
+        O.forward(x[offs[b]:offs[b] + lengths[b]].astype(np.float64), p)
+        done_samples += int(lengths[b])
+        used += 1
+        if time.perf_counter() - t0 > budget_s:
             break
-    per = el / reps
-    return {"value": len(x) / per / 1e9, "unit": "Gsamples*scales/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} full transforms of the N=102400 signal (6 terms, numpy float64, one thread)"}
+    el = time.perf_counter() - t0
+    return done_samples / el / 1e9, used, done_samples
+
+
+def bench_scalogram(args, torch, M):
+    import workloads
+    from oracle import morlet_oracle as O
+    x, lengths, sigmas, xis = workloads.ragged_scalogram()
+    dev = torch.device("cuda:0")
+    plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=args.mode)
+    plan.set_tile(args.tile)
+    xt = torch.from_numpy(x).to(dev)
+    S, Ntot = len(sigmas), int(lengths.sum())
+    out = torch.empty(S * Ntot, dtype=torch.complex64, device=dev)
+    ws = plan.workspace(dev)
+    ms_step, kern_ms = _timed(torch, lambda: plan.forward(xt, out=out, ws=ws), args.steps, args.warmup)
+    ss = Ntot * S
+    algo_bytes = ss * 8 + Ntot * 4
+    achieved = algo_bytes / (kern_ms * 1e-3) / 1e9
+    line = {
+        "metric": "Gsamples*scales/s (ASFT-scan Morlet scalogram) and % HBM peak",
+        "value": ss / (ms_step * 1e-3) / 1e9,
+        "unit": "Gsamples*scales/s",
+        "ms_per_step": ms_step,
+        "dtype": "f32",
+        "config": {"workload": "ragged scalogram: 256 pink-noise float32 signals, lengths log-uniform in "
+                               "[4096, 262144] (sum %d), 32 scales sigma=4..4096 geometric, xi=6/sigma, K=5, "
+                               "error-optimal windows, %s, complex64 out [signal][scale][n]" % (Ntot, args.mode),
+                   "signals": len(lengths), "scales": S, "samples_x_scales": ss, "tile_R": args.tile},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "kernel_ms": kern_ms,
+        "algorithmic_bytes_per_launch": algo_bytes,
+    }
+    if not args.no_cpu:
+        offs = np.concatenate([[0], np.cumsum(lengths)])
+        cache = {}
+
+        def plan_of(s):
+            if s not in cache:
+                info = plan.scale_info(s)
+                cache[s] = O.plan_morlet(sigmas[s], xis[s], 5, info["L"], mode=args.mode,
+                                         n0=info["n0"] if args.mode == "asft" else None, P_S=info["P_S"])
+            return cache[s]
+        rng = np.random.default_rng(7)
+        rows = [(int(rng.integers(0, len(lengths))), int(rng.integers(0, S))) for _ in range(400)]
+        rate, used, nsamp = _cpu_oracle_rows(x, offs, lengths, rows, plan_of)
+        line["cpu_baseline"] = {"value": rate, "unit": "Gsamples*scales/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{used} random (signal, scale) rows of the same workload "
+                                          f"({nsamp} samples x scales), numpy float64 kernel-integral "
+                                          "recurrences, one thread"}
+    return line
+
+
+def bench_paper_scale(args, torch, M):
+    import workloads
+    from oracle import morlet_oracle as O
+    dev = torch.device("cuda:0")
+    N, sigma, K, L = 102400, 8192.0, 6, 32768
+    x = workloads.paper_scale_signal(N)
+    xt = torch.from_numpy(x).to(dev)
+    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=args.mode)
+    plan.set_tile(args.tile)
+    info = plan.info()
+    out = torch.empty(N, dtype=torch.complex64, device=dev)
+    ws = plan.workspace(dev)
+    ms_step, kern_ms = _timed(torch, lambda: plan.forward(xt, out=out, ws=ws), args.steps, args.warmup)
+    algo_bytes = N * 4 + N * 8
+    achieved = algo_bytes / (kern_ms * 1e-3) / 1e9
+    line = {
+        "metric": "Gsamples*scales/s (ASFT-scan Morlet transform)",
+        "value": N / (ms_step * 1e-3) / 1e9,
+        "unit": "Gsamples*scales/s",
+        "ms_per_step": ms_step,
+        "dtype": "f32",
+        "config": {"workload": "paper_scale: N=102400, sigma=8192, xi=6/sigma, K=6, L=32768, "
+                               f"{args.mode}, float32 in, complex64 out", "P_S": info["P_S"], "n0": info["n0"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "kernel_ms": kern_ms,
+    }
+    if not args.no_cpu:
+        p = O.plan_morlet(sigma, 6.0 / sigma, K, L, mode=args.mode,
+                          n0=info["n0"] if args.mode == "asft" else None, P_S=info["P_S"])
+        xd = x.astype(np.float64)
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 10.0 and reps < 50:
+            O.forward(xd, p)
+            reps += 1
+        per = (time.perf_counter() - t0) / reps
+        line["cpu_baseline"] = {"value": N / per / 1e9, "unit": "Gsamples*scales/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{reps} full transforms of the same signal, numpy float64, one thread"}
+    return line
 
 
 def main():
@@ -62,57 +174,14 @@ def main():
     import torch
 
     import paper_2110_11866_amd as M
-    import workloads
-
-    dev = torch.device("cuda:0")
-    N, sigma, K, L = 102400, 8192.0, 6, 32768
-    x = workloads.paper_scale_signal(N)
-    xt = torch.from_numpy(x).to(dev)
-    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=args.mode)
-    info = plan.info()
-    out = torch.empty(N, dtype=torch.complex64, device=dev)
-    ws = plan.workspace(dev)
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        plan.forward(xt, out=out, ws=ws)
-    torch.cuda.synchronize()
-
-    # timed region: K steps, bracketed by synchronisation
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        plan.forward(xt, out=out, ws=ws)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
-    kern_ms_avg = float(np.mean(kern_ms))
-    ms_per_step = wall * 1e3 / args.steps
-
-    samples_scales = N * 1
-    bytes_per_launch = N * 4 + N * 8        # float32 in, complex64 out
-    achieved = bytes_per_launch / (kern_ms_avg * 1e-3) / 1e9
-    line = {
-        "metric": "Gsamples*scales/s (ASFT-scan Morlet transform)",
-        "value": samples_scales / (ms_per_step * 1e-3) / 1e9,
-        "unit": "Gsamples*scales/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "paper_scale: N=102400, sigma=8192, xi=6/sigma, K=6, L=32768, "
-                               f"{args.mode}, float32 in, complex64 out",
-                   "P_S": info["P_S"], "n0": info["n0"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "kernel_us": kern_ms_avg * 1e3,
-    }
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline_paper_scale(x, info, args.mode)
-    print(json.dumps(line))
+    fn = bench_scalogram if args.workload == "scalogram" else bench_paper_scale
+    line = fn(args, torch, M)
+    full = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"),
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": line.pop("dtype"),
+            "data": "synthetic"}
+    full.update(line)
+    print(json.dumps(full), flush=True)
 
 
 if __name__ == "__main__":

@@ -99,6 +99,12 @@ morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,
                               morlet_accum accum);
 
+/* Tile shape of the scan kernels: R consecutive samples per thread (8 or 16; 256 threads
+ * per block, so a tile covers 256 R scan positions). Default 16. Changes the workspace
+ * size; rebuilds the device tables synchronously. Results do not depend on R beyond
+ * float32 rounding. */
+morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R);
+
 /* Plan parameters (host outputs; any pointer may be NULL).
  *   cos_coef[K]: m_p (Morlet) or a_p (Gaussian); sin_coef[K]: l_p (0 for Gaussian);
  *   jac[4*K]: d(cos_coef)/dsigma, d(cos_coef)/dxi, d(sin_coef)/dsigma, d(sin_coef)/dxi
@@ -123,6 +129,67 @@ morlet_status morlet_forward(morlet_plan_t plan, const void* x, morlet_dtype dty
 /* Gaussian smoothing: y[n] float32 (device). Needs a Gaussian plan. */
 morlet_status gauss_smooth(morlet_plan_t plan, const void* x, morlet_dtype dtype, float* y,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Batched ragged scalogram: B signals of lengths lengths[b] (host int64[B], >= 0),
+ * packed back to back in one input array, each transformed at S scales (host
+ * sigmas[S], xis[S] in rad/sample) with the Morlet direct method (Sec. III-A), K terms.
+ * Every scale gets its own window, lowest order and fit:
+ *   L_over_sigma = 0 : error-optimal window per scale (the rule of morlet_plan with L = 0)
+ *   L_over_sigma > 0 : L_s = ceil(L_over_sigma * sigma_s) (at least K)
+ * Output layout (complex64, device): W_packed[S * off_b + s * len_b + n] is scale s of
+ * signal b at sample n, off_b = sum_{i<b} len_i (signal-major, then scale, then sample).
+ * One persistent launch processes every (signal, scale, tile) work item.
+ * morlet_plan_set applies to every scale; its n0 (if > 0) is clamped to each L_s, and
+ * n0 = 0 selects max(1, round(sigma_s/8)) per scale. Destroy with morlet_destroy.
+ * ------------------------------------------------------------------------------------ */
+morlet_status morlet_scalogram_plan(morlet_plan_t* out, int32_t B, const int64_t* lengths, int32_t S,
+                                    const double* sigmas, const double* xis, int32_t K, double L_over_sigma);
+
+/* Parameters of scale s of a scalogram plan (outputs as in morlet_plan_info). */
+morlet_status morlet_scalogram_scale_info(morlet_plan_t plan, int32_t s, int64_t* L, int32_t* P_S, int64_t* n0,
+                                          double* alpha, double* cos_coef, double* sin_coef, double* jac,
+                                          double* kernel_relrmse);
+
+/* Scalogram forward: x_packed (device, sum(lengths) elements of dtype) -> W_packed
+ * (device complex64, S * sum(lengths) elements). Workspace rules as above. */
+morlet_status morlet_scalogram_forward(morlet_plan_t plan, const void* x_packed, morlet_dtype dtype,
+                                       void* W_packed, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Differentiation (no counterpart in the paper). For a real loss of W and its cotangent
+ *   gW = dLoss/dRe W + i dLoss/dIm W            (complex64 [N], PyTorch's convention)
+ * the backward call writes
+ *   gx[j] = dLoss/dx[j] = Re sum_k conj(h[k]) gW[j + n0 + k]    (float32 [N], overwritten)
+ * where h are the taps of the transform (psi_hat for SFT, e^{i xi n0} e^{-n0^2/(2 sigma^2)}
+ * e^{-alpha k} psi_hat[k] for ASFT), computed as the same scan run on the time-reversed
+ * cotangent with the conjugate kernel; and, if gparams is not NULL (device float64),
+ *   gparams[0] = dLoss/dsigma, gparams[1] = dLoss/dxi
+ * with the window L, the order P_S and the shift n0 held fixed. The sigma and xi dependence
+ * goes through the fitted coefficients (the plan's Jacobian), and for ASFT also through
+ * alpha = n0/sigma^2 (a scan of the alpha-derivative states), the output scale and the
+ * carrier phase. x is the forward input (needed only when gparams is not NULL). The
+ * gradient pass scans and accumulates in float64 (the chain rule through the fitted
+ * coefficients cancels its per-term sums by orders of magnitude); the sums are taken in a
+ * fixed order, so repeated calls give identical bits.
+ * Workspace: morlet_backward_workspace_size bytes (zero-filled once, as above).
+ * ------------------------------------------------------------------------------------ */
+morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes);
+
+morlet_status morlet_backward(morlet_plan_t plan, const void* x, morlet_dtype dtype, const void* gW, float* gx,
+                              double* gparams, void* ws, size_t ws_bytes, void* stream);
+
+/* Gaussian smoothing backward: gy float32 [N] is dLoss/dy; gparams[0] = dLoss/dsigma,
+ * gparams[1] = 0. */
+morlet_status gauss_smooth_backward(morlet_plan_t plan, const void* x, morlet_dtype dtype, const float* gy,
+                                    float* gx, double* gparams, void* ws, size_t ws_bytes, void* stream);
+
+/* Scalogram backward: gW_packed as W_packed; gx_packed float32 [sum lengths] gets the sum
+ * over scales of each scale's adjoint (summed in scale order); gparams (device float64
+ * [S][2], nullable) gets dLoss/dsigma_s and dLoss/dxi_s summed over the signals. */
+morlet_status morlet_scalogram_backward(morlet_plan_t plan, const void* x_packed, morlet_dtype dtype,
+                                        const void* gW_packed, float* gx_packed, double* gparams, void* ws,
+                                        size_t ws_bytes, void* stream);
 
 /* Destroy a plan (NULL is ignored). Not stream-ordered: no call using it may be pending. */
 void morlet_destroy(morlet_plan_t plan);

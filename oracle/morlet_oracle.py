@@ -38,7 +38,7 @@ import math
 from dataclasses import dataclass, field
 
 import numpy as np
-from scipy.signal import lfilter
+from scipy.signal import fftconvolve, lfilter
 
 __all__ = [
     "gaussian", "morlet", "Plan", "plan_morlet", "plan_gauss", "fit_morlet", "fit_gauss",
@@ -255,13 +255,24 @@ def asft_kernel(plan: Plan) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Plain convolution, x zero outside [0, N-1] (eqs. xG..xGDD)
 # --------------------------------------------------------------------------
+FFT_CONV_MIN = 1 << 24   # N * (2L + 1) above which the full convolution is taken by FFT
+
+
 def conv_same(x: np.ndarray, h: np.ndarray, L: int, shift: int = 0) -> np.ndarray:
-    """y[n] = sum_{k=-L}^{L} h[k] x[n - shift - k], n = 0..N-1."""
-    x = np.asarray(x, dtype=np.float64)
+    """y[n] = sum_{k=-L}^{L} h[k] x[n - shift - k], n = 0..N-1 (x real or complex).
+
+    The full linear convolution is a library primitive: np.convolve (direct sums) for small
+    sizes, scipy's FFT convolution for large ones (same sums, rounding ~1e-15 of the
+    largest term)."""
+    x = np.asarray(x)
+    x = x.astype(np.complex128 if np.iscomplexobj(x) else np.float64)
     N = x.shape[0]
     if N == 0:
-        return np.zeros(0, dtype=np.result_type(h, np.float64))
-    full = np.convolve(x, h)            # full[i] = sum_k h[k+L] x[i - (k+L)]
+        return np.zeros(0, dtype=np.result_type(h, x, np.float64))
+    if N * len(h) >= FFT_CONV_MIN:
+        full = fftconvolve(x, h)
+    else:
+        full = np.convolve(x, h)        # full[i] = sum_k h[k+L] x[i - (k+L)]
     idx = np.arange(N) - shift + L      # index of n - shift in 'full'
     out = np.zeros(N, dtype=full.dtype)
     ok = (idx >= 0) & (idx < full.shape[0])
@@ -395,16 +406,9 @@ def adjoint(g: np.ndarray, plan: Plan) -> np.ndarray:
     Written as a plain sum over the taps."""
     h, s = _taps_and_shift(plan)
     g = np.asarray(g, dtype=np.complex128)
-    N = g.shape[0]
-    out = np.zeros(N)
-    L = plan.L
-    for idx, k in enumerate(range(-L, L + 1)):
-        # contribution conj(h[k]) g[j + s + k] for every j with 0 <= j + s + k < N
-        lo = max(0, -(s + k))
-        hi = min(N, N - (s + k))
-        if hi > lo:
-            out[lo:hi] += (np.conj(h[idx]) * g[lo + s + k: hi + s + k]).real
-    return out
+    # sum_k conj(h[k]) g[j + s + k] = sum_k' conj(h[-k']) g[(j + s) - k']: a convolution with
+    # the reversed conjugate taps, read s samples later
+    return conv_same(g, np.conj(np.asarray(h)[::-1]), plan.L, shift=-s).real
 
 
 def _jacobian(plan: Plan) -> np.ndarray:

@@ -13,7 +13,8 @@ from . import _abi
 from ._abi import (MORLET_ACC_COMPENSATED, MORLET_ACC_F32, MORLET_BF16, MORLET_F16, MORLET_F32,
                    MORLET_SCAN_ASFT, MORLET_SCAN_SFT, MorletError)
 
-__all__ = ["MorletPlan", "GaussPlan", "MorletError", "torch_dtype_code"]
+__all__ = ["MorletPlan", "GaussPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
+           "MorletTransform"]
 
 _DT = {torch.float32: MORLET_F32, torch.float16: MORLET_F16, torch.bfloat16: MORLET_BF16}
 _MODE = {"sft": MORLET_SCAN_SFT, "asft": MORLET_SCAN_ASFT}
@@ -43,15 +44,25 @@ class _PlanBase:
         _abi.morlet_plan_set(self.handle, _MODE[mode], int(n0), _ACC[accum])
         return self
 
+    def set_tile(self, R: int) -> "_PlanBase":
+        """Samples per thread of the scan kernels (8 or 16)."""
+        _abi.morlet_plan_set_tile(self.handle, int(R))
+        self._ws = None
+        return self
+
     def info(self) -> dict:
         return _abi.morlet_plan_info(self.handle, self.K)
 
     def workspace_bytes(self) -> int:
         return _abi.morlet_workspace_size(self.handle)
 
-    def workspace(self, device) -> torch.Tensor:
-        """A zero-filled workspace owned by the plan (allocated on first use)."""
-        need = self.workspace_bytes()
+    def backward_workspace_bytes(self) -> int:
+        return _abi.morlet_backward_workspace_size(self.handle)
+
+    def workspace(self, device, backward: bool = False) -> torch.Tensor:
+        """A zero-filled workspace owned by the plan (allocated on first use); the backward
+        size also serves the forward."""
+        need = self.backward_workspace_bytes() if backward else self.workspace_bytes()
         if self._ws is None or self._ws.numel() < need or self._ws.device != torch.device(device):
             self._ws = torch.zeros(max(need, 64), dtype=torch.uint8, device=device)
         return self._ws
@@ -70,6 +81,19 @@ class _PlanBase:
             except Exception:
                 pass
             self.handle = None
+
+
+def _bwd_common(plan, fn, x, g, want_params, nparams):
+    if not g.is_cuda or not g.is_contiguous():
+        raise ValueError("the cotangent must be a contiguous device tensor")
+    w = plan.workspace(g.device, backward=True)
+    gx = torch.empty(plan.N, dtype=torch.float32, device=g.device)
+    gp = torch.empty(nparams, dtype=torch.float64, device=g.device) if want_params else None
+    xp = x.data_ptr() if x is not None else None
+    dt = torch_dtype_code(x.dtype) if x is not None else 0
+    fn(plan.handle, xp, dt, g.data_ptr(), gx.data_ptr(), gp.data_ptr() if gp is not None else None,
+       w.data_ptr(), w.numel(), _stream())
+    return gx, gp
 
 
 class MorletPlan(_PlanBase):
@@ -96,6 +120,15 @@ class MorletPlan(_PlanBase):
                             w.numel(), _stream())
         return out
 
+    def backward(self, x: torch.Tensor | None, gW: torch.Tensor, want_params: bool = True):
+        """(dLoss/dx float32 [N], [dLoss/dsigma, dLoss/dxi] float64 or None) for the cotangent
+        gW = dLoss/dRe W + i dLoss/dIm W (complex64 [N])."""
+        if gW.dtype != torch.complex64 or gW.numel() != self.N:
+            raise ValueError("gW must be complex64 of N elements")
+        if want_params:
+            self._check_x(x)
+        return _bwd_common(self, _abi.morlet_backward, x if want_params else None, gW, want_params, 2)
+
 
 class GaussPlan(_PlanBase):
     """Gaussian smoothing (eqs. aproGauss, GsSFT, GsASFT): orders 0..K-1 on [-L, L]."""
@@ -119,3 +152,117 @@ class GaussPlan(_PlanBase):
         _abi.gauss_smooth(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(), w.data_ptr(),
                           w.numel(), _stream())
         return out
+
+    def backward(self, x: torch.Tensor | None, gy: torch.Tensor, want_params: bool = True):
+        if gy.dtype != torch.float32 or gy.numel() != self.N:
+            raise ValueError("gy must be float32 of N elements")
+        if want_params:
+            self._check_x(x)
+        return _bwd_common(self, _abi.gauss_smooth_backward, x if want_params else None, gy, want_params, 2)
+
+
+class ScalogramPlan(_PlanBase):
+    """Batched ragged scalogram: B packed signals x S scales, one persistent launch.
+    Output [signal][scale][n] packed: scale s of signal b starts at S*off_b + s*len_b."""
+
+    kind = "scalogram"
+
+    def __init__(self, lengths, sigmas, xis, K: int, L_over_sigma: float = 0.0, mode: str = "sft",
+                 n0: int = 0, accum: str = "f32"):
+        lengths = [int(v) for v in lengths]
+        h = _abi.morlet_scalogram_plan(lengths, list(sigmas), list(xis), int(K), float(L_over_sigma))
+        super().__init__(h, int(sum(lengths)), int(K))
+        self.lengths = lengths
+        self.S = len(sigmas)
+        self.sigmas, self.xis = [float(v) for v in sigmas], [float(v) for v in xis]
+        if mode != "sft" or n0 or accum != "f32":
+            self.set(mode, n0, accum)
+
+    def info(self) -> dict:
+        raise TypeError("use scale_info(s) for a scalogram plan")
+
+    def scale_info(self, s: int) -> dict:
+        return _abi.morlet_scalogram_scale_info(self.handle, int(s), self.K)
+
+    def out_offset(self, b: int, s: int) -> int:
+        return self.S * sum(self.lengths[:b]) + s * self.lengths[b]
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_x(x)
+        total = self.S * self.N
+        if out is None:
+            out = torch.empty(total, dtype=torch.complex64, device=x.device)
+        if out.dtype != torch.complex64 or out.numel() != total or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex64 tensor of S * sum(lengths) elements")
+        w = self.workspace(x.device) if ws is None else ws
+        _abi.morlet_scalogram_forward(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(),
+                                      w.data_ptr(), w.numel(), _stream())
+        return out
+
+    def backward(self, x: torch.Tensor | None, gW: torch.Tensor, want_params: bool = True):
+        """(dLoss/dx float32 [sum lengths], dLoss/d(sigma_s, xi_s) float64 [S, 2] or None)."""
+        if gW.dtype != torch.complex64 or gW.numel() != self.S * self.N:
+            raise ValueError("gW must be complex64 of S * sum(lengths) elements")
+        if want_params:
+            self._check_x(x)
+        gx, gp = _bwd_common(self, _abi.morlet_scalogram_backward, x if want_params else None, gW, want_params,
+                             2 * self.S)
+        return gx, (gp.view(self.S, 2) if gp is not None else None)
+
+
+class _MorletFn(torch.autograd.Function):
+    """W = psi_hat * x through the library; gradients for x, sigma and xi from its backward
+    kernels (window, lowest order and ASFT shift frozen by the plan)."""
+
+    @staticmethod
+    def forward(ctx, x, sigma, xi, plan):
+        ctx.plan = plan
+        ctx.save_for_backward(x)
+        return plan.forward(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, gW):
+        (x,) = ctx.saved_tensors
+        want_p = bool(ctx.needs_input_grad[1] or ctx.needs_input_grad[2])
+        gx, gp = ctx.plan.backward(x.contiguous(), gW.contiguous().to(torch.complex64), want_params=want_p)
+        gs = gxi = None
+        if want_p:
+            gs = gp[0].to(torch.float32 if ctx.needs_input_grad[1] else torch.float64)
+            gxi = gp[1].to(torch.float32 if ctx.needs_input_grad[2] else torch.float64)
+        return (gx.to(x.dtype) if ctx.needs_input_grad[0] else None), gs, gxi, None
+
+
+def morlet_transform(x: torch.Tensor, sigma: torch.Tensor, xi: torch.Tensor, plan: "MorletPlan") -> torch.Tensor:
+    """Differentiable Morlet transform of a 1-D device signal with a plan built at (sigma, xi)."""
+    return _MorletFn.apply(x, sigma, xi, plan)
+
+
+class MorletTransform(torch.nn.Module):
+    """Morlet transform layer with learnable sigma and xi (rad/sample). The plan (window L,
+    lowest order P_S, ASFT shift n0) is chosen once at construction and kept fixed; the
+    coefficients are refitted whenever sigma or xi change."""
+
+    def __init__(self, N: int, sigma: float, xi: float, K: int, L: int = 0, mode: str = "sft", n0: int = 0,
+                 accum: str = "f32"):
+        super().__init__()
+        self.sigma = torch.nn.Parameter(torch.tensor(float(sigma), dtype=torch.float64))
+        self.xi = torch.nn.Parameter(torch.tensor(float(xi), dtype=torch.float64))
+        base = MorletPlan(N, sigma, xi, K, L, mode=mode, n0=n0, accum=accum)
+        info = base.info()
+        self._cfg = dict(N=N, K=K, L=info["L"], mode=mode, n0=info["n0"], accum=accum, P_S=info["P_S"])
+        self._plan, self._key = base, (float(sigma), float(xi))
+
+    def plan(self) -> MorletPlan:
+        key = (float(self.sigma.detach()), float(self.xi.detach()))
+        if key != self._key:
+            c = self._cfg
+            p = MorletPlan(c["N"], key[0], key[1], c["K"], c["L"])
+            if p.info()["P_S"] != c["P_S"]:
+                raise MorletError(2, "the refitted plan chose another lowest order; rebuild the layer")
+            if c["mode"] != "sft" or c["accum"] != "f32":
+                p.set(c["mode"], c["n0"], c["accum"])
+            self._plan, self._key = p, key
+        return self._plan
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        return _MorletFn.apply(x, self.sigma, self.xi, self.plan())

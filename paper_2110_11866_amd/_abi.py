@@ -28,12 +28,21 @@ SIGNATURES = {
     "morlet_plan": (ctypes.c_int, [_P(_vp), _i64, _dbl, _dbl, _i32, _i64]),
     "morlet_plan_gauss": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
+    "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
     "morlet_plan_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i32), _P(_i64), _P(_dbl), _P(_dbl), _P(_dbl),
                                         _P(_dbl), _P(_dbl)]),
     "morlet_workspace_size": (ctypes.c_int, [_vp, _P(_sz)]),
     "morlet_workspace_init": (ctypes.c_int, [_vp, _sz, _vp]),
     "morlet_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
     "gauss_smooth": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "morlet_scalogram_plan": (ctypes.c_int, [_P(_vp), _i32, _P(_i64), _i32, _P(_dbl), _P(_dbl), _i32, _dbl]),
+    "morlet_scalogram_scale_info": (ctypes.c_int, [_vp, _i32, _P(_i64), _P(_i32), _P(_i64), _P(_dbl), _P(_dbl),
+                                                   _P(_dbl), _P(_dbl), _P(_dbl)]),
+    "morlet_scalogram_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "morlet_backward_workspace_size": (ctypes.c_int, [_vp, _P(_sz)]),
+    "morlet_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "gauss_smooth_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "morlet_scalogram_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "morlet_destroy": (None, [_vp]),
     "morlet_last_error": (ctypes.c_char_p, []),
 }
@@ -84,6 +93,10 @@ def morlet_plan_set(plan: int, mode: int, n0: int, accum: int) -> None:
     check(lib().morlet_plan_set(plan, mode, n0, accum))
 
 
+def morlet_plan_set_tile(plan: int, R: int) -> None:
+    check(lib().morlet_plan_set_tile(plan, R))
+
+
 def morlet_plan_info(plan: int, K: int) -> dict:
     L, ps, n0 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
     alpha, rel = ctypes.c_double(), ctypes.c_double()
@@ -110,6 +123,50 @@ def morlet_forward(plan: int, x_ptr: int, dtype: int, W_ptr: int, ws_ptr: int, w
 
 def gauss_smooth(plan: int, x_ptr: int, dtype: int, y_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
     check(lib().gauss_smooth(plan, x_ptr, dtype, y_ptr, ws_ptr, ws_bytes, stream))
+
+
+def morlet_scalogram_plan(lengths, sigmas, xis, K: int, L_over_sigma: float = 0.0) -> int:
+    B, S = len(lengths), len(sigmas)
+    h = ctypes.c_void_p()
+    ln = (ctypes.c_int64 * B)(*[int(v) for v in lengths])
+    sg = (ctypes.c_double * S)(*[float(v) for v in sigmas])
+    xs = (ctypes.c_double * S)(*[float(v) for v in xis])
+    check(lib().morlet_scalogram_plan(ctypes.byref(h), B, ln, S, sg, xs, K, float(L_over_sigma)))
+    return h.value
+
+
+def morlet_scalogram_scale_info(plan: int, s: int, K: int) -> dict:
+    L, ps, n0 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    alpha, rel = ctypes.c_double(), ctypes.c_double()
+    cc, sc, jac = (ctypes.c_double * K)(), (ctypes.c_double * K)(), (ctypes.c_double * (4 * K))()
+    check(lib().morlet_scalogram_scale_info(plan, s, ctypes.byref(L), ctypes.byref(ps), ctypes.byref(n0),
+                                            ctypes.byref(alpha), cc, sc, jac, ctypes.byref(rel)))
+    return {"L": L.value, "P_S": ps.value, "n0": n0.value, "alpha": alpha.value, "cos_coef": list(cc),
+            "sin_coef": list(sc), "jac": list(jac), "kernel_relrmse": rel.value}
+
+
+def morlet_scalogram_forward(plan: int, x_ptr: int, dtype: int, W_ptr: int, ws_ptr: int, ws_bytes: int,
+                             stream: int) -> None:
+    check(lib().morlet_scalogram_forward(plan, x_ptr, dtype, W_ptr, ws_ptr, ws_bytes, stream))
+
+
+def morlet_backward_workspace_size(plan: int) -> int:
+    n = ctypes.c_size_t()
+    check(lib().morlet_backward_workspace_size(plan, ctypes.byref(n)))
+    return n.value
+
+
+def morlet_backward(plan, x_ptr, dtype, gW_ptr, gx_ptr, gparams_ptr, ws_ptr, ws_bytes, stream) -> None:
+    check(lib().morlet_backward(plan, x_ptr, dtype, gW_ptr, gx_ptr, gparams_ptr, ws_ptr, ws_bytes, stream))
+
+
+def gauss_smooth_backward(plan, x_ptr, dtype, gy_ptr, gx_ptr, gparams_ptr, ws_ptr, ws_bytes, stream) -> None:
+    check(lib().gauss_smooth_backward(plan, x_ptr, dtype, gy_ptr, gx_ptr, gparams_ptr, ws_ptr, ws_bytes, stream))
+
+
+def morlet_scalogram_backward(plan, x_ptr, dtype, gW_ptr, gx_ptr, gparams_ptr, ws_ptr, ws_bytes, stream) -> None:
+    check(lib().morlet_scalogram_backward(plan, x_ptr, dtype, gW_ptr, gx_ptr, gparams_ptr, ws_ptr, ws_bytes,
+                                          stream))
 
 
 def morlet_destroy(plan: int) -> None:

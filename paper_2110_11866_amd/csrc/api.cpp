@@ -1,10 +1,13 @@
 // C ABI entry points (include/morlet.h): argument checks, plan construction, launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "../../include/morlet.h"
 #include "launch.h"
@@ -84,28 +87,86 @@ morlet_status check_common(int64_t N, double sigma, int32_t K, int64_t L) {
   return MORLET_OK;
 }
 
-morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, void* ws, size_t ws_bytes,
-                       void* stream, int want_kind) {
-  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
-  if (plan->kind != want_kind)
-    return fail(MORLET_ERR_INVALID_ARG, want_kind == 0 ? "morlet_forward needs a Morlet plan"
-                                                       : "gauss_smooth needs a Gaussian plan");
-  if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
-  if (plan->N == 0) return MORLET_OK;
-  if (!x || !out || !ws) return fail(MORLET_ERR_INVALID_ARG, "null x, output or workspace pointer");
+
+// ---------------------------------------------------------------- batched ragged plans
+// Rows are signal-major: row b*S + s filters signal b at scale s. The output of row (b, s)
+// starts at S * offset_b + s * len_b (layout [signal][scale][n]).
+void build_rows(morlet_plan_s* p) {
+  p->rows.clear();
+  p->tile_row.clear();
+  int64_t tile0 = 0, tmax = 0;
+  for (int b = 0; b < p->B; ++b) {
+    for (int s = 0; s < p->S; ++s) {
+      const ScaleParams& sp = p->scales[s];
+      const int64_t n0 = p->mode == 1 ? sp.n0_asft : 0;
+      mk::Row r{};
+      r.x_off = p->offsets[b];
+      r.w_off = (int64_t)p->S * p->offsets[b] + (int64_t)s * p->lengths[b];
+      r.N = p->lengths[b];
+      r.L = sp.L;
+      r.jout0 = sp.L - n0;
+      r.jend = p->lengths[b] + sp.L - n0;
+      r.tile0 = tile0;
+      r.scale = s;
+      const int64_t nt = p->lengths[b] == 0 ? 0 : tiles_for(r.jend, p->R);
+      r.ntiles = (int32_t)nt;
+      for (int64_t t = 0; t < nt; ++t) p->tile_row.push_back((int32_t)p->rows.size());
+      tile0 += nt;
+      tmax += p->lengths[b] == 0 ? 0 : tiles_for(p->lengths[b] + sp.L, p->R);
+      p->rows.push_back(r);
+    }
+  }
+  p->ntiles = tile0;
+  p->ntiles_max = tmax;
+}
+
+void build_batched_tables(morlet_plan_s* p) {
+  const mk::TabLayout lay{p->K, p->R};
+  const size_t tb = lay.bytes();
+  p->h_tab.assign(tb * p->S, 0);
+  for (int s = 0; s < p->S; ++s) {
+    const ScaleParams& sp = p->scales[s];
+    mk::fill_table(p->h_tab.data() + tb * s, p->kind, p->K, p->R, sp.L, sp.P_S, sp.sigma, sp.xi, p->mode,
+                   p->mode == 1 ? sp.n0_asft : 0, sp.cc, sp.sc, sp.jac);
+  }
+}
+
+morlet_status upload_batched(morlet_plan_s* p) {
+  morlet_status s = upload_table(p);
+  if (s != MORLET_OK || !p->d_tab) return s;
+  const size_t rb = p->rows.size() * sizeof(mk::Row), tb = p->tile_row.size() * sizeof(int32_t);
+  const size_t need = rb + tb + 16;
+  if (p->d_rows && p->rows_bytes < need) {
+    (void)hipFree(p->d_rows);
+    p->d_rows = nullptr;
+  }
+  if (!p->d_rows) {
+    if (hipMalloc(&p->d_rows, need) != hipSuccess) {
+      (void)hipGetLastError();
+      p->d_rows = nullptr;
+      return fail(MORLET_ERR_ALLOC, "hipMalloc of the row table failed");
+    }
+    p->rows_bytes = need;
+  }
+  if ((rb && hipMemcpy(p->d_rows, p->rows.data(), rb, hipMemcpyHostToDevice) != hipSuccess) ||
+      (tb && hipMemcpy(static_cast<char*>(p->d_rows) + rb, p->tile_row.data(), tb, hipMemcpyHostToDevice) != hipSuccess)) {
+    (void)hipGetLastError();
+    return fail(MORLET_ERR_HIP, "hipMemcpy of the row table failed");
+  }
+  return MORLET_OK;
+}
+
+// Fill the launch descriptor for this plan (rows, tables, tiles, workspace, grid).
+morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int variant, int mom) {
   const int64_t jend = plan->N + plan->L - plan->n0;
-  const int64_t ntiles = tiles_for(jend, plan->R);
-  if (ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
-  if (ws_bytes < mk::workspace_bytes(plan->K, ntiles)) return fail(MORLET_ERR_WORKSPACE, "workspace too small");
-  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
-  mk::ScanLaunch a{};
+  const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(jend, plan->R);
+  a = mk::ScanLaunch{};
   a.K = plan->K;
   a.R = plan->R;
-  a.wide = plan->accum;
+  // the gradient pass always accumulates in float64: the chain rule through the fitted
+  // coefficients cancels the per-term sums by orders of magnitude
+  a.wide = variant == mk::kVarParamGrad ? 1 : plan->accum;
   a.kind = plan->kind;
-  a.x = x;
-  a.dtype = dtype;
-  a.out = out;
   a.row0.x_off = 0;
   a.row0.w_off = 0;
   a.row0.N = plan->N;
@@ -115,19 +176,116 @@ morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, 
   a.row0.tile0 = 0;
   a.row0.scale = 0;
   a.row0.ntiles = (int32_t)ntiles;
-  a.rows = nullptr;
   a.nrows = 1;
-  a.tile_row = nullptr;
+  if (plan->batched) {
+    if (!plan->d_rows) return fail(MORLET_ERR_HIP, "plan has no device row table");
+    a.rows = static_cast<const mk::Row*>(plan->d_rows);
+    a.tile_row = reinterpret_cast<const int32_t*>(static_cast<const char*>(plan->d_rows) +
+                                                  plan->rows.size() * sizeof(mk::Row));
+    a.nrows = (int)plan->rows.size();
+    if (a.nrows == 1) a.row0 = plan->rows[0];
+  }
   a.ntiles = ntiles;
   a.tabs = static_cast<const unsigned char*>(plan->d_tab);
-  a.tab_stride = (int64_t)plan->tab_bytes;
+  a.tab_stride = (int64_t)mk::TabLayout{plan->K, plan->R}.bytes();
   a.f32_bytes = (int64_t)mk::TabLayout{plan->K, plan->R}.f32Bytes();
   a.ws = ws;
-  const int occ = mk::scan_forward_occupancy(a.K, a.R, a.wide, a.kind);
+  const int occ = mk::scan_occupancy(a.K, a.R, variant, a.wide, a.kind, mom);
   if (occ <= 0) return fail(MORLET_ERR_UNSUPPORTED, "no kernel for this configuration");
   const int64_t cap = (int64_t)occ * plan->num_cus;
   a.grid = (int)(ntiles < cap ? ntiles : cap);
-  const hipError_t e = mk::launch_scan_forward(a, static_cast<hipStream_t>(stream));
+  return MORLET_OK;
+}
+
+int64_t plan_ntiles_max(morlet_plan_t plan) {
+  return plan->batched ? plan->ntiles_max : tiles_for(plan->N + plan->L, plan->R);
+}
+
+// Backward workspace: header + tile states (2K complex states) | per-tile partials |
+// (batched) per-scale adjoint scratch [S][sum lengths] float32.
+struct BwdLayout {
+  size_t states_end, partials_off, scratch_off, total;
+};
+BwdLayout bwd_layout(morlet_plan_t plan) {
+  const int64_t nt = plan_ntiles_max(plan);
+  BwdLayout b;
+  b.states_end = mk::workspace_bytes(2 * plan->K, nt);
+  b.partials_off = (b.states_end + 255) / 256 * 256;
+  const size_t pbytes = (size_t)nt * mk::pg_partials(plan->K) * sizeof(double);
+  b.scratch_off = (b.partials_off + pbytes + 255) / 256 * 256;
+  const size_t sbytes = plan->batched ? (size_t)plan->S * (size_t)plan->N * sizeof(float) : 0;
+  b.total = b.scratch_off + sbytes;
+  return b;
+}
+
+morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, void* ws, size_t ws_bytes,
+                       void* stream, int want_kind, bool want_batched = false) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->kind != want_kind)
+    return fail(MORLET_ERR_INVALID_ARG, want_kind == 0 ? "morlet_forward needs a Morlet plan"
+                                                       : "gauss_smooth needs a Gaussian plan");
+  if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  if (want_batched != plan->batched)
+    return fail(MORLET_ERR_INVALID_ARG, want_batched ? "needs a scalogram plan" : "needs a single-signal plan");
+  const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(plan->N + plan->L - plan->n0, plan->R);
+  if (plan->N == 0 || ntiles == 0) return MORLET_OK;
+  if (!x || !out || !ws) return fail(MORLET_ERR_INVALID_ARG, "null x, output or workspace pointer");
+  if (ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  if (ws_bytes < mk::workspace_bytes(plan->K, ntiles)) return fail(MORLET_ERR_WORKSPACE, "workspace too small");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  mk::ScanLaunch a;
+  morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0);
+  if (st != MORLET_OK) return st;
+  a.x = x;
+  a.dtype = dtype;
+  a.out = out;
+  const hipError_t e = mk::launch_scan(a, mk::kVarForward, 0, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
+}
+
+morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const void* g, float* gx, double* gparams,
+                           void* ws, size_t ws_bytes, void* stream, int want_kind, bool want_batched) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
+  if (want_batched != plan->batched)
+    return fail(MORLET_ERR_INVALID_ARG, want_batched ? "needs a scalogram plan" : "needs a single-signal plan");
+  if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(plan->N + plan->L - plan->n0, plan->R);
+  if (plan->N == 0 || ntiles == 0) {
+    if (gparams) return fail(MORLET_ERR_UNSUPPORTED, "parameter gradients of an empty signal are not computed");
+    return MORLET_OK;
+  }
+  if (!g || !gx || !ws || (gparams && !x)) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  if (ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  const BwdLayout L = bwd_layout(plan);
+  if (ws_bytes < L.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  // 1. adjoint: dLoss/dx (per scale into the scratch for batched plans, then summed)
+  mk::ScanLaunch a;
+  morlet_status st = make_launch(plan, a, ws, mk::kVarAdjoint, 0);
+  if (st != MORLET_OK) return st;
+  a.x = g;
+  a.dtype = 0;
+  a.out = plan->batched ? static_cast<void*>(wsb + L.scratch_off) : static_cast<void*>(gx);
+  hipError_t e = mk::launch_scan(a, mk::kVarAdjoint, 0, s);
+  if (e == hipSuccess && plan->batched)
+    e = mk::launch_sum_scales(reinterpret_cast<const float*>(wsb + L.scratch_off), gx, a.rows, plan->B, plan->S,
+                              plan->N, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  if (!gparams) return MORLET_OK;
+  // 2. parameter gradients: forward scan of x reduced against g, then the finalize kernel
+  const int mom = plan->mode == 1 ? 1 : 0;
+  st = make_launch(plan, a, ws, mk::kVarParamGrad, mom);
+  if (st != MORLET_OK) return st;
+  a.x = x;
+  a.dtype = dtype;
+  a.g = g;
+  a.partials = reinterpret_cast<double*>(wsb + L.partials_off);
+  e = mk::launch_scan(a, mk::kVarParamGrad, mom, s);
+  if (e == hipSuccess) e = mk::launch_pg_finalize(a, plan->batched ? plan->S : 1, gparams, s);
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return MORLET_OK;
 }
@@ -189,9 +347,18 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
   if (mode != MORLET_SCAN_SFT && mode != MORLET_SCAN_ASFT) return fail(MORLET_ERR_UNSUPPORTED, "unknown scan mode");
   if (accum != MORLET_ACC_F32 && accum != MORLET_ACC_COMPENSATED)
     return fail(MORLET_ERR_UNSUPPORTED, "unknown accumulation mode");
-  if (n0 < 0 || n0 > plan->L) return fail(MORLET_ERR_INVALID_ARG, "n0 must be 0 (default) or in [1, L]");
+  if (n0 < 0 || (!plan->batched && n0 > plan->L))
+    return fail(MORLET_ERR_INVALID_ARG, "n0 must be 0 (default) or in [1, L]");
   plan->mode = (int)mode;
   plan->accum = (int)accum;
+  if (plan->batched) {
+    for (ScaleParams& sp : plan->scales)
+      sp.n0_asft = n0 > 0 ? std::min<int64_t>(n0, sp.L) : default_n0(sp.sigma, sp.L);
+    build_rows(plan);
+    build_batched_tables(plan);
+    if (plan->d_tab) return upload_batched(plan);
+    return MORLET_OK;
+  }
   if (n0 > 0) plan->n0_asft = n0;
   plan->n0 = (mode == MORLET_SCAN_ASFT) ? plan->n0_asft : 0;
   std::string err;
@@ -200,9 +367,42 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
   return MORLET_OK;
 }
 
+morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (R != 8 && R != 16) return fail(MORLET_ERR_UNSUPPORTED, "R must be 8 or 16");
+  if (R == plan->R) return MORLET_OK;
+  const int oldR = plan->R;
+  plan->R = R;
+  if (plan->batched) {
+    build_rows(plan);
+    if (plan->ntiles > ((int64_t)1 << 31)) {
+      plan->R = oldR;
+      build_rows(plan);
+      return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+    }
+    build_batched_tables(plan);
+    if (plan->d_tab) {
+      // the table size depends on R: reallocate
+      (void)hipFree(plan->d_tab);
+      plan->d_tab = nullptr;
+      return upload_batched(plan);
+    }
+    return MORLET_OK;
+  }
+  std::string err;
+  mk::build_table(plan, &err);
+  if (plan->d_tab) {
+    (void)hipFree(plan->d_tab);
+    plan->d_tab = nullptr;
+    return upload_table(plan);
+  }
+  return MORLET_OK;
+}
+
 morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int64_t* n0, double* alpha,
                                double* cos_coef, double* sin_coef, double* jac, double* kernel_relrmse) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->batched) return fail(MORLET_ERR_INVALID_ARG, "use morlet_scalogram_scale_info for a scalogram plan");
   if (L) *L = plan->L;
   if (P_S) *P_S = plan->P_S;
   if (n0) *n0 = plan->n0;
@@ -217,7 +417,7 @@ morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int
 morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
   // sized for the longest scan range over every n0 the plan may use (n0 = 0)
-  *bytes = mk::workspace_bytes(plan->K, tiles_for(plan->N + plan->L, plan->R));
+  *bytes = mk::workspace_bytes(plan->K, plan->batched ? plan->ntiles_max : tiles_for(plan->N + plan->L, plan->R));
   return MORLET_OK;
 }
 
@@ -230,18 +430,144 @@ morlet_status morlet_workspace_init(void* ws, size_t ws_bytes, void* stream) {
 
 morlet_status morlet_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W, void* ws,
                              size_t ws_bytes, void* stream) {
-  return run_scan(plan, x, (int)dtype, W, ws, ws_bytes, stream, 0);
+  return run_scan(plan, x, (int)dtype, W, ws, ws_bytes, stream, 0, false);
 }
 
 morlet_status gauss_smooth(morlet_plan_t plan, const void* x, morlet_dtype dtype, float* y, void* ws,
                            size_t ws_bytes, void* stream) {
-  return run_scan(plan, x, (int)dtype, y, ws, ws_bytes, stream, 1);
+  return run_scan(plan, x, (int)dtype, y, ws, ws_bytes, stream, 1, false);
+}
+
+
+morlet_status morlet_scalogram_plan(morlet_plan_t* out, int32_t B, const int64_t* lengths, int32_t S,
+                                    const double* sigmas, const double* xis, int32_t K, double L_over_sigma) {
+  if (!out) return fail(MORLET_ERR_INVALID_ARG, "null output handle");
+  if (B < 1 || S < 1) return fail(MORLET_ERR_INVALID_ARG, "B and S must be >= 1");
+  if (!lengths || !sigmas || !xis) return fail(MORLET_ERR_INVALID_ARG, "null lengths, sigmas or xis");
+  if (K < 1 || K > MORLET_MAX_TERMS) return fail(MORLET_ERR_INVALID_ARG, "K must be in [1, MORLET_MAX_TERMS]");
+  if (!(L_over_sigma >= 0.0) || !std::isfinite(L_over_sigma))
+    return fail(MORLET_ERR_INVALID_ARG, "L_over_sigma must be 0 or a finite positive ratio");
+  int64_t total = 0;
+  for (int b = 0; b < B; ++b) {
+    if (lengths[b] < 0 || lengths[b] > ((int64_t)1 << 40)) return fail(MORLET_ERR_INVALID_ARG, "bad signal length");
+    total += lengths[b];
+  }
+  for (int s = 0; s < S; ++s) {
+    if (!finite_pos(sigmas[s]) || !finite_pos(xis[s])) return fail(MORLET_ERR_INVALID_ARG, "bad sigma or xi");
+    if (L_over_sigma > 0 && std::ceil(L_over_sigma * sigmas[s]) > (double)((int64_t)1 << 30))
+      return fail(MORLET_ERR_INVALID_ARG, "window too large");
+  }
+  auto* p = new (std::nothrow) morlet_plan_s;
+  if (!p) return fail(MORLET_ERR_ALLOC, "out of host memory");
+  p->kind = 0;
+  p->batched = true;
+  p->B = B;
+  p->S = S;
+  p->K = K;
+  p->N = total;
+  p->R = 16;
+  p->lengths.assign(lengths, lengths + B);
+  p->offsets.resize(B);
+  int64_t off = 0;
+  for (int b = 0; b < B; ++b) { p->offsets[b] = off; off += lengths[b]; }
+  p->scales.resize(S);
+  bool bad = false;
+  auto work = [&](int s) {
+    ScaleParams& sp = p->scales[s];
+    sp.sigma = sigmas[s];
+    sp.xi = xis[s];
+    sp.L = L_over_sigma > 0 ? (int64_t)std::ceil(L_over_sigma * sp.sigma) : mk::select_L(sp.sigma, sp.xi, K, false);
+    if (sp.L < K) sp.L = K;
+    sp.P_S = mk::select_ps(sp.sigma, sp.xi, K, sp.L, nullptr);
+    std::vector<double> re, im;
+    mk::morlet_taps(sp.sigma, sp.xi, sp.L, re, im);
+    const mk::Fit f = mk::fit_orders(re, im, sp.L, sp.P_S, K);
+    sp.cc = f.cc;
+    sp.sc = f.sc;
+    sp.relrmse = f.relrmse;
+    morlet_plan_s tmp;
+    tmp.kind = 0; tmp.sigma = sp.sigma; tmp.xi = sp.xi; tmp.K = K; tmp.L = sp.L; tmp.P_S = sp.P_S;
+    mk::jacobian(&tmp);
+    sp.jac = tmp.jac;
+    sp.n0_asft = default_n0(sp.sigma, sp.L);
+    if (!std::isfinite(sp.relrmse)) bad = true;
+  };
+  {
+    const int nth = (int)std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+      th.emplace_back([&, t] { for (int s = t; s < S; s += nth) work(s); });
+    for (auto& t : th) t.join();
+  }
+  if (bad) {
+    delete p;
+    return fail(MORLET_ERR_INVALID_ARG, "fit failed for some scale");
+  }
+  build_rows(p);
+  if (p->ntiles > ((int64_t)1 << 31)) {
+    delete p;
+    return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  }
+  build_batched_tables(p);
+  const morlet_status s = upload_batched(p);
+  if (s != MORLET_OK) {
+    morlet_destroy(p);
+    return s;
+  }
+  *out = p;
+  return MORLET_OK;
+}
+
+morlet_status morlet_scalogram_scale_info(morlet_plan_t plan, int32_t s, int64_t* L, int32_t* P_S, int64_t* n0,
+                                          double* alpha, double* cos_coef, double* sin_coef, double* jac,
+                                          double* kernel_relrmse) {
+  if (!plan || !plan->batched) return fail(MORLET_ERR_INVALID_ARG, "needs a scalogram plan");
+  if (s < 0 || s >= plan->S) return fail(MORLET_ERR_INVALID_ARG, "scale index out of range");
+  const ScaleParams& sp = plan->scales[s];
+  const int64_t n0v = plan->mode == 1 ? sp.n0_asft : 0;
+  if (L) *L = sp.L;
+  if (P_S) *P_S = sp.P_S;
+  if (n0) *n0 = n0v;
+  if (alpha) *alpha = (double)n0v / (sp.sigma * sp.sigma);
+  if (cos_coef) std::memcpy(cos_coef, sp.cc.data(), sizeof(double) * plan->K);
+  if (sin_coef) std::memcpy(sin_coef, sp.sc.data(), sizeof(double) * plan->K);
+  if (jac) std::memcpy(jac, sp.jac.data(), sizeof(double) * 4 * plan->K);
+  if (kernel_relrmse) *kernel_relrmse = sp.relrmse;
+  return MORLET_OK;
+}
+
+morlet_status morlet_scalogram_forward(morlet_plan_t plan, const void* x_packed, morlet_dtype dtype,
+                                       void* W_packed, void* ws, size_t ws_bytes, void* stream) {
+  return run_scan(plan, x_packed, (int)dtype, W_packed, ws, ws_bytes, stream, 0, true);
 }
 
 void morlet_destroy(morlet_plan_t plan) {
   if (!plan) return;
   if (plan->d_tab) (void)hipFree(plan->d_tab);
+  if (plan->d_rows) (void)hipFree(plan->d_rows);
   delete plan;
+}
+
+morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
+  *bytes = bwd_layout(plan).total;
+  return MORLET_OK;
+}
+
+morlet_status morlet_backward(morlet_plan_t plan, const void* x, morlet_dtype dtype, const void* gW, float* gx,
+                              double* gparams, void* ws, size_t ws_bytes, void* stream) {
+  return run_backward(plan, x, (int)dtype, gW, gx, gparams, ws, ws_bytes, stream, 0, false);
+}
+
+morlet_status gauss_smooth_backward(morlet_plan_t plan, const void* x, morlet_dtype dtype, const float* gy,
+                                    float* gx, double* gparams, void* ws, size_t ws_bytes, void* stream) {
+  return run_backward(plan, x, (int)dtype, gy, gx, gparams, ws, ws_bytes, stream, 1, false);
+}
+
+morlet_status morlet_scalogram_backward(morlet_plan_t plan, const void* x_packed, morlet_dtype dtype,
+                                        const void* gW_packed, float* gx_packed, double* gparams, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  return run_backward(plan, x_packed, (int)dtype, gW_packed, gx_packed, gparams, ws, ws_bytes, stream, 0, true);
 }
 
 const char* morlet_last_error(void) { return g_err.c_str(); }

@@ -21,7 +21,21 @@ struct ScanLaunch {
   int64_t f32_bytes;            // offset of the float64 half of a table
   void* ws;                     // workspace (header + tile states)
   int grid;                     // persistent grid size
+  const void* g;                // gradient pass: cotangent at the outputs (complex64 or float32)
+  double* partials;             // gradient pass: per-tile float64 partial sums
 };
+
+enum ScanVariant { kVarForward = 0, kVarAdjoint = 1, kVarParamGrad = 2 };
+
+// Launch a scan variant (forward, adjoint, parameter-gradient pass; mom: carry the
+// alpha-derivative states for the ASFT sigma gradient).
+hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s);
+int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom);
+// Sum per-tile partials into d/dsigma, d/dxi per scale (one block per scale).
+hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* gparams, hipStream_t s);
+// out[b][n] = sum_s part[b][s][n] over the signals of a batched adjoint.
+hipError_t launch_sum_scales(const float* part, float* out, const Row* rows, int B, int S, int64_t total,
+                             hipStream_t s);
 
 hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s);
 // Resident blocks per CU of the forward kernel for this configuration (0 if unsupported).

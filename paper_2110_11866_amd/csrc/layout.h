@@ -28,7 +28,7 @@ constexpr int kLookback = 64;    // predecessors inspected per look-back step (o
 // ---------------------------------------------------------------------------------
 struct TabLayout {
   int K, R;
-  // complex entries
+  // complex entries: powers a_p^d at the distances the kernels need
   MK_HD int eA() const { return 0; }                    // a_p
   MK_HD int eP1(int r) const { return 1 + r; }          // a_p^{R-1-r}, r in [0, R): chunk sum weights
   MK_HD int eTR(int d) const { return 1 + R + d; }      // a_p^{R 2^d}, d in [0, 6): wave scan
@@ -36,16 +36,28 @@ struct TabLayout {
   MK_HD int eWV(int w) const { return 71 + R + w; }     // a_p^{64 R w}, w in [0, kWaves]: per-wave carry; w = kWaves gives a^T
   MK_HD int eLB(int k) const { return 72 + R + kWaves + k; }  // a_p^{T k}, k in [0, 64]: look-back weights
   MK_HD int nComplex() const { return 72 + R + kWaves + 65; }
-  // real entries, after the complex ones (index in units of K values)
-  MK_HD int rMW() const { return 2 * nComplex(); }      // (-1)^p m_p e^{alpha L}
-  MK_HD int rLW() const { return 2 * nComplex() + 1; }  // (-1)^p l_p e^{alpha L}
-  MK_HD int nKRows() const { return 2 * nComplex() + 2; }
+  // entry nComplex() + e holds d a_p^d for the distance d of entry e (alpha-derivative)
+  MK_HD int nComplexAll() const { return 2 * nComplex(); }
+  // real K-rows, after the complex ones (row index in units of K values)
+  MK_HD int rMW() const { return 2 * nComplexAll(); }      // (-1)^p m_p e^{alpha L}
+  MK_HD int rLW() const { return 2 * nComplexAll() + 1; }  // (-1)^p l_p e^{alpha L}
+  MK_HD int rSGN() const { return 2 * nComplexAll() + 2; } // (-1)^p
+  MK_HD int rCC() const { return 2 * nComplexAll() + 3; }  // m_p (a_p for the Gaussian)
+  MK_HD int rSC() const { return 2 * nComplexAll() + 4; }  // l_p
+  MK_HD int rJ(int q) const { return 2 * nComplexAll() + 5 + q; }  // Jacobian rows: dcc/dsigma, dcc/dxi, dsc/dsigma, dsc/dxi
+  MK_HD int nKRows() const { return 2 * nComplexAll() + 9; }
   // scalars, after the K-rows
   MK_HD int sCX() const { return nKRows() * K + 0; }    // sum_p (-1)^p m_p e^{-alpha L}
   MK_HD int sD() const { return nKRows() * K + 1; }     // e^{-2 alpha L}: trailing-edge weight
   MK_HD int sGre() const { return nKRows() * K + 2; }   // output factor e^{i xi n0} e^{-n0^2/(2 sigma^2)}
   MK_HD int sGim() const { return nKRows() * K + 3; }
-  MK_HD int nValues() const { return nKRows() * K + 4; }
+  MK_HD int sUP() const { return nKRows() * K + 4; }    // e^{alpha L}
+  MK_HD int sDN() const { return nKRows() * K + 5; }    // e^{-alpha L}
+  MK_HD int sLL() const { return nKRows() * K + 6; }    // L
+  MK_HD int sDSIG() const { return nKRows() * K + 7; }  // d log(output scale) / d sigma = n0^2 / sigma^3 (ASFT)
+  MK_HD int sDXI() const { return nKRows() * K + 8; }   // d arg(output factor) / d xi = n0 (ASFT Morlet)
+  MK_HD int sDALPHA() const { return nKRows() * K + 9; }  // d alpha / d sigma = -2 n0 / sigma^3 (ASFT)
+  MK_HD int nValues() const { return nKRows() * K + 10; }
   MK_HD size_t f32Bytes() const { return ((size_t)nValues() * 4 + 255) / 256 * 256; }
   MK_HD size_t f64Bytes() const { return ((size_t)nValues() * 8 + 255) / 256 * 256; }
   MK_HD size_t bytes() const { return f32Bytes() + f64Bytes(); }
@@ -82,5 +94,8 @@ MK_HD inline size_t tile_state_bytes(int K) { return ((size_t)(8 + 32 * K) + 63)
 inline size_t workspace_bytes(int K, int64_t ntiles) {
   return sizeof(WsHeader) + tile_state_bytes(K) * (size_t)(ntiles > 0 ? ntiles : 0);
 }
+
+// Per-tile partial sums of the parameter-gradient pass: 4K + 3 doubles.
+inline int pg_partials(int K) { return 4 * K + 3; }
 
 }  // namespace mk

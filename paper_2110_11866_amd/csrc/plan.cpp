@@ -296,77 +296,81 @@ inline void apow(int64_t p, int64_t m, int64_t L, double alpha, double& re, doub
 }  // namespace
 
 void fill_table(unsigned char* dst, int kind, int K, int R, int64_t L, int P_S, double sigma, double xi,
-                int mode, int64_t n0, const std::vector<double>& cc, const std::vector<double>& sc) {
+                int mode, int64_t n0, const std::vector<double>& cc, const std::vector<double>& sc,
+                const std::vector<double>& jac) {
   TabLayout lay{K, R};
   std::memset(dst, 0, lay.bytes());
   float* tf = (float*)dst;
   double* td = (double*)(dst + lay.f32Bytes());
   const double alpha = (mode == 1) ? (double)n0 / (sigma * sigma) : 0.0;
   const int64_t T = (int64_t)R * kThreads;
-  auto put = [&](int e, int i, double re, double im) {
+  const int mo = lay.nComplex();
+  // entry e gets a^d, entry mo + e gets d a^d
+  auto put = [&](int e, int i, int64_t p, int64_t d) {
+    double re, im;
+    apow(p, d, L, alpha, re, im);
+    const double dd = (double)d;
     tf[(2 * e) * K + i] = (float)re;
     tf[(2 * e + 1) * K + i] = (float)im;
     td[(2 * e) * K + i] = re;
     td[(2 * e + 1) * K + i] = im;
+    tf[(2 * (mo + e)) * K + i] = (float)(dd * re);
+    tf[(2 * (mo + e) + 1) * K + i] = (float)(dd * im);
+    td[(2 * (mo + e)) * K + i] = dd * re;
+    td[(2 * (mo + e) + 1) * K + i] = dd * im;
+  };
+  auto putrow = [&](int row, int i, double v) {
+    tf[row * K + i] = (float)v;
+    td[row * K + i] = v;
   };
   double cx = 0;
   for (int i = 0; i < K; ++i) {
     const int64_t p = P_S + i;
-    double re, im;
-    apow(p, 1, L, alpha, re, im);
-    put(lay.eA(), i, re, im);
-    for (int r = 0; r < R; ++r) {
-      apow(p, R - 1 - r, L, alpha, re, im);
-      put(lay.eP1(r), i, re, im);
-    }
-    for (int d = 0; d < 6; ++d) {
-      apow(p, (int64_t)R << d, L, alpha, re, im);
-      put(lay.eTR(d), i, re, im);
-    }
-    for (int l = 0; l < 64; ++l) {
-      apow(p, (int64_t)R * l, L, alpha, re, im);
-      put(lay.eLANE(l), i, re, im);
-    }
-    for (int w = 0; w <= kWaves; ++w) {
-      apow(p, (int64_t)64 * R * w, L, alpha, re, im);
-      put(lay.eWV(w), i, re, im);
-    }
-    for (int k = 0; k <= 64; ++k) {
-      apow(p, T * k, L, alpha, re, im);
-      put(lay.eLB(k), i, re, im);
-    }
+    put(lay.eA(), i, p, 1);
+    for (int r = 0; r < R; ++r) put(lay.eP1(r), i, p, R - 1 - r);
+    for (int d = 0; d < 6; ++d) put(lay.eTR(d), i, p, (int64_t)R << d);
+    for (int l = 0; l < 64; ++l) put(lay.eLANE(l), i, p, (int64_t)R * l);
+    for (int w = 0; w <= kWaves; ++w) put(lay.eWV(w), i, p, (int64_t)64 * R * w);
+    for (int k = 0; k <= 64; ++k) put(lay.eLB(k), i, p, T * k);
     const double sgn = (p & 1) ? -1.0 : 1.0;
     const double up = std::exp(alpha * (double)L), dn = std::exp(-alpha * (double)L);
-    const double mw = sgn * cc[i] * up, lw = sgn * sc[i] * up;
-    tf[lay.rMW() * K + i] = (float)mw;
-    td[lay.rMW() * K + i] = mw;
-    tf[lay.rLW() * K + i] = (float)lw;
-    td[lay.rLW() * K + i] = lw;
+    putrow(lay.rMW(), i, sgn * cc[i] * up);
+    putrow(lay.rLW(), i, sgn * sc[i] * up);
+    putrow(lay.rSGN(), i, sgn);
+    putrow(lay.rCC(), i, cc[i]);
+    putrow(lay.rSC(), i, sc[i]);
+    for (int q = 0; q < 4; ++q) putrow(lay.rJ(q), i, jac.size() == (size_t)4 * K ? jac[q * K + i] : 0.0);
     cx += sgn * cc[i] * dn;
   }
   const double D = std::exp(-2.0 * alpha * (double)L);
-  double gre = 1.0, gim = 0.0;
+  double gre = 1.0, gim = 0.0, dsig = 0.0, dxi = 0.0, dalpha = 0.0;
   if (mode == 1) {
     const double s = std::exp(-(double)n0 * (double)n0 / (2.0 * sigma * sigma));
     if (kind == 0) {
       gre = s * std::cos(xi * (double)n0);
       gim = s * std::sin(xi * (double)n0);
+      dxi = (double)n0;
     } else {
       gre = s;
     }
+    dsig = (double)n0 * (double)n0 / (sigma * sigma * sigma);
+    dalpha = -2.0 * (double)n0 / (sigma * sigma * sigma);
   }
-  const double sc4[4] = {cx, D, gre, gim};
-  const int so[4] = {lay.sCX(), lay.sD(), lay.sGre(), lay.sGim()};
-  for (int q = 0; q < 4; ++q) {
-    tf[so[q]] = (float)sc4[q];
-    td[so[q]] = sc4[q];
+  const double sv[10] = {cx, D, gre, gim, std::exp(alpha * (double)L), std::exp(-alpha * (double)L), (double)L,
+                         dsig, dxi, dalpha};
+  const int so[10] = {lay.sCX(), lay.sD(), lay.sGre(), lay.sGim(), lay.sUP(), lay.sDN(), lay.sLL(), lay.sDSIG(),
+                      lay.sDXI(), lay.sDALPHA()};
+  for (int q = 0; q < 10; ++q) {
+    tf[so[q]] = (float)sv[q];
+    td[so[q]] = sv[q];
   }
 }
 
 bool build_table(morlet_plan_s* p, std::string* err) {
   TabLayout lay{p->K, p->R};
   p->h_tab.assign(lay.bytes(), 0);
-  fill_table(p->h_tab.data(), p->kind, p->K, p->R, p->L, p->P_S, p->sigma, p->xi, p->mode, p->n0, p->cc, p->sc);
+  fill_table(p->h_tab.data(), p->kind, p->K, p->R, p->L, p->P_S, p->sigma, p->xi, p->mode, p->n0, p->cc, p->sc,
+             p->jac);
   (void)err;
   return true;
 }

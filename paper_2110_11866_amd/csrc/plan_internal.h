@@ -6,6 +6,16 @@
 
 #include "layout.h"
 
+// One scale of a batched plan.
+struct ScaleParams {
+  double sigma = 0, xi = 0;
+  int64_t L = 0;
+  int P_S = 0;
+  int64_t n0_asft = 0;
+  std::vector<double> cc, sc, jac;
+  double relrmse = 0;
+};
+
 struct morlet_plan_s {
   int kind = 0;           // 0 Morlet, 1 Gaussian
   int64_t N = 0;
@@ -26,6 +36,16 @@ struct morlet_plan_s {
   void* d_tab = nullptr;  // device copy of the constant table
   size_t tab_bytes = 0;
   std::vector<unsigned char> h_tab;
+  // batched ragged plans (B signals x S scales); empty for single-signal plans
+  bool batched = false;
+  int B = 0, S = 0;
+  std::vector<int64_t> lengths, offsets;   // per signal (offsets: prefix sums of lengths)
+  std::vector<ScaleParams> scales;
+  std::vector<mk::Row> rows;               // B*S rows, signal-major
+  std::vector<int32_t> tile_row;
+  int64_t ntiles = 0, ntiles_max = 0;
+  void* d_rows = nullptr;                  // device rows followed by tile_row
+  size_t rows_bytes = 0;
 };
 
 namespace mk {
@@ -51,6 +71,7 @@ void jacobian(morlet_plan_s* p);
 bool build_table(morlet_plan_s* p, std::string* err);
 // Fill one table for arbitrary parameters (used by the scalogram plans as well).
 void fill_table(unsigned char* dst, int kind, int K, int R, int64_t L, int P_S, double sigma, double xi,
-                int mode, int64_t n0, const std::vector<double>& cc, const std::vector<double>& sc);
+                int mode, int64_t n0, const std::vector<double>& cc, const std::vector<double>& sc,
+                const std::vector<double>& jac);
 
 }  // namespace mk

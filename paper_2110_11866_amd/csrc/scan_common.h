@@ -1,0 +1,188 @@
+// Device helpers shared by the scan kernels (gfx950): coherent tile-state access for the
+// look-back, input loads, and the constant-table view.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "launch.h"
+
+namespace mk {
+namespace {
+
+// ------------------------------------------------------------ coherent tile-state access
+__device__ __forceinline__ void st_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_u64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_f64(double* p, double v) {
+  st_u64(reinterpret_cast<uint64_t*>(p), (uint64_t)__double_as_longlong(v));
+}
+__device__ __forceinline__ double ld_f64(const double* p) {
+  return __longlong_as_double((long long)ld_u64(reinterpret_cast<const uint64_t*>(p)));
+}
+// s_waitcnt vmcnt(0): wait for all of this wave's vector memory operations.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+__device__ __forceinline__ void release_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  wait_vmem();
+}
+__device__ __forceinline__ void acquire_order() {
+  wait_vmem();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+struct TileState {
+  unsigned char* b;
+  int K;
+  __device__ uint64_t* flag() const { return reinterpret_cast<uint64_t*>(b); }
+  __device__ double* agg(int i, int c) const { return reinterpret_cast<double*>(b + 8) + 2 * i + c; }
+  __device__ double* inc(int i, int c) const { return reinterpret_cast<double*>(b + 8) + 2 * K + 2 * i + c; }
+};
+
+// ------------------------------------------------------------ input loads
+__device__ __forceinline__ float cvt_f16(unsigned short h) {
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+__device__ __forceinline__ float cvt_bf16(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float load1(const void* base, int dtype, int64_t j) {
+  if (dtype == 0) return static_cast<const float*>(base)[j];
+  const unsigned short h = static_cast<const unsigned short*>(base)[j];
+  return dtype == 1 ? cvt_f16(h) : cvt_bf16(h);
+}
+
+// v[r] = x[j + r] for r < R, zero outside [0, N).
+template <int R>
+__device__ __forceinline__ void load_run(const void* base, int dtype, int64_t j, int64_t N, float (&v)[R]) {
+  if (j >= 0 && j + R <= N) {
+    if (dtype == 0) {
+      const float* p = static_cast<const float*>(base) + j;
+      if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+#pragma unroll
+        for (int r = 0; r < R; r += 4) {
+          const float4 q = *reinterpret_cast<const float4*>(p + r);
+          v[r] = q.x; v[r + 1] = q.y; v[r + 2] = q.z; v[r + 3] = q.w;
+        }
+      } else if ((reinterpret_cast<uintptr_t>(p) & 7) == 0) {
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+          const float2 q = *reinterpret_cast<const float2*>(p + r);
+          v[r] = q.x; v[r + 1] = q.y;
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = p[r];
+      }
+    } else {
+      const unsigned short* p = static_cast<const unsigned short*>(base) + j;
+      if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+#pragma unroll
+        for (int r = 0; r < R; r += 8) {
+          const uint4 q = *reinterpret_cast<const uint4*>(p + r);
+          const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const unsigned short lo = (unsigned short)(w[h] & 0xffffu), hi = (unsigned short)(w[h] >> 16);
+            v[r + 2 * h] = dtype == 1 ? cvt_f16(lo) : cvt_bf16(lo);
+            v[r + 2 * h + 1] = dtype == 1 ? cvt_f16(hi) : cvt_bf16(hi);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = dtype == 1 ? cvt_f16(p[r]) : cvt_bf16(p[r]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t q = j + r;
+      v[r] = (q >= 0 && q < N) ? load1(base, dtype, q) : 0.0f;
+    }
+  }
+}
+
+// v[r] = p[j + r] (float32), zero outside [0, N)
+template <int R>
+__device__ __forceinline__ void load_run_f32(const float* p, int64_t j, int64_t N, float (&v)[R]) {
+  if (j >= 0 && j + R <= N) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = p[j + r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = (j + r >= 0 && j + r < N) ? p[j + r] : 0.0f;
+  }
+}
+
+// (re, im)[r] = p[j + r] (complex64), zero outside [0, N)
+template <int R>
+__device__ __forceinline__ void load_run_c(const float2* p, int64_t j, int64_t N, float (&re)[R], float (&im)[R]) {
+  if (j >= 0 && j + R <= N) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) { const float2 q = p[j + r]; re[r] = q.x; im[r] = q.y; }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool in = (j + r >= 0 && j + r < N);
+      const float2 q = in ? p[j + r] : make_float2(0.f, 0.f);
+      re[r] = q.x; im[r] = q.y;
+    }
+  }
+}
+
+// time-reversed runs: v[r] = p[N - 1 - (j + r)], zero where j + r is outside [0, N)
+template <int R>
+__device__ __forceinline__ void load_run_rev(const float* p, int64_t j, int64_t N, float (&v)[R]) {
+  if (j >= 0 && j + R <= N) {
+    const float* q = p + (N - j - R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = q[R - 1 - r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = (j + r >= 0 && j + r < N) ? p[N - 1 - (j + r)] : 0.0f;
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void load_run_rev_c(const float2* p, int64_t j, int64_t N, float (&re)[R], float (&im)[R]) {
+  if (j >= 0 && j + R <= N) {
+    const float2* q = p + (N - j - R);
+#pragma unroll
+    for (int r = 0; r < R; ++r) { const float2 z = q[R - 1 - r]; re[r] = z.x; im[r] = z.y; }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool in = (j + r >= 0 && j + r < N);
+      const float2 z = in ? p[N - 1 - (j + r)] : make_float2(0.f, 0.f);
+      re[r] = z.x; im[r] = z.y;
+    }
+  }
+}
+
+// LDS writes of this wave are visible to its other lanes after this (single-wave exchange)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ------------------------------------------------------------ constant table access
+// Table reads go through the constant address space: uniform indices become scalar loads
+// into SGPRs instead of occupying vector registers.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <bool WIDE>
+struct Tab {
+  using T = typename std::conditional<WIDE, double, float>::type;
+  cptr<T> p;
+  int K;
+  __device__ T re(int e, int i) const { return p[(2 * e) * K + i]; }
+  __device__ T im(int e, int i) const { return p[(2 * e + 1) * K + i]; }
+  __device__ T row(int rrow, int i) const { return p[rrow * K + i]; }
+  __device__ T scalar(int s) const { return p[s]; }
+};
+
+}  // namespace
+}  // namespace mk

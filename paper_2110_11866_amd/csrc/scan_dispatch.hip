@@ -1,0 +1,170 @@
+// Dispatch of the scan kernels, the gradient finalize and scale-sum kernels and the
+// workspace fill kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "launch.h"
+#include "scan_common.h"
+
+namespace mk {
+
+using KernelFn = void (*)(ScanLaunch);
+KernelFn select_scan_k1(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k2(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k3(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k4(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k5(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k6(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k7(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k8(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k9(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k10(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k11(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k12(int R, int var, int wide, int gauss, int mom);
+
+namespace {
+
+KernelFn select_kernel(int K, int R, int var, int wide, int gauss, int mom) {
+  switch (K) {
+    case 1: return select_scan_k1(R, var, wide, gauss, mom);
+    case 2: return select_scan_k2(R, var, wide, gauss, mom);
+    case 3: return select_scan_k3(R, var, wide, gauss, mom);
+    case 4: return select_scan_k4(R, var, wide, gauss, mom);
+    case 5: return select_scan_k5(R, var, wide, gauss, mom);
+    case 6: return select_scan_k6(R, var, wide, gauss, mom);
+    case 7: return select_scan_k7(R, var, wide, gauss, mom);
+    case 8: return select_scan_k8(R, var, wide, gauss, mom);
+    case 9: return select_scan_k9(R, var, wide, gauss, mom);
+    case 10: return select_scan_k10(R, var, wide, gauss, mom);
+    case 11: return select_scan_k11(R, var, wide, gauss, mom);
+    case 12: return select_scan_k12(R, var, wide, gauss, mom);
+    default: return nullptr;
+  }
+}
+
+__global__ void zero_fill_kernel(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+  if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+// One block per scale. The per-tile partial sums of the gradient pass are summed in a fixed
+// order (tile k of the scale goes to thread k mod 256, then a fixed tree), then turned into
+// dLoss/dsigma and dLoss/dxi:
+//   dL/dm_p = sgn_p (e^{aL} S1_p + e^{-aL} Sx),  dL/dl_p = sgn_p e^{aL} S2_p   (chain rule
+//   through the fitted coefficients, Jacobian rows from the plan), plus for ASFT the output
+//   scale (n0^2/sigma^3 Re Q), the carrier phase (-n0 Im Q) and the decay
+//   dL/dalpha = sum_p sgn_p [m_p (e^{aL} (L S1_p + S3_p) - L e^{-aL} Sx) + l_p e^{aL} (L S2_p + S4_p)],
+//   dalpha/dsigma = -2 n0 / sigma^3.
+__global__ __launch_bounds__(256) void pg_finalize_kernel(ScanLaunch P, int K, double* gparams) {
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int NRED = 4 * K + 3;
+  __shared__ double red[256];
+  __shared__ double tot[4 * kMaxTerms + 3];
+  double acc[4 * kMaxTerms + 3];
+  for (int q = 0; q < NRED; ++q) acc[q] = 0.0;
+  int64_t k = 0;
+  for (int r = 0; r < P.nrows; ++r) {
+    const Row row = P.nrows == 1 ? P.row0 : P.rows[r];
+    if (row.scale != s) continue;
+    for (int64_t t = 0; t < row.ntiles; ++t, ++k) {
+      if ((k & 255) != tid) continue;
+      const double* pp = P.partials + (size_t)(row.tile0 + t) * NRED;
+      for (int q = 0; q < NRED; ++q) acc[q] += pp[q];
+    }
+  }
+  for (int q = 0; q < NRED; ++q) {
+    red[tid] = acc[q];
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) tot[q] = red[0];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const TabLayout lay{K, P.R};
+    const double* td = reinterpret_cast<const double*>(P.tabs + (int64_t)s * P.tab_stride + P.f32_bytes);
+    const double up = td[lay.sUP()], dn = td[lay.sDN()], LL = td[lay.sLL()];
+    const double* S = tot;
+    const double Sx = S[4 * K], Qr = S[4 * K + 1], Qi = S[4 * K + 2];
+    double ds = td[lay.sDSIG()] * Qr, dx = -td[lay.sDXI()] * Qi, dal = 0.0;
+    for (int t = 0; t < K; ++t) {
+      const double sg = td[lay.rSGN() * K + t];
+      const double gm = sg * (up * S[t] + dn * Sx), gl = sg * up * S[K + t];
+      ds += td[lay.rJ(0) * K + t] * gm + td[lay.rJ(2) * K + t] * gl;
+      dx += td[lay.rJ(1) * K + t] * gm + td[lay.rJ(3) * K + t] * gl;
+      const double cc = td[lay.rCC() * K + t], sc = td[lay.rSC() * K + t];
+      dal += sg * (cc * (up * (LL * S[t] + S[2 * K + t]) - LL * dn * Sx) + sc * up * (LL * S[K + t] + S[3 * K + t]));
+    }
+    ds += td[lay.sDALPHA()] * dal;
+    gparams[2 * s] = ds;
+    gparams[2 * s + 1] = dx;
+  }
+}
+
+// out[x_off_b + n] = sum_s part[S x_off_b + s len_b + n]: the adjoints of one signal's
+// scales summed in scale order. Row b S is scale 0 of signal b.
+__global__ void sum_scales_kernel(const float* part, float* out, const Row* rows, int B, int S, int64_t total) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    int lo = 0, hi = B - 1;   // last signal with x_off <= e
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rows[(int64_t)mid * S].x_off <= e) lo = mid; else hi = mid - 1;
+    }
+    const Row r0 = rows[(int64_t)lo * S];
+    const int64_t n = e - r0.x_off;
+    float acc = 0.f;
+    for (int s = 0; s < S; ++s) acc += part[(int64_t)S * r0.x_off + (int64_t)s * r0.N + n];
+    out[e] = acc;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s) {
+  KernelFn fn = select_kernel(a.K, a.R, variant, a.wide, a.kind, mom);
+  if (!fn) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fn, dim3(a.grid), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom) {
+  KernelFn fn = select_kernel(K, R, variant, wide, kind, mom);
+  if (!fn) return 0;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), kThreads, 0) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s) { return launch_scan(a, kVarForward, 0, s); }
+
+int scan_forward_occupancy(int K, int R, int wide, int kind) { return scan_occupancy(K, R, kVarForward, wide, kind, 0); }
+
+hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* gparams, hipStream_t s) {
+  hipLaunchKernelGGL(pg_finalize_kernel, dim3(nscales), dim3(256), 0, s, a, a.K, gparams);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_scales(const float* part, float* out, const Row* rows, int B, int S, int64_t total,
+                             hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const unsigned int blocks = (unsigned int)std::min<int64_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(sum_scales_kernel, dim3(blocks), dim3(256), 0, s, part, out, rows, B, S, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const size_t n16 = bytes / 16, ntail = bytes % 16;
+  const unsigned int blocks = (unsigned int)std::min<size_t>((n16 + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(blocks), dim3(256), 0, s, static_cast<uint4*>(p), n16,
+                     static_cast<unsigned char*>(p) + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+}  // namespace mk

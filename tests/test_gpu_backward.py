@@ -1,0 +1,219 @@
+"""Backward pass of the HIP path against the FP64 oracle: the adjoint (dLoss/dx), the
+parameter gradients (dLoss/dsigma, dLoss/dxi with the plan frozen), the batched scalogram
+backward and the autograd layer. Bars: relative L2 1e-5 for dLoss/dx (1e-6 compensated),
+relative 1e-5 for the parameter gradients."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import morlet_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_11866_amd  # noqa: F401
+    yield
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_plan(kind, sigma, K, info, mode):
+    if kind == "morlet":
+        return O.plan_morlet(sigma, 6.0 / sigma, K, info["L"], mode=mode,
+                             n0=info["n0"] if mode == "asft" else None, P_S=info["P_S"])
+    return O.plan_gauss(sigma, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None)
+
+
+CASES = [(1024, 16.0, 4, 64), (50000, 300.0, 6, 1200), (9000, 40.0, 5, 0)]
+
+
+@pytest.mark.parametrize("accum", ["f32", "compensated"])
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+@pytest.mark.parametrize("kind", ["morlet", "gauss"])
+@pytest.mark.parametrize("N,sigma,K,L", CASES)
+def test_backward_matches_oracle(N, sigma, K, L, kind, mode, accum):
+    import paper_2110_11866_amd as M
+    _announce("backward", N, sigma, K, L, kind, mode, accum)
+    rng = np.random.default_rng(N + K + len(mode))
+    x = rng.standard_normal(N).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    if kind == "morlet":
+        plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode, accum=accum)
+        W = plan.forward(xt)
+        w = torch.from_numpy(rng.uniform(size=N).astype(np.float32)).cuda()
+        g = (2 * w * W).contiguous()             # cotangent of Loss = sum w |W|^2
+    else:
+        plan = M.GaussPlan(N, sigma, K, L, mode=mode, accum=accum)
+        g = torch.from_numpy(rng.standard_normal(N).astype(np.float32)).cuda()
+    gx, gp = plan.backward(xt, g)
+    torch.cuda.synchronize()
+    info = plan.info()
+    p = _oracle_plan(kind, sigma, K, info, mode)
+    gn = g.cpu().numpy().astype(np.complex128 if kind == "morlet" else np.float64)
+    want_gx = O.adjoint(gn, p)
+    tol = 1e-6 if accum == "compensated" else 1e-5
+    assert rel(gx.cpu().numpy(), want_gx) <= tol, rel(gx.cpu().numpy(), want_gx)
+    want_gp = O.param_grads(x.astype(np.float64), gn, p)
+    got_gp = gp.cpu().numpy()
+    if kind == "gauss":
+        assert got_gp[1] == 0.0
+        assert abs(got_gp[0] - want_gp[0]) <= 1e-5 * abs(want_gp[0]), (got_gp, want_gp)
+    else:
+        assert np.all(np.abs(got_gp - want_gp) <= 1e-5 * np.abs(want_gp)), (got_gp, want_gp)
+
+
+def test_adjoint_identity_on_gpu():
+    # Re <g, A x> = <x, A^T g> with both sides from the GPU kernels
+    import paper_2110_11866_amd as M
+    _announce("adjoint-identity")
+    N = 70000
+    rng = np.random.default_rng(3)
+    x = torch.from_numpy(rng.standard_normal(N).astype(np.float32)).cuda()
+    g = torch.from_numpy((rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)).cuda()
+    for mode in ("sft", "asft"):
+        plan = M.MorletPlan(N, 500.0, 6 / 500.0, 6, 2000, mode=mode)
+        W = plan.forward(x).cpu().numpy().astype(np.complex128)
+        gx, _ = plan.backward(None, g, want_params=False)
+        lhs = np.sum((np.conj(g.cpu().numpy().astype(np.complex128)) * W).real)
+        rhs = float(np.dot(x.cpu().numpy().astype(np.float64), gx.cpu().numpy().astype(np.float64)))
+        assert abs(lhs - rhs) <= 2e-5 * (abs(lhs) + np.sqrt(N)), (mode, lhs, rhs)
+
+
+def test_backward_repeat_bitwise():
+    import paper_2110_11866_amd as M
+    _announce("backward-repeat")
+    N = 200000
+    rng = np.random.default_rng(8)
+    x = torch.from_numpy(rng.standard_normal(N).astype(np.float32)).cuda()
+    g = torch.from_numpy((rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)).cuda()
+    plan = M.MorletPlan(N, 100.0, 0.06, 5, 400, mode="asft")
+    a = [plan.backward(x, g) for _ in range(3)]
+    torch.cuda.synchronize()
+    for gx, gp in a[1:]:
+        assert torch.equal(gx, a[0][0]) and torch.equal(gp, a[0][1])
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_scalogram_backward_small(mode):
+    import paper_2110_11866_amd as M
+    _announce("scalogram-backward", mode)
+    lengths = [300, 5000, 1, 12000]
+    sigmas = [4.0, 30.0, 200.0]
+    xis = [6.0 / s for s in sigmas]
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(sum(lengths)).astype(np.float32)
+    plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=mode)
+    xt = torch.from_numpy(x).cuda()
+    W = plan.forward(xt)
+    g = torch.from_numpy((rng.standard_normal(W.numel()) + 1j * rng.standard_normal(W.numel()))
+                         .astype(np.complex64)).cuda()
+    gx, gp = plan.backward(xt, g)
+    torch.cuda.synchronize()
+    gn, gxn, gpn = g.cpu().numpy().astype(np.complex128), gx.cpu().numpy(), gp.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    want_gx = np.zeros(sum(lengths))
+    want_gp = np.zeros((len(sigmas), 2))
+    for s in range(len(sigmas)):
+        info = plan.scale_info(s)
+        p = O.plan_morlet(sigmas[s], xis[s], 5, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None,
+                          P_S=info["P_S"])
+        for b in range(len(lengths)):
+            n = lengths[b]
+            o = plan.out_offset(b, s)
+            gb = gn[o:o + n]
+            want_gx[offs[b]:offs[b] + n] += O.adjoint(gb, p)
+            if n:
+                want_gp[s] += O.param_grads(x[offs[b]:offs[b] + n].astype(np.float64), gb, p)
+    assert rel(gxn, want_gx) <= 1e-5, rel(gxn, want_gx)
+    assert np.all(np.abs(gpn - want_gp) <= 1e-5 * np.abs(want_gp) + 1e-9), (gpn, want_gp)
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_autograd_layer_and_central_differences(mode):
+    # Loss = sum w |W|^2: torch autograd through the layer against the oracle's gradients,
+    # and the oracle's gradient against central differences at relative steps 1e-3 / 1e-4
+    import paper_2110_11866_amd as M
+    _announce("autograd", mode)
+    N, sigma, xi, K = 4000, 25.0, 6 / 25.0, 5
+    rng = np.random.default_rng(6)
+    x = torch.from_numpy(rng.standard_normal(N).astype(np.float32)).cuda().requires_grad_(True)
+    w = torch.from_numpy(rng.uniform(size=N).astype(np.float32)).cuda()
+    layer = M.MorletTransform(N, sigma, xi, K, 0, mode=mode)
+    W = layer(x)
+    loss = (w * (W.real ** 2 + W.imag ** 2)).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    p = layer.plan()
+    info = p.info()
+    op = O.plan_morlet(sigma, xi, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None,
+                       P_S=info["P_S"])
+    xd = x.detach().cpu().numpy().astype(np.float64)
+    wd = w.cpu().numpy().astype(np.float64)
+    Wo = O.forward(xd, op)
+    go = 2 * wd * Wo
+    want = O.param_grads(xd, go, op)
+    assert abs(layer.sigma.grad.item() - want[0]) <= 1e-4 * abs(want[0]), (layer.sigma.grad.item(), want[0])
+    assert abs(layer.xi.grad.item() - want[1]) <= 1e-4 * abs(want[1]), (layer.xi.grad.item(), want[1])
+    assert rel(x.grad.cpu().numpy(), O.adjoint(go, op)) <= 1e-4
+
+    def loss_o(s, xx):
+        m, l = O.fit_morlet(s, xx, K, op.L, op.P_S)
+        q = O.Plan("morlet", s, xx, K, op.L, op.P_S, mode, op.n0, m, l)
+        return np.sum(wd * np.abs(O.forward(xd, q)) ** 2)
+
+    for t, (base, grad) in enumerate(((sigma, want[0]), (xi, want[1]))):
+        errs = []
+        for h in (1e-3, 1e-4):
+            a = (base * (1 + h), xi) if t == 0 else (sigma, base * (1 + h))
+            b = (base * (1 - h), xi) if t == 0 else (sigma, base * (1 - h))
+            fd = (loss_o(*a) - loss_o(*b)) / (2 * h * base)
+            errs.append(abs(fd - grad) / abs(grad))
+        assert errs[1] < 1e-4 and errs[1] < errs[0], errs
+
+
+def test_differentiation_workload_sampled():
+    # 64 signals x 32768 samples, 16 scales sigma = 8..2048, K = 5, Loss = sum w |W|^2 with
+    # w ~ U[0,1] per (scale, n) shared over the batch; gradients for x (4 signals checked in
+    # full) and for every (sigma_s, xi_s) (oracle summed over all 64 signals)
+    import paper_2110_11866_amd as M
+    _announce("differentiation-workload")
+    x, sigmas, xis, w = workloads.differentiation_batch()
+    B, N = x.shape
+    S = len(sigmas)
+    plan = M.ScalogramPlan([N] * B, sigmas, xis, 5, 0.0)
+    xt = torch.from_numpy(x.reshape(-1)).cuda()
+    W = plan.forward(xt)
+    wt = torch.from_numpy(np.tile(w.reshape(1, S, N), (B, 1, 1)).reshape(-1)).cuda()
+    g = (2 * wt * W).contiguous()
+    gx, gp = plan.backward(xt, g)
+    torch.cuda.synchronize()
+    gn = g.cpu().numpy().astype(np.complex128).reshape(B, S, N)
+    gxn, gpn = gx.cpu().numpy().reshape(B, N), gp.cpu().numpy()
+    plans = []
+    for s in range(S):
+        info = plan.scale_info(s)
+        plans.append(O.plan_morlet(sigmas[s], xis[s], 5, info["L"], P_S=info["P_S"]))
+    for b in (0, 17, 40, 63):
+        want = sum(O.adjoint(gn[b, s], plans[s]) for s in range(S))
+        assert rel(gxn[b], want) <= 1e-5, (b, rel(gxn[b], want))
+    want_gp = np.zeros((S, 2))
+    for b in range(B):
+        xb = x[b].astype(np.float64)
+        for s in range(S):
+            want_gp[s] += O.param_grads(xb, gn[b, s], plans[s])
+    assert np.all(np.abs(gpn - want_gp) <= 1e-5 * np.abs(want_gp)), np.abs(gpn - want_gp) / np.abs(want_gp)

@@ -1,0 +1,97 @@
+"""Batched ragged scalogram (one persistent launch over every signal x scale row) against
+the FP64 oracle, row by row."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import morlet_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_11866_amd  # noqa: F401
+    yield
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _check_rows(plan, W, x_used, rows, mode, tol):
+    offs = np.concatenate([[0], np.cumsum(plan.lengths)])
+    worst = 0.0
+    for b, s in rows:
+        n = plan.lengths[b]
+        info = plan.scale_info(s)
+        p = O.plan_morlet(plan.sigmas[s], plan.xis[s], plan.K, info["L"], mode=mode,
+                          n0=info["n0"] if mode == "asft" else None, P_S=info["P_S"])
+        want = O.forward(x_used[offs[b]:offs[b] + n], p)
+        o = plan.out_offset(b, s)
+        got = W[o:o + n]
+        if n:
+            e = rel_l2(got, want)
+            worst = max(worst, e)
+            assert e <= tol, (b, s, e)
+    return worst
+
+
+@pytest.mark.parametrize("mode,accum,tol", [("sft", "f32", 1e-5), ("asft", "f32", 1e-5), ("asft", "compensated", 1e-6)])
+def test_small_ragged_batch_all_rows(mode, accum, tol):
+    # ragged lengths including empty, shorter than the window, and multi-tile signals
+    import paper_2110_11866_amd as M
+    _announce("ragged-small", mode, accum)
+    lengths = [0, 1, 37, 4096, 5000, 20000, 123, 65536]
+    sigmas = [3.0, 10.0, 45.0, 300.0, 1500.0]
+    xis = [6.0 / s for s in sigmas]
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(sum(lengths)).astype(np.float32)
+    plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=mode, accum=accum)
+    xt = torch.from_numpy(x).cuda()
+    W = plan.forward(xt).cpu().numpy()
+    W2 = plan.forward(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(W.view(np.uint32), W2.view(np.uint32))
+    rows = [(b, s) for b in range(len(lengths)) for s in range(len(sigmas))]
+    _check_rows(plan, W, xt.double().cpu().numpy(), rows, mode, tol)
+
+
+def test_fixed_window_ratio():
+    import paper_2110_11866_amd as M
+    _announce("ratio-window")
+    lengths = [3000, 7000]
+    sigmas = [8.0, 64.0]
+    plan = M.ScalogramPlan(lengths, sigmas, [6 / s for s in sigmas], 6, 4.0)
+    assert [plan.scale_info(s)["L"] for s in range(2)] == [32, 256]
+    x = np.random.default_rng(3).standard_normal(10000).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    W = plan.forward(xt).cpu().numpy()
+    _check_rows(plan, W, xt.double().cpu().numpy(), [(b, s) for b in range(2) for s in range(2)], "sft", 1e-5)
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_full_ragged_scalogram_sampled_rows(mode):
+    # 256 pink-noise signals, lengths log-uniform in [4096, 262144], 32 scales 4..4096, K = 5,
+    # error-optimal windows: the launch the benchmark times; 40 rows checked in full
+    import paper_2110_11866_amd as M
+    _announce("ragged-full", mode)
+    x, lengths, sigmas, xis = workloads.ragged_scalogram()
+    plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=mode)
+    xt = torch.from_numpy(x).cuda()
+    W = plan.forward(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(99)
+    rows = [(int(rng.integers(0, 256)), int(rng.integers(0, 32))) for _ in range(36)]
+    rows += [(int(np.argmax(lengths)), 31), (int(np.argmin(lengths)), 31), (0, 0), (255, 31)]
+    _check_rows(plan, W, xt.double().cpu().numpy(), rows, mode, 1e-5)

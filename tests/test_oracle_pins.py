@@ -399,3 +399,33 @@ def test_gaussian_unit_mass_and_variance():
         g = O.gaussian(sigma, k)
         assert abs(g.sum() - 1.0) < 1e-13
         assert abs((k * k * g).sum() / sigma ** 2 - 1.0) < 1e-12
+
+
+def test_fft_convolution_path_matches_direct_sums():
+    # the large-size path of conv_same (FFT convolution) against the direct sums of the
+    # small-size path, on the same data, complex taps and both shifts
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal(3000)
+    h = rng.standard_normal(801) + 1j * rng.standard_normal(801)
+    old = O.FFT_CONV_MIN
+    try:
+        for shift in (0, 7, -5):
+            O.FFT_CONV_MIN = 1 << 62
+            a = O.conv_same(x, h, 400, shift)
+            O.FFT_CONV_MIN = 1
+            b = O.conv_same(x, h, 400, shift)
+            assert np.abs(a - b).max() < 1e-11 * np.abs(a).max()
+    finally:
+        O.FFT_CONV_MIN = old
+
+
+def test_adjoint_equals_transposed_matrix():
+    # the adjoint against the explicit transpose of the forward matrix on a tiny case
+    rng = np.random.default_rng(18)
+    for mode in ("sft", "asft"):
+        pl = O.plan_morlet(3.0, 2.0, 3, 9, mode=mode, n0=2 if mode == "asft" else None)
+        N = 30
+        A = np.stack([O.forward(np.eye(N)[j], pl) for j in range(N)], axis=1)   # W = A x
+        g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        want = (A.conj().T @ g).real                                            # Re A^H g
+        assert np.allclose(O.adjoint(g, pl), want, atol=1e-13)
