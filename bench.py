@@ -38,7 +38,9 @@ def _parse():
     ap.add_argument("--workload", default="scalogram", choices=["scalogram", "paper_scale"])
     ap.add_argument("--mode", default="asft", choices=["sft", "asft"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--tile", type=int, default=16, choices=[8, 16], help="samples per thread")
+    ap.add_argument("--tile", type=int, default=16, choices=[16, 32], help="samples per thread")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run plain device copies of this many MB (counter calibration for HBM bytes)")
     return ap.parse_args()
 
 
@@ -172,6 +174,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.randn(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": args.steps}), flush=True)
+        return
 
     import paper_2110_11866_amd as M
     fn = bench_scalogram if args.workload == "scalogram" else bench_paper_scale

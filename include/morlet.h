@@ -99,7 +99,7 @@ morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,
                               morlet_accum accum);
 
-/* Tile shape of the scan kernels: R consecutive samples per thread (8 or 16; 256 threads
+/* Tile shape of the scan kernels: R consecutive samples per thread (16 or 32; 256 threads
  * per block, so a tile covers 256 R scan positions). Default 16. Changes the workspace
  * size; rebuilds the device tables synchronously. Results do not depend on R beyond
  * float32 rounding. */

@@ -45,7 +45,7 @@ class _PlanBase:
         return self
 
     def set_tile(self, R: int) -> "_PlanBase":
-        """Samples per thread of the scan kernels (8 or 16)."""
+        """Samples per thread of the scan kernels (16 or 32)."""
         _abi.morlet_plan_set_tile(self.handle, int(R))
         self._ws = None
         return self

@@ -157,7 +157,7 @@ morlet_status upload_batched(morlet_plan_s* p) {
 }
 
 // Fill the launch descriptor for this plan (rows, tables, tiles, workspace, grid).
-morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int variant, int mom) {
+morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int variant, int mom, int dtype) {
   const int64_t jend = plan->N + plan->L - plan->n0;
   const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(jend, plan->R);
   a = mk::ScanLaunch{};
@@ -190,7 +190,8 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   a.tab_stride = (int64_t)mk::TabLayout{plan->K, plan->R}.bytes();
   a.f32_bytes = (int64_t)mk::TabLayout{plan->K, plan->R}.f32Bytes();
   a.ws = ws;
-  const int occ = mk::scan_occupancy(a.K, a.R, variant, a.wide, a.kind, mom);
+  a.dtype = dtype;
+  const int occ = mk::scan_occupancy(a.K, a.R, variant, a.wide, a.kind, mom, dtype);
   if (occ <= 0) return fail(MORLET_ERR_UNSUPPORTED, "no kernel for this configuration");
   const int64_t cap = (int64_t)occ * plan->num_cus;
   a.grid = (int)(ntiles < cap ? ntiles : cap);
@@ -234,7 +235,7 @@ morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, 
   if (ws_bytes < mk::workspace_bytes(plan->K, ntiles)) return fail(MORLET_ERR_WORKSPACE, "workspace too small");
   if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
   mk::ScanLaunch a;
-  morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0);
+  morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0, dtype);
   if (st != MORLET_OK) return st;
   a.x = x;
   a.dtype = dtype;
@@ -265,7 +266,7 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
   unsigned char* wsb = static_cast<unsigned char*>(ws);
   // 1. adjoint: dLoss/dx (per scale into the scratch for batched plans, then summed)
   mk::ScanLaunch a;
-  morlet_status st = make_launch(plan, a, ws, mk::kVarAdjoint, 0);
+  morlet_status st = make_launch(plan, a, ws, mk::kVarAdjoint, 0, 0);
   if (st != MORLET_OK) return st;
   a.x = g;
   a.dtype = 0;
@@ -278,7 +279,7 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
   if (!gparams) return MORLET_OK;
   // 2. parameter gradients: forward scan of x reduced against g, then the finalize kernel
   const int mom = plan->mode == 1 ? 1 : 0;
-  st = make_launch(plan, a, ws, mk::kVarParamGrad, mom);
+  st = make_launch(plan, a, ws, mk::kVarParamGrad, mom, dtype);
   if (st != MORLET_OK) return st;
   a.x = x;
   a.dtype = dtype;
@@ -369,7 +370,7 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
 
 morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
-  if (R != 8 && R != 16) return fail(MORLET_ERR_UNSUPPORTED, "R must be 8 or 16");
+  if (R != 16 && R != 32) return fail(MORLET_ERR_UNSUPPORTED, "R must be 16 or 32");
   if (R == plan->R) return MORLET_OK;
   const int oldR = plan->R;
   plan->R = R;

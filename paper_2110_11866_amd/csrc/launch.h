@@ -30,7 +30,7 @@ enum ScanVariant { kVarForward = 0, kVarAdjoint = 1, kVarParamGrad = 2 };
 // Launch a scan variant (forward, adjoint, parameter-gradient pass; mom: carry the
 // alpha-derivative states for the ASFT sigma gradient).
 hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s);
-int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom);
+int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int dtype);
 // Sum per-tile partials into d/dsigma, d/dxi per scale (one block per scale).
 hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* gparams, hipStream_t s);
 // out[b][n] = sum_s part[b][s][n] over the signals of a batched adjoint.

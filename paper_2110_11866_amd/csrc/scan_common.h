@@ -161,6 +161,106 @@ __device__ __forceinline__ void load_run_rev_c(const float2* p, int64_t j, int64
   }
 }
 
+// ------------------------------------------------------------ four-sample loads
+// v[r] = x[j + r], r < 4, zero outside [0, N); 16-byte (8-byte for 16-bit types) loads
+// when the quad is inside the signal and aligned
+__device__ __forceinline__ void load4(const void* base, int dtype, int64_t j, int64_t N, float (&v)[4]) {
+  if (j >= 0 && j + 4 <= N) {
+    if (dtype == 0) {
+      const float* p = static_cast<const float*>(base) + j;
+      if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = p[r];
+      }
+    } else {
+      const unsigned short* p = static_cast<const unsigned short*>(base) + j;
+      uint32_t w0, w1;
+      if ((reinterpret_cast<uintptr_t>(p) & 7) == 0) {
+        const uint2 q = *reinterpret_cast<const uint2*>(p);
+        w0 = q.x; w1 = q.y;
+      } else {
+        w0 = (uint32_t)p[0] | ((uint32_t)p[1] << 16);
+        w1 = (uint32_t)p[2] | ((uint32_t)p[3] << 16);
+      }
+      const unsigned short h[4] = {(unsigned short)(w0 & 0xffffu), (unsigned short)(w0 >> 16),
+                                   (unsigned short)(w1 & 0xffffu), (unsigned short)(w1 >> 16)};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = dtype == 1 ? cvt_f16(h[r]) : cvt_bf16(h[r]);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = (j + r >= 0 && j + r < N) ? load1(base, dtype, j + r) : 0.0f;
+  }
+}
+
+__device__ __forceinline__ void load4_f32(const float* p, int64_t j, int64_t N, float (&v)[4]) {
+  if (j >= 0 && j + 4 <= N && (reinterpret_cast<uintptr_t>(p + j) & 15) == 0) {
+    const float4 q = *reinterpret_cast<const float4*>(p + j);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = (j + r >= 0 && j + r < N) ? p[j + r] : 0.0f;
+  }
+}
+
+__device__ __forceinline__ void load4_c(const float2* p, int64_t j, int64_t N, float (&re)[4], float (&im)[4]) {
+  if (j >= 0 && j + 4 <= N && (reinterpret_cast<uintptr_t>(p + j) & 15) == 0) {
+    const float4 a = *reinterpret_cast<const float4*>(p + j), b = *reinterpret_cast<const float4*>(p + j + 2);
+    re[0] = a.x; im[0] = a.y; re[1] = a.z; im[1] = a.w; re[2] = b.x; im[2] = b.y; re[3] = b.z; im[3] = b.w;
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool in = j + r >= 0 && j + r < N;
+      const float2 z = in ? p[j + r] : make_float2(0.f, 0.f);
+      re[r] = z.x; im[r] = z.y;
+    }
+  }
+}
+
+// unchecked quads (the caller has checked range and alignment)
+template <int DT>
+__device__ __forceinline__ void ld4_fast(const void* base, int64_t j, float (&v)[4]) {
+  if constexpr (DT == 0) {
+    const float4 q = *reinterpret_cast<const float4*>(static_cast<const float*>(base) + j);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else {
+    const uint2 q = *reinterpret_cast<const uint2*>(static_cast<const unsigned short*>(base) + j);
+    const unsigned short h[4] = {(unsigned short)(q.x & 0xffffu), (unsigned short)(q.x >> 16),
+                                 (unsigned short)(q.y & 0xffffu), (unsigned short)(q.y >> 16)};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = DT == 1 ? cvt_f16(h[r]) : cvt_bf16(h[r]);
+  }
+}
+
+__device__ __forceinline__ void ld4_rev_fast(const float* p, int64_t N, int64_t j, float (&v)[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p + (N - 4 - j));
+  v[0] = q.w; v[1] = q.z; v[2] = q.y; v[3] = q.x;
+}
+
+__device__ __forceinline__ void ld4c_rev_fast(const float2* p, int64_t N, int64_t j, float (&re)[4], float (&im)[4]) {
+  const float2* q = p + (N - 4 - j);
+  const float4 a = *reinterpret_cast<const float4*>(q), b = *reinterpret_cast<const float4*>(q + 2);
+  re[3] = a.x; im[3] = a.y; re[2] = a.z; im[2] = a.w; re[1] = b.x; im[1] = b.y; re[0] = b.z; im[0] = b.w;
+}
+
+// time-reversed quads: v[r] = p[N - 1 - (j + r)], zero where j + r is outside [0, N)
+__device__ __forceinline__ void load4_rev(const float* p, int64_t j, int64_t N, float (&v)[4]) {
+  float t[4];
+  load4_f32(p, N - 4 - j, N, t);   // covers indices N-4-j .. N-1-j, i.e. j+3 .. j reversed
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = t[3 - r];
+}
+
+__device__ __forceinline__ void load4_rev_c(const float2* p, int64_t j, int64_t N, float (&re)[4], float (&im)[4]) {
+  float tr[4], ti[4];
+  load4_c(p, N - 4 - j, N, tr, ti);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) { re[r] = tr[3 - r]; im[r] = ti[3 - r]; }
+}
+
 // LDS writes of this wave are visible to its other lanes after this (single-wave exchange)
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0)

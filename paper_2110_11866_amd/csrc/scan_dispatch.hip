@@ -10,35 +10,35 @@
 namespace mk {
 
 using KernelFn = void (*)(ScanLaunch);
-KernelFn select_scan_k1(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k2(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k3(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k4(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k5(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k6(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k7(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k8(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k9(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k10(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k11(int R, int var, int wide, int gauss, int mom);
-KernelFn select_scan_k12(int R, int var, int wide, int gauss, int mom);
+KernelFn select_scan_k1(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k2(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k3(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k4(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k5(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k6(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k7(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k8(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k9(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k10(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k11(int R, int var, int wide, int gauss, int mom, int dt);
+KernelFn select_scan_k12(int R, int var, int wide, int gauss, int mom, int dt);
 
 namespace {
 
-KernelFn select_kernel(int K, int R, int var, int wide, int gauss, int mom) {
+KernelFn select_kernel(int K, int R, int var, int wide, int gauss, int mom, int dt) {
   switch (K) {
-    case 1: return select_scan_k1(R, var, wide, gauss, mom);
-    case 2: return select_scan_k2(R, var, wide, gauss, mom);
-    case 3: return select_scan_k3(R, var, wide, gauss, mom);
-    case 4: return select_scan_k4(R, var, wide, gauss, mom);
-    case 5: return select_scan_k5(R, var, wide, gauss, mom);
-    case 6: return select_scan_k6(R, var, wide, gauss, mom);
-    case 7: return select_scan_k7(R, var, wide, gauss, mom);
-    case 8: return select_scan_k8(R, var, wide, gauss, mom);
-    case 9: return select_scan_k9(R, var, wide, gauss, mom);
-    case 10: return select_scan_k10(R, var, wide, gauss, mom);
-    case 11: return select_scan_k11(R, var, wide, gauss, mom);
-    case 12: return select_scan_k12(R, var, wide, gauss, mom);
+    case 1: return select_scan_k1(R, var, wide, gauss, mom, dt);
+    case 2: return select_scan_k2(R, var, wide, gauss, mom, dt);
+    case 3: return select_scan_k3(R, var, wide, gauss, mom, dt);
+    case 4: return select_scan_k4(R, var, wide, gauss, mom, dt);
+    case 5: return select_scan_k5(R, var, wide, gauss, mom, dt);
+    case 6: return select_scan_k6(R, var, wide, gauss, mom, dt);
+    case 7: return select_scan_k7(R, var, wide, gauss, mom, dt);
+    case 8: return select_scan_k8(R, var, wide, gauss, mom, dt);
+    case 9: return select_scan_k9(R, var, wide, gauss, mom, dt);
+    case 10: return select_scan_k10(R, var, wide, gauss, mom, dt);
+    case 11: return select_scan_k11(R, var, wide, gauss, mom, dt);
+    case 12: return select_scan_k12(R, var, wide, gauss, mom, dt);
     default: return nullptr;
   }
 }
@@ -126,14 +126,14 @@ __global__ void sum_scales_kernel(const float* part, float* out, const Row* rows
 }  // namespace
 
 hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s) {
-  KernelFn fn = select_kernel(a.K, a.R, variant, a.wide, a.kind, mom);
+  KernelFn fn = select_kernel(a.K, a.R, variant, a.wide, a.kind, mom, variant == kVarAdjoint ? 0 : a.dtype);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(a.grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom) {
-  KernelFn fn = select_kernel(K, R, variant, wide, kind, mom);
+int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int dtype) {
+  KernelFn fn = select_kernel(K, R, variant, wide, kind, mom, variant == kVarAdjoint ? 0 : dtype);
   if (!fn) return 0;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), kThreads, 0) != hipSuccess)
@@ -143,7 +143,7 @@ int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom) {
 
 hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s) { return launch_scan(a, kVarForward, 0, s); }
 
-int scan_forward_occupancy(int K, int R, int wide, int kind) { return scan_occupancy(K, R, kVarForward, wide, kind, 0); }
+int scan_forward_occupancy(int K, int R, int wide, int kind) { return scan_occupancy(K, R, kVarForward, wide, kind, 0, 0); }
 
 hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* gparams, hipStream_t s) {
   hipLaunchKernelGGL(pg_finalize_kernel, dim3(nscales), dim3(256), 0, s, a, a.K, gparams);

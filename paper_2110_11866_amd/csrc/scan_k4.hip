@@ -2,9 +2,9 @@
 #include "scan_kernel.h"
 
 namespace mk {
-KernelFn select_scan_k4(int R, int var, int wide, int gauss, int mom) {
-  if (R == 8) return pick_scan<4, 8>(var, wide, gauss, mom);
-  if (R == 16) return pick_scan<4, 16>(var, wide, gauss, mom);
+KernelFn select_scan_k4(int R, int var, int wide, int gauss, int mom, int dt) {
+  if (R == 16) return pick_scan<4, 16>(var, wide, gauss, mom, dt);
+  if (R == 32) return pick_scan<4, 32>(var, wide, gauss, mom, dt);
   return nullptr;
 }
 }  // namespace mk

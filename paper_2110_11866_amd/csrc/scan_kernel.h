@@ -30,18 +30,19 @@
 //
 // How (one block = one tile of T = 256 R scan positions, persistent grid, ticketed tiles):
 //   1. each thread loads R consecutive inputs at j and j-2L and forms dy (coalesced runs);
-//   2. chunk sums B = sum_r a^{R-1-r} dy[r] (the thread's contribution to the state);
+//   2. chunk sums B = sum_r a^{R-1-r} dy[r] (the thread's contribution to the state), in
+//      float64 like everything else that propagates along the row;
 //   3. inclusive scan of the chunk sums across the wavefront (6 shuffle levels, constants
-//      a^{R 2^d});
+//      a^{R 2^d}, float64);
 //   4. wave 0 forms the tile aggregate in float64, publishes it, and resolves the tile's
 //      exclusive prefix by a deterministic decoupled look-back: the aggregates of the
 //      earlier tiles of its 64-tile group plus the inclusive prefix of the previous
 //      group's last tile, gathered one predecessor per lane and summed by a fixed butterfly
 //      (agent-scope atomics that bypass the per-XCD L2, so tiles on different XCDs see each
 //      other's states);
-//   5. each thread rotates its carry in, runs the R-step recurrence and produces its
-//      outputs, staged through LDS for coalesced stores (kFwd, kAdj) or reduced per tile
-//      into float64 partials (kPg).
+//   5. each thread rotates its carry in, runs the R-step recurrence and writes its R
+//      outputs straight from registers as 16-byte stores (kFwd, kAdj), or reduces them per
+//      tile into float64 partials (kPg).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -62,13 +63,12 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
   zi = fma(cr, xi, fma(ci, xr, zi));
 }
 
-template <int VAR, int K, int R, bool WIDE, bool GAUSS, bool MOM>
+template <int VAR, int K, int R, bool WIDE, bool GAUSS, bool MOM, int DT>
 __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
   using acc_t = typename std::conditional<WIDE, double, float>::type;
   constexpr int T = R * kThreads;
   constexpr int NS = (VAR == kAdj && !GAUSS) ? 2 : 1;   // real input streams
   constexpr int KS = (NS == 2 || MOM) ? 2 * K : K;      // complex states per position
-  constexpr int LSTR = (VAR == kFwd && !GAUSS) ? (2 * R + 2) : (R + 1);
   constexpr int NRED = 4 * K + 3;                        // kPg partial sums per tile
   static_assert(!(MOM && VAR != kPg), "moment states only in the gradient pass");
 
@@ -77,7 +77,6 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
   __shared__ double s_xw[kWaves][2 * KS];
   __shared__ double s_e[kWaves][2 * KS];
   __shared__ double s_p[2 * KS];
-  __shared__ float s_stage[(VAR == kPg) ? 1 : kWaves * 64 * LSTR];
   __shared__ double s_red[(VAR == kPg) ? kWaves * NRED : 1];
 
   WsHeader* hdr = static_cast<WsHeader*>(P.ws);
@@ -87,7 +86,6 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
   const uint64_t epoch = ld_u64(&hdr->epoch);
   const uint64_t tag = (epoch + 1) << 2;
   const TabLayout lay{K, R};
-  const int esz = P.dtype == 0 ? 4 : 2;
 
   // A block claims its next tile only when it is ready to start it: a tile claimed early
   // would hold back the look-back of every later tile of its group.
@@ -112,53 +110,112 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
     const Tab<true> tabd{(cptr<double>)(tb + P.f32_bytes), K};
     const int mo = lay.nComplex();   // offset of the moment entries d a^d
 
-    // 1. differenced inputs dy[j] = y[j] - a^{2L} y[j-2L] (zero past the row's scan range)
-    float ya[NS][R], yb[NS][R];
-    if constexpr (VAR == kAdj) {
-      if constexpr (GAUSS) {
-        const float* g = static_cast<const float*>(P.x) + row.w_off;
-        load_run_rev<R>(g, j0, row.N, ya[0]);
-        load_run_rev<R>(g, j0 - 2 * row.L, row.N, yb[0]);
+    // 1. inputs, four positions at a time: y[j..j+3] and y[j-2L..j-2L+3] (zero outside the
+    //    signal). Passes over the thread's R positions run as rolled loops over these quads,
+    //    so register use does not grow with R.
+    auto load_quad = [&](int64_t j, float (&ya)[NS][4], float (&yb)[NS][4]) {
+      if constexpr (VAR == kAdj) {
+        if constexpr (GAUSS) {
+          const float* g = static_cast<const float*>(P.x) + row.w_off;
+          load4_rev(g, j, row.N, ya[0]);
+          load4_rev(g, j - 2 * row.L, row.N, yb[0]);
+        } else {
+          const float2* g = static_cast<const float2*>(P.x) + row.w_off;
+          load4_rev_c(g, j, row.N, ya[0], ya[NS - 1]);
+          load4_rev_c(g, j - 2 * row.L, row.N, yb[0], yb[NS - 1]);
+        }
       } else {
-        const float2* g = static_cast<const float2*>(P.x) + row.w_off;
-        load_run_rev_c<R>(g, j0, row.N, ya[0], ya[NS - 1]);
-        load_run_rev_c<R>(g, j0 - 2 * row.L, row.N, yb[0], yb[NS - 1]);
+        const void* xs = static_cast<const char*>(P.x) + row.x_off * (DT == 0 ? 4 : 2);
+        load4(xs, DT, j, row.N, ya[0]);
+        load4(xs, DT, j - 2 * row.L, row.N, yb[0]);
       }
-    } else {
-      const void* xs = static_cast<const char*>(P.x) + row.x_off * esz;
-      load_run<R>(xs, P.dtype, j0, row.N, ya[0]);
-      load_run<R>(xs, P.dtype, j0 - 2 * row.L, row.N, yb[0]);
+    };
+    // the same without bounds checks, for threads whose whole run (and trailing run) lies
+    // inside the signal with 16-byte (f32) / 8-byte (16-bit) aligned quads
+    auto load_quad_fast = [&](int64_t j, float (&ya)[NS][4], float (&yb)[NS][4]) {
+      if constexpr (VAR == kAdj) {
+        if constexpr (GAUSS) {
+          const float* g = static_cast<const float*>(P.x) + row.w_off;
+          ld4_rev_fast(g, row.N, j, ya[0]);
+          ld4_rev_fast(g, row.N, j - 2 * row.L, yb[0]);
+        } else {
+          const float2* g = static_cast<const float2*>(P.x) + row.w_off;
+          ld4c_rev_fast(g, row.N, j, ya[0], ya[NS - 1]);
+          ld4c_rev_fast(g, row.N, j - 2 * row.L, yb[0], yb[NS - 1]);
+        }
+      } else {
+        const void* xs = static_cast<const char*>(P.x) + row.x_off * (DT == 0 ? 4 : 2);
+        ld4_fast<DT>(xs, j, ya[0]);
+        ld4_fast<DT>(xs, j - 2 * row.L, yb[0]);
+      }
+    };
+    bool fast_in = (j0 - 2 * row.L >= 0) && (j0 + R <= row.N) && (j0 + R <= row.jend);
+    {
+      if constexpr (VAR == kAdj) {
+        const char* g = static_cast<const char*>(P.x) + row.w_off * (GAUSS ? 4 : 8);
+        const int64_t e = GAUSS ? 4 : 8;
+        fast_in = fast_in && ((reinterpret_cast<uintptr_t>(g + (row.N - j0 - R) * e) & 15) == 0) &&
+                  ((reinterpret_cast<uintptr_t>(g + (row.N - j0 + 2 * row.L - R) * e) & 15) == 0);
+      } else {
+        const char* xs = static_cast<const char*>(P.x) + row.x_off * (DT == 0 ? 4 : 2);
+        const uintptr_t m = DT == 0 ? 15 : 7;
+        const int64_t e = DT == 0 ? 4 : 2;
+        fast_in = fast_in && ((reinterpret_cast<uintptr_t>(xs + j0 * e) & m) == 0) &&
+                  ((reinterpret_cast<uintptr_t>(xs + (j0 - 2 * row.L) * e) & m) == 0);
+      }
     }
     const acc_t Dw = tab.scalar(lay.sD());
-    acc_t dy[NS][R];
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        dy[s][r] = (j0 + r < row.jend) ? (acc_t)ya[s][r] - Dw * (acc_t)yb[s][r] : (acc_t)0;
 
-    // 2. chunk sums. State i = s K + t: stream s, term t; with MOM, state K + t is the
-    //    alpha-derivative of state t: B_w = sum_r a^m ddy[r] - m a^m dy[r], m = R-1-r,
-    //    ddy = d dy / d alpha = 2L a^{2L} y[j-2L].
-    acc_t br[KS], bi[KS];
+    // 2. chunk sums: the recurrence run from a zero state over the thread's R positions,
+    //    B = sum_r a^{R-1-r} dy[r], in Horner form and in float64. Everything that propagates
+    //    along the row (chunk sums, wave scan, tile aggregates, carries) is float64, so float32
+    //    rounding never accumulates over the row; only the per-sample recurrence of step 5 is
+    //    float32 (one rounded carry, then R steps). On gfx950 a float64 FMA issues at the rate
+    //    of an unpacked float32 FMA.
+    //    State i = s K + t: stream s, term t; with MOM, state K + t is the alpha-derivative of
+    //    state t: w <- a (w - v) + ddy, ddy = d dy / d alpha = 2L a^{2L} y[j-2L].
+    double br[KS], bi[KS];
 #pragma unroll
     for (int i = 0; i < KS; ++i) { br[i] = 0; bi[i] = 0; }
+    {
+      const double Dd = tabd.scalar(lay.sD());
+      auto step1 = [&](int q, const float (&ya)[NS][4], const float (&yb)[NS][4]) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < 4; ++r) {
+          const bool in = j0 + 4 * q + r < row.jend;
+          const double ddy = (MOM && in) ? (double)(2 * row.L) * Dd * (double)yb[0][r] : 0.0;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
+          for (int s = 0; s < NS; ++s) {
+            const double dyd = in ? (double)ya[s][r] - Dd * (double)yb[s][r] : 0.0;
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-          br[s * K + t] = fma(tab.re(lay.eP1(r), t), dy[s][r], br[s * K + t]);
-          bi[s * K + t] = fma(tab.im(lay.eP1(r), t), dy[s][r], bi[s * K + t]);
+            for (int t = 0; t < K; ++t) {
+              const int i = s * K + t;
+              const double ar = tabd.re(lay.eA(), t), ai = tabd.im(lay.eA(), t);
+              const double pr = br[i], pi = bi[i];
+              br[i] = fma(ar, pr, fma(-ai, pi, dyd));
+              bi[i] = fma(ar, pi, ai * pr);
+              if (MOM && s == 0) {
+                const double wr = br[K + t] - pr, wi = bi[K + t] - pi;
+                br[K + t] = fma(ar, wr, fma(-ai, wi, ddy));
+                bi[K + t] = fma(ar, wi, ai * wr);
+              }
+            }
+          }
         }
-      }
-      if constexpr (MOM) {
-        const acc_t ddy = (j0 + r < row.jend) ? (acc_t)(2 * row.L) * Dw * (acc_t)yb[0][r] : (acc_t)0;
+      };
+      if (fast_in) {
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-          br[K + t] = fma(tab.re(lay.eP1(r), t), ddy, fma(-tab.re(mo + lay.eP1(r), t), dy[0][r], br[K + t]));
-          bi[K + t] = fma(tab.im(lay.eP1(r), t), ddy, fma(-tab.im(mo + lay.eP1(r), t), dy[0][r], bi[K + t]));
+        for (int q = 0; q < R / 4; ++q) {
+          float ya[NS][4], yb[NS][4];
+          load_quad_fast(j0 + 4 * q, ya, yb);
+          step1(q, ya, yb);
+        }
+      } else {
+#pragma unroll 1
+        for (int q = 0; q < R / 4; ++q) {
+          float ya[NS][4], yb[NS][4];
+          load_quad(j0 + 4 * q, ya, yb);
+          step1(q, ya, yb);
         }
       }
     }
@@ -168,19 +225,20 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
 #pragma unroll
     for (int d = 0; d < 6; ++d) {
       const int off = 1 << d;
-      acc_t ur[KS], ui[KS];
+      const bool take = lane >= off;
+      double ur[KS], ui[KS];
 #pragma unroll
-      for (int i = 0; i < KS; ++i) { ur[i] = __shfl_up(br[i], off, 64); ui[i] = __shfl_up(bi[i], off, 64); }
-      if (lane >= off) {
-#pragma unroll
-        for (int i = 0; i < KS; ++i) {
-          const int t = i % K;
-          cmac(br[i], bi[i], tab.re(lay.eTR(d), t), tab.im(lay.eTR(d), t), ur[i], ui[i]);
-          if (MOM && i >= K) cmac(br[i], bi[i], -tab.re(mo + lay.eTR(d), t), -tab.im(mo + lay.eTR(d), t), ur[t], ui[t]);
-        }
+      for (int i = 0; i < KS; ++i) {
+        const int t = i % K;
+        ur[i] = __shfl_up(br[i], off, 64);
+        ui[i] = __shfl_up(bi[i], off, 64);
+        ur[i] = take ? ur[i] : 0.0;
+        ui[i] = take ? ui[i] : 0.0;
+        cmac(br[i], bi[i], tabd.re(lay.eTR(d), t), tabd.im(lay.eTR(d), t), ur[i], ui[i]);
+        if (MOM && i >= K) cmac(br[i], bi[i], -tabd.re(mo + lay.eTR(d), t), -tabd.im(mo + lay.eTR(d), t), ur[t], ui[t]);
       }
     }
-    acc_t er[KS], ei[KS];
+    double er[KS], ei[KS];
 #pragma unroll
     for (int i = 0; i < KS; ++i) {
       er[i] = __shfl_up(br[i], 1, 64);
@@ -189,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
     }
     if (lane == 63) {
 #pragma unroll
-      for (int i = 0; i < KS; ++i) { s_wagg[wid][2 * i] = (double)br[i]; s_wagg[wid][2 * i + 1] = (double)bi[i]; }
+      for (int i = 0; i < KS; ++i) { s_wagg[wid][2 * i] = br[i]; s_wagg[wid][2 * i + 1] = bi[i]; }
     }
     __syncthreads();
 
@@ -300,60 +358,69 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
 #pragma unroll
       for (int i = 0; i < KS; ++i) {
         const int t = i % K;
-        vr[i] = er[i];
-        vi[i] = ei[i];
-        cmac(vr[i], vi[i], tab.re(lay.eLANE(lane), t), tab.im(lay.eLANE(lane), t), (acc_t)s_xw[wid][2 * i],
-             (acc_t)s_xw[wid][2 * i + 1]);
+        double cr = er[i], ci = ei[i];
+        cmac(cr, ci, tabd.re(lay.eLANE(lane), t), tabd.im(lay.eLANE(lane), t), s_xw[wid][2 * i], s_xw[wid][2 * i + 1]);
         if (MOM && i >= K)
-          cmac(vr[i], vi[i], -tab.re(mo + lay.eLANE(lane), t), -tab.im(mo + lay.eLANE(lane), t),
-               (acc_t)s_xw[wid][2 * t], (acc_t)s_xw[wid][2 * t + 1]);
+          cmac(cr, ci, -tabd.re(mo + lay.eLANE(lane), t), -tabd.im(mo + lay.eLANE(lane), t), s_xw[wid][2 * t],
+               s_xw[wid][2 * t + 1]);
+        vr[i] = (acc_t)cr;
+        vi[i] = (acc_t)ci;
       }
       const acc_t cx = tab.scalar(lay.sCX());
       const acc_t gre = tab.scalar(lay.sGre()), gim = tab.scalar(lay.sGim());
+      const int64_t nb = j0 - row.jout0;   // output index of the thread's first position
 
       if constexpr (VAR == kPg) {
-        // reductions against the cotangent at the output positions n = j - jout0
-        float gr[R], gi[R];
-        const int64_t n0v = j0 - row.jout0;
-        if constexpr (GAUSS) {
-          load_run_f32<R>(static_cast<const float*>(P.g) + row.w_off, n0v, row.N, gr);
-#pragma unroll
-          for (int r = 0; r < R; ++r) gi[r] = 0.f;
-        } else {
-          load_run_c<R>(static_cast<const float2*>(P.g) + row.w_off, n0v, row.N, gr, gi);
-        }
+        // reductions against the cotangent at the output positions n = j - jout0:
+        // S1_t = sum Re u Re v_t, S2_t = sum Im u Im v_t (S3, S4 the same for the alpha
+        // derivative states), Sx = sum Re u y[j-2L], Q = sum u (A - iB), u = conj(g) G
         acc_t sv_re[K], sv_im[K], sw_re[K], sw_im[K], s_xb = 0, q_re = 0, q_im = 0;
 #pragma unroll
         for (int t = 0; t < K; ++t) { sv_re[t] = 0; sv_im[t] = 0; sw_re[t] = 0; sw_im[t] = 0; }
+#pragma unroll 1
+        for (int q = 0; q < R / 4; ++q) {
+          float ya[NS][4], yb[NS][4], gr[4], gi[4];
+          load_quad(j0 + 4 * q, ya, yb);
+          if constexpr (GAUSS) {
+            load4_f32(static_cast<const float*>(P.g) + row.w_off, nb + 4 * q, row.N, gr);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          // u = conj(g) G (positions past the row read g = 0)
-          const acc_t ur = (acc_t)gr[r] * gre + (acc_t)gi[r] * gim;
-          const acc_t ui = (acc_t)gr[r] * gim - (acc_t)gi[r] * gre;
-          const acc_t ddy = MOM ? (acc_t)(2 * row.L) * Dw * (acc_t)yb[0][r] : (acc_t)0;
-          acc_t A = cx * (acc_t)yb[0][r], B = 0;
-#pragma unroll
-          for (int t = 0; t < K; ++t) {
-            const acc_t ar = tab.re(lay.eA(), t), ai = tab.im(lay.eA(), t);
-            const acc_t pr = vr[t], pi = vi[t];
-            const acc_t nr = fma(ar, pr, fma(-ai, pi, dy[0][r]));
-            const acc_t ni = fma(ar, pi, ai * pr);
-            vr[t] = nr; vi[t] = ni;
-            if constexpr (MOM) {   // w = a (w - v_prev) + ddy
-              const acc_t wr = vr[K + t] - pr, wi = vi[K + t] - pi;
-              vr[K + t] = fma(ar, wr, fma(-ai, wi, ddy));
-              vi[K + t] = fma(ar, wi, ai * wr);
-              sw_re[t] = fma(ur, vr[K + t], sw_re[t]);
-              sw_im[t] = fma(ui, vi[K + t], sw_im[t]);
-            }
-            sv_re[t] = fma(ur, nr, sv_re[t]);
-            sv_im[t] = fma(ui, ni, sv_im[t]);
-            A = fma(tab.row(lay.rMW(), t), nr, A);
-            if (!GAUSS) B = fma(tab.row(lay.rLW(), t), ni, B);
+            for (int r = 0; r < 4; ++r) gi[r] = 0.f;
+          } else {
+            load4_c(static_cast<const float2*>(P.g) + row.w_off, nb + 4 * q, row.N, gr, gi);
           }
-          s_xb = fma(ur, (acc_t)yb[0][r], s_xb);
-          q_re = fma(ur, A, fma(ui, B, q_re));
-          q_im = fma(ui, A, fma(-ur, B, q_im));
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const bool in = j0 + 4 * q + r < row.jend;
+            const acc_t dyr = in ? (acc_t)ya[0][r] - Dw * (acc_t)yb[0][r] : (acc_t)0;
+            const acc_t ybr = (acc_t)yb[0][r];
+            const acc_t ur = (acc_t)gr[r] * gre + (acc_t)gi[r] * gim;
+            const acc_t ui = (acc_t)gr[r] * gim - (acc_t)gi[r] * gre;
+            const acc_t ddy = (MOM && in) ? (acc_t)(2 * row.L) * Dw * ybr : (acc_t)0;
+            acc_t A = cx * ybr, B = 0;
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+              const acc_t ar = tab.re(lay.eA(), t), ai = tab.im(lay.eA(), t);
+              const acc_t pr = vr[t], pi = vi[t];
+              const acc_t nr = fma(ar, pr, fma(-ai, pi, dyr));
+              const acc_t ni = fma(ar, pi, ai * pr);
+              vr[t] = nr;
+              vi[t] = ni;
+              if constexpr (MOM) {   // w = a (w - v_prev) + ddy
+                const acc_t wr = vr[K + t] - pr, wi = vi[K + t] - pi;
+                vr[K + t] = fma(ar, wr, fma(-ai, wi, ddy));
+                vi[K + t] = fma(ar, wi, ai * wr);
+                sw_re[t] = fma(ur, vr[K + t], sw_re[t]);
+                sw_im[t] = fma(ui, vi[K + t], sw_im[t]);
+              }
+              sv_re[t] = fma(ur, nr, sv_re[t]);
+              sv_im[t] = fma(ui, ni, sv_im[t]);
+              A = fma(tab.row(lay.rMW(), t), nr, A);
+              if (!GAUSS) B = fma(tab.row(lay.rLW(), t), ni, B);
+            }
+            s_xb = fma(ur, ybr, s_xb);
+            q_re = fma(ur, A, fma(ui, B, q_re));
+            q_im = fma(ui, A, fma(-ur, B, q_im));
+          }
         }
         // block reduction of the 4K + 3 partial sums in float64, fixed order
         double red[NRED];
@@ -378,58 +445,86 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
           P.partials[(size_t)tile * NRED + tid] = sacc;
         }
       } else {
-        float* stg = &s_stage[(wid * 64 + lane) * LSTR];
+        // outputs n = j - jout0, stored straight from registers: complex64 pairs as 16-byte
+        // stores, reals in 16-byte groups, when aligned and in range
+        float2* W = static_cast<float2*>(P.out) + row.w_off;
+        float* Y = static_cast<float*>(P.out) + row.w_off;
+        auto step2 = [&](int q, const float (&ya)[NS][4], const float (&yb)[NS][4]) {
+          const int64_t nq = nb + 4 * q;
+          const bool full = nq >= 0 && nq + 4 <= row.N;
+          float o0[4], o1[4];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          acc_t A[NS], B[NS];
+          for (int r = 0; r < 4; ++r) {
+            const bool in = j0 + 4 * q + r < row.jend;
+            acc_t A[NS], B[NS];
 #pragma unroll
-          for (int s = 0; s < NS; ++s) { A[s] = cx * (acc_t)yb[s][r]; B[s] = 0; }
+            for (int s = 0; s < NS; ++s) {
+              const acc_t dyr = in ? (acc_t)ya[s][r] - Dw * (acc_t)yb[s][r] : (acc_t)0;
+              A[s] = cx * (acc_t)yb[s][r];
+              B[s] = 0;
 #pragma unroll
-          for (int s = 0; s < NS; ++s) {
-#pragma unroll
-            for (int t = 0; t < K; ++t) {
-              const int i = s * K + t;
-              const acc_t ar = tab.re(lay.eA(), t), ai = tab.im(lay.eA(), t);
-              const acc_t nr = fma(ar, vr[i], fma(-ai, vi[i], dy[s][r]));
-              const acc_t ni = fma(ar, vi[i], ai * vr[i]);
-              vr[i] = nr;
-              vi[i] = ni;
-              A[s] = fma(tab.row(lay.rMW(), t), nr, A[s]);
-              if (!GAUSS) B[s] = fma(tab.row(lay.rLW(), t), ni, B[s]);
+              for (int t = 0; t < K; ++t) {
+                const int i = s * K + t;
+                const acc_t ar = tab.re(lay.eA(), t), ai = tab.im(lay.eA(), t);
+                const acc_t nr = fma(ar, vr[i], fma(-ai, vi[i], dyr));
+                const acc_t ni = fma(ar, vi[i], ai * vr[i]);
+                vr[i] = nr;
+                vi[i] = ni;
+                A[s] = fma(tab.row(lay.rMW(), t), nr, A[s]);
+                if (!GAUSS) B[s] = fma(tab.row(lay.rLW(), t), ni, B[s]);
+              }
             }
-          }
-          if constexpr (VAR == kFwd) {
-            if (GAUSS) {
-              stg[r] = (float)(gre * A[0]);
+            if constexpr (VAR == kFwd && !GAUSS) {
+              o0[r] = (float)(gre * A[0] + gim * B[0]);
+              o1[r] = (float)(gim * A[0] - gre * B[0]);
+            } else if constexpr (VAR == kFwd || GAUSS) {
+              o0[r] = (float)(gre * A[0]);
             } else {
-              stg[2 * r] = (float)(gre * A[0] + gim * B[0]);
-              stg[2 * r + 1] = (float)(gim * A[0] - gre * B[0]);
+              // Re[conj(G) W_c(Re g')] - Im[conj(G) W_c(Im g')], W_c(y) = A(y) + i B(y)
+              o0[r] = (float)(gre * (A[0] - B[NS - 1]) + gim * (B[0] + A[NS - 1]));
             }
-          } else {
-            // Re[conj(G) W_c(Re g')] - Im[conj(G) W_c(Im g')], W_c(y) = A(y) + i B(y)
-            if (GAUSS) stg[r] = (float)(gre * A[0]);
-            else stg[r] = (float)(gre * (A[0] - B[NS - 1]) + gim * (B[0] + A[NS - 1]));
           }
-        }
-        __syncthreads();
-        const int64_t jw = jt + (int64_t)wid * 64 * R;
-        const float* sw = &s_stage[wid * 64 * LSTR];
-        if constexpr (VAR == kFwd && !GAUSS) {
-          float2* W = static_cast<float2*>(P.out) + row.w_off;
+          if constexpr (VAR == kFwd && !GAUSS) {
+            if (full && (reinterpret_cast<uintptr_t>(W + nq) & 15) == 0) {
+              *reinterpret_cast<float4*>(W + nq) = make_float4(o0[0], o1[0], o0[1], o1[1]);
+              *reinterpret_cast<float4*>(W + nq + 2) = make_float4(o0[2], o1[2], o0[3], o1[3]);
+            } else {
 #pragma unroll
-          for (int s = 0; s < R; ++s) {
-            const int e = s * 64 + lane;
-            const int64_t n = jw + e - row.jout0;
-            const float* q = sw + (e / R) * LSTR + 2 * (e % R);
-            if (n >= 0 && n < row.N) W[n] = make_float2(q[0], q[1]);
+              for (int r = 0; r < 4; ++r)
+                if (nq + r >= 0 && nq + r < row.N) W[nq + r] = make_float2(o0[r], o1[r]);
+            }
+          } else if constexpr (VAR == kFwd) {
+            if (full && (reinterpret_cast<uintptr_t>(Y + nq) & 15) == 0) {
+              *reinterpret_cast<float4*>(Y + nq) = make_float4(o0[0], o0[1], o0[2], o0[3]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (nq + r >= 0 && nq + r < row.N) Y[nq + r] = o0[r];
+            }
+          } else {   // adjoint: written time-reversed
+            float* Yr = Y + (row.N - 4 - nq);
+            if (full && (reinterpret_cast<uintptr_t>(Yr) & 15) == 0) {
+              *reinterpret_cast<float4*>(Yr) = make_float4(o0[3], o0[2], o0[1], o0[0]);
+            } else {
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                if (nq + r >= 0 && nq + r < row.N) Y[row.N - 1 - (nq + r)] = o0[r];
+            }
+          }
+        };
+        if (fast_in) {
+#pragma unroll
+          for (int q = 0; q < R / 4; ++q) {
+            float ya[NS][4], yb[NS][4];
+            load_quad_fast(j0 + 4 * q, ya, yb);
+            step2(q, ya, yb);
           }
         } else {
-          float* y = static_cast<float*>(P.out) + row.w_off;
-#pragma unroll
-          for (int s = 0; s < R; ++s) {
-            const int e = s * 64 + lane;
-            const int64_t n = jw + e - row.jout0;
-            if (n >= 0 && n < row.N) y[VAR == kAdj ? row.N - 1 - n : n] = sw[(e / R) * LSTR + (e % R)];
+#pragma unroll 1
+          for (int q = 0; q < R / 4; ++q) {
+            float ya[NS][4], yb[NS][4];
+            load_quad(j0 + 4 * q, ya, yb);
+            step2(q, ya, yb);
           }
         }
       }
@@ -456,12 +551,15 @@ using KernelFn = void (*)(ScanLaunch);
 
 // One instantiation set per K, defined in scan_k<K>.hip.
 template <int K, int R>
-KernelFn pick_scan(int var, int wide, int gauss, int mom) {
-#define MK_PICK(V, W, G, M) \
-  if (var == V && wide == W && gauss == G && mom == M) return (KernelFn)scan_kernel<V, K, R, W, G, M>;
-  MK_PICK(kFwd, 0, 0, 0) MK_PICK(kFwd, 0, 1, 0) MK_PICK(kFwd, 1, 0, 0) MK_PICK(kFwd, 1, 1, 0)
-  MK_PICK(kAdj, 0, 0, 0) MK_PICK(kAdj, 0, 1, 0) MK_PICK(kAdj, 1, 0, 0) MK_PICK(kAdj, 1, 1, 0)
-  MK_PICK(kPg, 1, 0, 0) MK_PICK(kPg, 1, 1, 0) MK_PICK(kPg, 1, 0, 1) MK_PICK(kPg, 1, 1, 1)
+KernelFn pick_scan(int var, int wide, int gauss, int mom, int dt) {
+  static_assert(R % 4 == 0, "R must be a multiple of 4");
+#define MK_PICK(V, W, G, M, D) \
+  if (var == V && wide == W && gauss == G && mom == M && dt == D) return (KernelFn)scan_kernel<V, K, R, W, G, M, D>;
+#define MK_PICK_DT(V, W, G, M) MK_PICK(V, W, G, M, 0) MK_PICK(V, W, G, M, 1) MK_PICK(V, W, G, M, 2)
+  MK_PICK_DT(kFwd, 0, 0, 0) MK_PICK_DT(kFwd, 0, 1, 0) MK_PICK_DT(kFwd, 1, 0, 0) MK_PICK_DT(kFwd, 1, 1, 0)
+  MK_PICK(kAdj, 0, 0, 0, 0) MK_PICK(kAdj, 0, 1, 0, 0) MK_PICK(kAdj, 1, 0, 0, 0) MK_PICK(kAdj, 1, 1, 0, 0)
+  MK_PICK_DT(kPg, 1, 0, 0) MK_PICK_DT(kPg, 1, 1, 0) MK_PICK_DT(kPg, 1, 0, 1) MK_PICK_DT(kPg, 1, 1, 1)
+#undef MK_PICK_DT
 #undef MK_PICK
   return nullptr;
 }
