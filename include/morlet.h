@@ -191,6 +191,15 @@ morlet_status morlet_scalogram_backward(morlet_plan_t plan, const void* x_packed
                                         const void* gW_packed, float* gx_packed, double* gparams, void* ws,
                                         size_t ws_bytes, void* stream);
 
+/* Baseline for comparison (Sec. V-B, the "conventional method"): the truncated direct
+ * convolution W[n] = sum_{|k|<=H} psi[k] x[n-k] with the exact Morlet taps of the plan's
+ * sigma and xi (not the K-term fit), H = half_width (0 = the plan's L; the paper's method
+ * uses H = ceil(3 sigma)). W complex64 [N] (device). O(N H) work. The first call for a given
+ * H allocates and uploads the taps (synchronously); later calls allocate nothing. Needs a
+ * single-signal Morlet plan. */
+morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W,
+                                    int64_t half_width, void* stream);
+
 /* Destroy a plan (NULL is ignored). Not stream-ordered: no call using it may be pending. */
 void morlet_destroy(morlet_plan_t plan);
 

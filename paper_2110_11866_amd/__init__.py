@@ -120,6 +120,16 @@ class MorletPlan(_PlanBase):
                             w.numel(), _stream())
         return out
 
+    def direct(self, x: torch.Tensor, half_width: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Baseline: truncated direct convolution with the exact wavelet on [-H, H]
+        (H = half_width, 0 = the plan's L)."""
+        self._check_x(x)
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.complex64, device=x.device)
+        _abi.morlet_direct_forward(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(),
+                                   int(half_width), _stream())
+        return out
+
     def backward(self, x: torch.Tensor | None, gW: torch.Tensor, want_params: bool = True):
         """(dLoss/dx float32 [N], [dLoss/dsigma, dLoss/dxi] float64 or None) for the cotangent
         gW = dLoss/dRe W + i dLoss/dIm W (complex64 [N])."""

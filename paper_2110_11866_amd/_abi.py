@@ -43,6 +43,7 @@ SIGNATURES = {
     "morlet_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "gauss_smooth_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "morlet_scalogram_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "morlet_direct_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _i64, _vp]),
     "morlet_destroy": (None, [_vp]),
     "morlet_last_error": (ctypes.c_char_p, []),
 }
@@ -167,6 +168,10 @@ def gauss_smooth_backward(plan, x_ptr, dtype, gy_ptr, gx_ptr, gparams_ptr, ws_pt
 def morlet_scalogram_backward(plan, x_ptr, dtype, gW_ptr, gx_ptr, gparams_ptr, ws_ptr, ws_bytes, stream) -> None:
     check(lib().morlet_scalogram_backward(plan, x_ptr, dtype, gW_ptr, gx_ptr, gparams_ptr, ws_ptr, ws_bytes,
                                           stream))
+
+
+def morlet_direct_forward(plan, x_ptr, dtype, W_ptr, half_width, stream) -> None:
+    check(lib().morlet_direct_forward(plan, x_ptr, dtype, W_ptr, half_width, stream))
 
 
 def morlet_destroy(plan: int) -> None:

@@ -18,7 +18,7 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
 
 HOST_SOURCES = ["plan.cpp", "api.cpp"]
-DEVICE_SOURCES = ["scan_dispatch.hip"] + ["scan_k%d.hip" % k for k in range(1, 13)]
+DEVICE_SOURCES = ["scan_dispatch.hip", "direct_conv.hip"] + ["scan_k%d.hip" % k for k in range(1, 13)]
 
 
 def _compile(src: str) -> str:

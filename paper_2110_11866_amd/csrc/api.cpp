@@ -546,6 +546,7 @@ void morlet_destroy(morlet_plan_t plan) {
   if (!plan) return;
   if (plan->d_tab) (void)hipFree(plan->d_tab);
   if (plan->d_rows) (void)hipFree(plan->d_rows);
+  if (plan->d_direct) (void)hipFree(plan->d_direct);
   delete plan;
 }
 
@@ -569,6 +570,38 @@ morlet_status morlet_scalogram_backward(morlet_plan_t plan, const void* x_packed
                                         const void* gW_packed, float* gx_packed, double* gparams, void* ws,
                                         size_t ws_bytes, void* stream) {
   return run_backward(plan, x_packed, (int)dtype, gW_packed, gx_packed, gparams, ws, ws_bytes, stream, 0, true);
+}
+
+morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W,
+                                    int64_t half_width, void* stream) {
+  if (!plan || plan->batched || plan->kind != 0) return fail(MORLET_ERR_INVALID_ARG, "needs a single-signal Morlet plan");
+  if ((int)dtype < 0 || (int)dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  if (half_width < 0 || half_width > ((int64_t)1 << 30)) return fail(MORLET_ERR_INVALID_ARG, "bad half width");
+  if (plan->N == 0) return MORLET_OK;
+  if (!x || !W) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  const int64_t H = half_width ? half_width : plan->L;
+  if (plan->direct_H != H) {
+    std::vector<double> re, im;
+    mk::morlet_taps(plan->sigma, plan->xi, H, re, im);
+    std::vector<float> h(2 * (2 * H + 1));
+    for (int64_t k = 0; k < 2 * H + 1; ++k) { h[2 * k] = (float)re[k]; h[2 * k + 1] = (float)im[k]; }
+    if (plan->d_direct) { (void)hipFree(plan->d_direct); plan->d_direct = nullptr; }
+    if (hipMalloc(&plan->d_direct, h.size() * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      plan->d_direct = nullptr;
+      plan->direct_H = -1;
+      return fail(MORLET_ERR_ALLOC, "hipMalloc of the direct taps failed");
+    }
+    if (hipMemcpy(plan->d_direct, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MORLET_ERR_HIP, "hipMemcpy of the direct taps failed");
+    }
+    plan->direct_H = H;
+  }
+  const hipError_t e = mk::launch_direct_conv(x, (int)dtype, plan->N, static_cast<const float2*>(plan->d_direct), H,
+                                              static_cast<float2*>(W), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
 }
 
 const char* morlet_last_error(void) { return g_err.c_str(); }

@@ -37,6 +37,10 @@ hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* gparams,
 hipError_t launch_sum_scales(const float* part, float* out, const Row* rows, int B, int S, int64_t total,
                              hipStream_t s);
 
+// Truncated direct convolution with exact taps h[k], k in [-H, H] (the benchmark's baseline).
+hipError_t launch_direct_conv(const void* x, int dtype, int64_t N, const float2* taps, int64_t H, float2* W,
+                              hipStream_t s);
+
 hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s);
 // Resident blocks per CU of the forward kernel for this configuration (0 if unsupported).
 int scan_forward_occupancy(int K, int R, int wide, int kind);

@@ -46,6 +46,9 @@ struct morlet_plan_s {
   int64_t ntiles = 0, ntiles_max = 0;
   void* d_rows = nullptr;                  // device rows followed by tile_row
   size_t rows_bytes = 0;
+  // exact taps of the direct-convolution baseline (uploaded on its first call)
+  void* d_direct = nullptr;
+  int64_t direct_H = -1;
 };
 
 namespace mk {
