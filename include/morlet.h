@@ -195,8 +195,9 @@ morlet_status morlet_scalogram_backward(morlet_plan_t plan, const void* x_packed
  * convolution W[n] = sum_{|k|<=H} psi[k] x[n-k] with the exact Morlet taps of the plan's
  * sigma and xi (not the K-term fit), H = half_width (0 = the plan's L; the paper's method
  * uses H = ceil(3 sigma)). W complex64 [N] (device). O(N H) work. The first call for a given
- * H allocates and uploads the taps (synchronously); later calls allocate nothing. Needs a
- * single-signal Morlet plan. */
+ * H allocates and uploads the taps (synchronously), plus a partial-output buffer of up to 64 N
+ * complex64 when the taps are split into slabs to fill the device (few outputs, many taps);
+ * later calls allocate nothing. Needs a single-signal Morlet plan. */
 morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W,
                                     int64_t half_width, void* stream);
 

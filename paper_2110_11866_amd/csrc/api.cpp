@@ -580,16 +580,20 @@ morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dt
   if (plan->N == 0) return MORLET_OK;
   if (!x || !W) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
   const int64_t H = half_width ? half_width : plan->L;
+  const int slabs = mk::direct_conv_slabs(plan->N, H, plan->num_cus);
+  const size_t tap_bytes = ((size_t)(2 * H + 1) * 8 + 255) / 256 * 256;
   if (plan->direct_H != H) {
     std::vector<double> re, im;
     mk::morlet_taps(plan->sigma, plan->xi, H, re, im);
     std::vector<float> h(2 * (2 * H + 1));
     for (int64_t k = 0; k < 2 * H + 1; ++k) { h[2 * k] = (float)re[k]; h[2 * k + 1] = (float)im[k]; }
     if (plan->d_direct) { (void)hipFree(plan->d_direct); plan->d_direct = nullptr; }
-    if (hipMalloc(&plan->d_direct, h.size() * sizeof(float)) != hipSuccess) {
+    plan->direct_H = -1;
+    // taps, then the slab partials (slabs x N complex64) when the taps are split
+    const size_t bytes = tap_bytes + (slabs > 1 ? (size_t)slabs * (size_t)plan->N * 8 : 0);
+    if (hipMalloc(&plan->d_direct, bytes) != hipSuccess) {
       (void)hipGetLastError();
       plan->d_direct = nullptr;
-      plan->direct_H = -1;
       return fail(MORLET_ERR_ALLOC, "hipMalloc of the direct taps failed");
     }
     if (hipMemcpy(plan->d_direct, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
@@ -598,8 +602,9 @@ morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dt
     }
     plan->direct_H = H;
   }
+  float2* part = reinterpret_cast<float2*>(static_cast<char*>(plan->d_direct) + tap_bytes);
   const hipError_t e = mk::launch_direct_conv(x, (int)dtype, plan->N, static_cast<const float2*>(plan->d_direct), H,
-                                              static_cast<float2*>(W), static_cast<hipStream_t>(stream));
+                                              slabs, part, static_cast<float2*>(W), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return MORLET_OK;
 }

@@ -2,10 +2,12 @@
 // exact complex taps h (the conventional method of Sec. V-B uses H = 3 sigma), x zero outside
 // [0, N). Not part of the SFT/ASFT path: it is the comparison the benchmark times.
 //
-// One block computes 256 x 4 consecutive outputs; the taps are swept in chunks of 1024 staged
-// in LDS together with the signal segment they touch. Each thread keeps a sliding window of
-// four signal samples in registers, so a tap costs one broadcast tap read, a quarter of a
-// 16-byte signal read and 8 FMAs.
+// One block computes 256 x 4 consecutive outputs over one slab of the taps; the slab's taps
+// are swept in chunks of 1024 staged in LDS together with the signal segment they touch. Each
+// thread keeps a sliding window of four signal samples in registers, so a tap costs one
+// broadcast tap read, a quarter of a signal read and 8 FMAs. With several slabs (short
+// signals, long windows: too few output blocks to fill the chip) each slab writes a partial
+// output and a second kernel adds the slabs in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,20 +29,25 @@ __device__ __forceinline__ float dc_load(const void* x, int dtype, int64_t i, in
   return dtype == 1 ? (float)__builtin_bit_cast(_Float16, h) : __uint_as_float((uint32_t)h << 16);
 }
 
+// slab blockIdx.y covers tap chunks [y cps, min((y + 1) cps, nchunks)); its partial goes to
+// out + y N
 __global__ __launch_bounds__(kDcThreads) void direct_conv_kernel(const void* x, int dtype, int64_t N,
-                                                                  const float2* taps, int64_t H, float2* W) {
-  // seg[s] = x[nb - k0 - kDcChunk + s], s in [0, kDcTile + kDcChunk + 3)
+                                                                  const float2* taps, int64_t H, int64_t cps,
+                                                                  float2* out) {
+  // seg[s] = x[nb - k0 - kDcChunk + 1 + s], s in [0, kDcTile + kDcChunk + 4)
   __shared__ float seg[kDcTile + kDcChunk + 4];
   __shared__ float2 tp[kDcChunk];
   const int tid = threadIdx.x;
   const int64_t nb = (int64_t)blockIdx.x * kDcTile;
   const int64_t ntaps = 2 * H + 1;
+  const int64_t c_lo = (int64_t)blockIdx.y * cps * kDcChunk;
+  const int64_t c_hi = std::min<int64_t>(ntaps, c_lo + cps * kDcChunk);
   float accr[kDcOut], acci[kDcOut];
 #pragma unroll
   for (int i = 0; i < kDcOut; ++i) { accr[i] = 0.f; acci[i] = 0.f; }
-  for (int64_t c0 = 0; c0 < ntaps; c0 += kDcChunk) {
+  for (int64_t c0 = c_lo; c0 < c_hi; c0 += kDcChunk) {
     const int64_t k0 = c0 - H;                     // first tap offset k of this chunk
-    const int nt = (int)std::min<int64_t>(kDcChunk, ntaps - c0);
+    const int nt = (int)std::min<int64_t>(kDcChunk, c_hi - c0);
     __syncthreads();
     for (int s = tid; s < kDcChunk; s += kDcThreads) tp[s] = s < nt ? taps[c0 + s] : make_float2(0.f, 0.f);
     const int64_t base = nb - k0 - kDcChunk + 1;   // x index of seg[0]
@@ -63,6 +70,7 @@ __global__ __launch_bounds__(kDcThreads) void direct_conv_kernel(const void* x, 
       if (t + 1 < nt) win[0] = seg[o + kDcChunk - 2 - t];
     }
   }
+  float2* W = out + (int64_t)blockIdx.y * N;
 #pragma unroll
   for (int i = 0; i < kDcOut; ++i) {
     const int64_t n = nb + kDcOut * tid + i;
@@ -70,13 +78,41 @@ __global__ __launch_bounds__(kDcThreads) void direct_conv_kernel(const void* x, 
   }
 }
 
+__global__ __launch_bounds__(256) void direct_sum_kernel(const float2* part, int slabs, int64_t N, float2* W) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += stride) {
+    float2 a = part[n];
+    for (int s = 1; s < slabs; ++s) {
+      const float2 b = part[(int64_t)s * N + n];
+      a.x += b.x;
+      a.y += b.y;
+    }
+    W[n] = a;
+  }
+}
+
 }  // namespace
 
-hipError_t launch_direct_conv(const void* x, int dtype, int64_t N, const float2* taps, int64_t H, float2* W,
-                              hipStream_t s) {
+int direct_conv_slabs(int64_t N, int64_t H, int num_cus) {
+  const int64_t blocks = (N + kDcTile - 1) / kDcTile;
+  const int64_t nchunks = (2 * H + 1 + kDcChunk - 1) / kDcChunk;
+  const int64_t want = (4 * (int64_t)num_cus + blocks - 1) / std::max<int64_t>(blocks, 1);
+  return (int)std::max<int64_t>(1, std::min<int64_t>({want, nchunks, 64}));
+}
+
+hipError_t launch_direct_conv(const void* x, int dtype, int64_t N, const float2* taps, int64_t H, int slabs,
+                              float2* part, float2* W, hipStream_t s) {
   if (N <= 0) return hipSuccess;
   const int64_t blocks = (N + kDcTile - 1) / kDcTile;
-  hipLaunchKernelGGL(direct_conv_kernel, dim3((unsigned)blocks), dim3(kDcThreads), 0, s, x, dtype, N, taps, H, W);
+  const int64_t nchunks = (2 * H + 1 + kDcChunk - 1) / kDcChunk;
+  const int64_t cps = (nchunks + slabs - 1) / slabs;
+  const int used = (int)((nchunks + cps - 1) / cps);   // slabs that hold at least one chunk
+  hipLaunchKernelGGL(direct_conv_kernel, dim3((unsigned)blocks, (unsigned)used), dim3(kDcThreads), 0, s, x, dtype, N,
+                     taps, H, cps, used > 1 ? part : W);
+  if (used > 1) {
+    const unsigned sb = (unsigned)std::min<int64_t>((N + 255) / 256, 4096);
+    hipLaunchKernelGGL(direct_sum_kernel, dim3(sb), dim3(256), 0, s, part, used, N, W);
+  }
   return hipGetLastError();
 }
 

@@ -38,8 +38,11 @@ hipError_t launch_sum_scales(const float* part, float* out, const Row* rows, int
                              hipStream_t s);
 
 // Truncated direct convolution with exact taps h[k], k in [-H, H] (the benchmark's baseline).
-hipError_t launch_direct_conv(const void* x, int dtype, int64_t N, const float2* taps, int64_t H, float2* W,
-                              hipStream_t s);
+// Number of tap slabs for N outputs and half width H on a device with num_cus compute units;
+// with more than one slab the launch needs a partial buffer of slabs x N complex64.
+int direct_conv_slabs(int64_t N, int64_t H, int num_cus);
+hipError_t launch_direct_conv(const void* x, int dtype, int64_t N, const float2* taps, int64_t H, int slabs,
+                              float2* part, float2* W, hipStream_t s);
 
 hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s);
 // Resident blocks per CU of the forward kernel for this configuration (0 if unsupported).

@@ -40,9 +40,10 @@
 //      group's last tile, gathered one predecessor per lane and summed by a fixed butterfly
 //      (agent-scope atomics that bypass the per-XCD L2, so tiles on different XCDs see each
 //      other's states);
-//   5. each thread rotates its carry in, runs the R-step recurrence and writes its R
-//      outputs straight from registers as 16-byte stores (kFwd, kAdj), or reduces them per
-//      tile into float64 partials (kPg).
+//   5. each thread rotates its carry in and runs the R-step recurrence; its R outputs go to
+//      an LDS stage from which the wave writes its 64 R consecutive outputs with consecutive
+//      lanes on consecutive 16-byte words (kFwd, kAdj), or they are reduced per tile into
+//      float64 partials (kPg).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -56,6 +57,10 @@ namespace {
 
 enum { kFwd = 0, kAdj = 1, kPg = 2 };
 
+// four floats as a clang vector (what the nontemporal-store builtin takes); outputs are
+// written once and never re-read by the kernel, so they bypass the cache hierarchy's reuse
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // complex multiply-add helpers on (re, im) pairs
 template <typename T>
 __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  // z += c x
@@ -64,7 +69,7 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
 }
 
 template <int VAR, int K, int R, bool WIDE, bool GAUSS, bool MOM, int DT>
-__global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR == kFwd && !WIDE) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
   using acc_t = typename std::conditional<WIDE, double, float>::type;
   constexpr int T = R * kThreads;
   constexpr int NS = (VAR == kAdj && !GAUSS) ? 2 : 1;   // real input streams
@@ -78,6 +83,12 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
   __shared__ double s_e[kWaves][2 * KS];
   __shared__ double s_p[2 * KS];
   __shared__ double s_red[(VAR == kPg) ? kWaves * NRED : 1];
+  // output stage: per wave 64 threads x kSub outputs, each thread's sub-run padded by 16 bytes
+  constexpr bool kCplxOut = VAR == kFwd && !GAUSS;
+  constexpr int kSub = 16;                                  // positions per thread per store round
+  static_assert(R % kSub == 0, "R must be a multiple of the store sub-run");
+  constexpr int kStride = kSub * (kCplxOut ? 2 : 1) + 4;   // floats per thread
+  __shared__ __align__(16) float s_out[kWaves][(VAR == kPg) ? 4 : 64 * kStride];
 
   WsHeader* hdr = static_cast<WsHeader*>(P.ws);
   unsigned char* states = static_cast<unsigned char*>(P.ws) + sizeof(WsHeader);
@@ -445,13 +456,13 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
           P.partials[(size_t)tile * NRED + tid] = sacc;
         }
       } else {
-        // outputs n = j - jout0, stored straight from registers: complex64 pairs as 16-byte
-        // stores, reals in 16-byte groups, when aligned and in range
-        float2* W = static_cast<float2*>(P.out) + row.w_off;
-        float* Y = static_cast<float*>(P.out) + row.w_off;
+        // outputs n = j - jout0, in sub-runs of kSub positions per thread: each thread writes
+        // a sub-run to the wave's LDS stage, then the wave stores the 64 sub-runs with
+        // consecutive lanes on consecutive 16-byte words (every line written whole by one
+        // instruction), instead of each lane writing its own run R positions from its
+        // neighbour's
+        float* stg = &s_out[wid][0] + lane * kStride;
         auto step2 = [&](int q, const float (&ya)[NS][4], const float (&yb)[NS][4]) {
-          const int64_t nq = nb + 4 * q;
-          const bool full = nq >= 0 && nq + 4 <= row.N;
           float o0[4], o1[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -484,48 +495,84 @@ __global__ __launch_bounds__(kThreads) void scan_kernel(ScanLaunch P) {
               o0[r] = (float)(gre * (A[0] - B[NS - 1]) + gim * (B[0] + A[NS - 1]));
             }
           }
-          if constexpr (VAR == kFwd && !GAUSS) {
-            if (full && (reinterpret_cast<uintptr_t>(W + nq) & 15) == 0) {
-              *reinterpret_cast<float4*>(W + nq) = make_float4(o0[0], o1[0], o0[1], o1[1]);
-              *reinterpret_cast<float4*>(W + nq + 2) = make_float4(o0[2], o1[2], o0[3], o1[3]);
-            } else {
-#pragma unroll
-              for (int r = 0; r < 4; ++r)
-                if (nq + r >= 0 && nq + r < row.N) W[nq + r] = make_float2(o0[r], o1[r]);
-            }
-          } else if constexpr (VAR == kFwd) {
-            if (full && (reinterpret_cast<uintptr_t>(Y + nq) & 15) == 0) {
-              *reinterpret_cast<float4*>(Y + nq) = make_float4(o0[0], o0[1], o0[2], o0[3]);
-            } else {
-#pragma unroll
-              for (int r = 0; r < 4; ++r)
-                if (nq + r >= 0 && nq + r < row.N) Y[nq + r] = o0[r];
-            }
-          } else {   // adjoint: written time-reversed
-            float* Yr = Y + (row.N - 4 - nq);
-            if (full && (reinterpret_cast<uintptr_t>(Yr) & 15) == 0) {
-              *reinterpret_cast<float4*>(Yr) = make_float4(o0[3], o0[2], o0[1], o0[0]);
-            } else {
-#pragma unroll
-              for (int r = 0; r < 4; ++r)
-                if (nq + r >= 0 && nq + r < row.N) Y[row.N - 1 - (nq + r)] = o0[r];
-            }
+          const int qs = q % (kSub / 4);
+          if constexpr (kCplxOut) {
+            *reinterpret_cast<float4*>(stg + 8 * qs) = make_float4(o0[0], o1[0], o0[1], o1[1]);
+            *reinterpret_cast<float4*>(stg + 8 * qs + 4) = make_float4(o0[2], o1[2], o0[3], o1[3]);
+          } else {
+            *reinterpret_cast<float4*>(stg + 4 * qs) = make_float4(o0[0], o0[1], o0[2], o0[3]);
           }
         };
-        if (fast_in) {
+        // store sub-run u: element e (0 <= e < 64 kSub) is lane e / kSub's position
+        // kSub u + e % kSub, output nw + (e / kSub) R + kSub u + e % kSub
+        auto flush = [&](int u) {
+          wave_lds_sync();
+          const float* sw = &s_out[wid][0];
+          const int64_t nw = jt + (int64_t)wid * 64 * R - row.jout0;   // output of the wave's first position
+          const bool whole = nw >= 0 && nw + 64 * R <= row.N;
+          auto nof = [&](int e) { return nw + (int64_t)(e / kSub) * R + kSub * u + (e % kSub); };
+          auto at = [&](int e) { return sw + (e / kSub) * kStride + (e % kSub) * (kCplxOut ? 2 : 1); };
+          if constexpr (VAR == kFwd && !GAUSS) {
+            float2* W = static_cast<float2*>(P.out) + row.w_off;
+            if (whole && (reinterpret_cast<uintptr_t>(W + nw) & 15) == 0) {
 #pragma unroll
-          for (int q = 0; q < R / 4; ++q) {
-            float ya[NS][4], yb[NS][4];
-            load_quad_fast(j0 + 4 * q, ya, yb);
-            step2(q, ya, yb);
-          }
-        } else {
+              for (int i = 0; i < kSub / 2; ++i) {
+                const int e = 2 * lane + 128 * i;
+                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(at(e)), reinterpret_cast<v4f*>(W + nof(e)));
+              }
+            } else {
 #pragma unroll 1
-          for (int q = 0; q < R / 4; ++q) {
-            float ya[NS][4], yb[NS][4];
-            load_quad(j0 + 4 * q, ya, yb);
-            step2(q, ya, yb);
+              for (int i = 0; i < kSub; ++i) {
+                const int e = lane + 64 * i;
+                const int64_t n = nof(e);
+                if (n >= 0 && n < row.N) W[n] = *reinterpret_cast<const float2*>(at(e));
+              }
+            }
+          } else {
+            float* Y = static_cast<float*>(P.out) + row.w_off;
+            // forward (Gaussian): Y[n]; adjoint: written time-reversed, Y[N - 1 - n]
+            constexpr bool rev = VAR == kAdj;
+            if (whole && (reinterpret_cast<uintptr_t>(rev ? Y + (row.N - 4 - nw) : Y + nw) & 15) == 0) {
+#pragma unroll
+              for (int i = 0; i < kSub / 4; ++i) {
+                const int e = 4 * lane + 256 * i;
+                const int64_t n = nof(e);
+                const v4f v = *reinterpret_cast<const v4f*>(at(e));
+                if constexpr (rev) __builtin_nontemporal_store(v.wzyx, reinterpret_cast<v4f*>(Y + (row.N - 4 - n)));
+                else __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(Y + n));
+              }
+            } else {
+#pragma unroll 1
+              for (int i = 0; i < kSub; ++i) {
+                const int e = lane + 64 * i;
+                const int64_t n = nof(e);
+                if (n >= 0 && n < row.N) Y[rev ? row.N - 1 - n : n] = *at(e);
+              }
+            }
           }
+          // the next sub-run's stage writes stay behind this one's reads
+          __builtin_amdgcn_wave_barrier();
+        };
+        // fast_in differs between the lanes of a wave, so each sub-run's quads run on either
+        // path and the wave reconverges before the cooperative store
+#pragma unroll
+        for (int u = 0; u < R / kSub; ++u) {
+          if (fast_in) {
+#pragma unroll
+            for (int q = u * (kSub / 4); q < (u + 1) * (kSub / 4); ++q) {
+              float ya[NS][4], yb[NS][4];
+              load_quad_fast(j0 + 4 * q, ya, yb);
+              step2(q, ya, yb);
+            }
+          } else {
+#pragma unroll 1
+            for (int q = u * (kSub / 4); q < (u + 1) * (kSub / 4); ++q) {
+              float ya[NS][4], yb[NS][4];
+              load_quad(j0 + 4 * q, ya, yb);
+              step2(q, ya, yb);
+            }
+          }
+          flush(u);
         }
       }
     } else if constexpr (VAR == kPg) {

@@ -39,16 +39,16 @@ def _oracle_plan(kind, sigma, K, info, mode):
     return O.plan_gauss(sigma, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None)
 
 
-CASES = [(1024, 16.0, 4, 64), (50000, 300.0, 6, 1200), (9000, 40.0, 5, 0)]
+CASES = [(1024, 16.0, 4, 64, 16), (50000, 300.0, 6, 1200, 16), (9000, 40.0, 5, 0, 16), (70001, 300.0, 5, 1200, 32)]
 
 
 @pytest.mark.parametrize("accum", ["f32", "compensated"])
 @pytest.mark.parametrize("mode", ["sft", "asft"])
 @pytest.mark.parametrize("kind", ["morlet", "gauss"])
-@pytest.mark.parametrize("N,sigma,K,L", CASES)
-def test_backward_matches_oracle(N, sigma, K, L, kind, mode, accum):
+@pytest.mark.parametrize("N,sigma,K,L,tile", CASES)
+def test_backward_matches_oracle(N, sigma, K, L, tile, kind, mode, accum):
     import paper_2110_11866_amd as M
-    _announce("backward", N, sigma, K, L, kind, mode, accum)
+    _announce("backward", N, sigma, K, L, tile, kind, mode, accum)
     rng = np.random.default_rng(N + K + len(mode))
     x = rng.standard_normal(N).astype(np.float32)
     xt = torch.from_numpy(x).cuda()
@@ -60,6 +60,7 @@ def test_backward_matches_oracle(N, sigma, K, L, kind, mode, accum):
     else:
         plan = M.GaussPlan(N, sigma, K, L, mode=mode, accum=accum)
         g = torch.from_numpy(rng.standard_normal(N).astype(np.float32)).cuda()
+    plan.set_tile(tile)
     gx, gp = plan.backward(xt, g)
     torch.cuda.synchronize()
     info = plan.info()

@@ -33,7 +33,8 @@ def _announce(*args):
     sys.stdout.flush()
 
 
-def run_gpu(x32, kind, sigma, K, L, mode="sft", n0=0, accum="f32", dtype=torch.float32, xi=None, repeats=1):
+def run_gpu(x32, kind, sigma, K, L, mode="sft", n0=0, accum="f32", dtype=torch.float32, xi=None, repeats=1,
+            tile=16):
     import paper_2110_11866_amd as M
     N = len(x32)
     xt = torch.from_numpy(np.ascontiguousarray(x32)).to("cuda").to(dtype)
@@ -41,6 +42,7 @@ def run_gpu(x32, kind, sigma, K, L, mode="sft", n0=0, accum="f32", dtype=torch.f
         plan = M.MorletPlan(N, sigma, xi if xi is not None else 6.0 / sigma, K, L, mode=mode, n0=n0, accum=accum)
     else:
         plan = M.GaussPlan(N, sigma, K, L, mode=mode, n0=n0, accum=accum)
+    plan.set_tile(tile)
     outs = []
     for _ in range(repeats):
         outs.append(plan.forward(xt).cpu().numpy())
@@ -171,3 +173,17 @@ def test_direct_convolution_baseline(N, sigma, H, dtype):
     torch.cuda.synchronize()
     want = O.forward_direct(xt.double().cpu().numpy(), sigma, 6.0 / sigma, H if H else plan.info()["L"])
     assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
+
+
+@pytest.mark.parametrize("mode,accum", MODES)
+@pytest.mark.parametrize("kind", ["morlet", "gauss"])
+@pytest.mark.parametrize("N,sigma,K,L,dtype", [(50000, 300.0, 6, 1200, torch.float32),
+                                               (77777, 2000.0, 3, 8000, torch.bfloat16),
+                                               (9000, 1.5, 12, 12, torch.float16)])
+def test_tile32_parity(N, sigma, K, L, dtype, kind, mode, accum):
+    # 32 positions per thread (8192-position tiles, two store sub-runs per thread)
+    _announce("tile32", N, sigma, K, L, dtype, kind, mode, accum)
+    x = np.random.default_rng(N + K).standard_normal(N).astype(np.float32)
+    (got,), info, xu = run_gpu(x, kind, sigma, K, L, mode=mode, accum=accum, dtype=dtype, tile=32)
+    want, _ = oracle_of(xu, kind, sigma, K, L, info, mode)
+    assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
