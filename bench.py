@@ -40,6 +40,8 @@ def _parse():
     ap.add_argument("--mode", default="asft", choices=["sft", "asft"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", type=int, default=16, choices=[16, 32], help="samples per thread")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "rows"],
+                    help="batched launch schedule (scalogram workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of this many MB (counter calibration for HBM bytes)")
     return ap.parse_args()
@@ -84,7 +86,7 @@ def bench_scalogram(args, torch, M):
     x, lengths, sigmas, xis = workloads.ragged_scalogram()
     dev = torch.device("cuda:0")
     plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=args.mode)
-    plan.set_tile(args.tile)
+    plan.set_tile(args.tile).set_schedule(args.schedule)
     xt = torch.from_numpy(x).to(dev)
     S, Ntot = len(sigmas), int(lengths.sum())
     out = torch.empty(S * Ntot, dtype=torch.complex64, device=dev)
@@ -102,7 +104,8 @@ def bench_scalogram(args, torch, M):
         "config": {"workload": "ragged scalogram: 256 pink-noise float32 signals, lengths log-uniform in "
                                "[4096, 262144] (sum %d), 32 scales sigma=4..4096 geometric, xi=6/sigma, K=5, "
                                "error-optimal windows, %s, complex64 out [signal][scale][n]" % (Ntot, args.mode),
-                   "signals": len(lengths), "scales": S, "samples_x_scales": ss, "tile_R": args.tile},
+                   "signals": len(lengths), "scales": S, "samples_x_scales": ss, "tile_R": args.tile,
+                   "schedule": args.schedule},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "kernel_ms": kern_ms,

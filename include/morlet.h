@@ -105,6 +105,17 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,
  * float32 rounding. */
 morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R);
 
+/* How a batched plan's launch distributes its rows (signal x scale) over the persistent
+ * blocks. MORLET_SCHED_TILES: blocks take single tiles in row order and resolve each
+ * tile's incoming state with the decoupled look-back. MORLET_SCHED_ROWS: a block takes a
+ * whole row (longest rows first) and carries the state from tile to tile itself, so no
+ * block waits on another. MORLET_SCHED_AUTO (default): rows when the longest row has no
+ * more tiles than one block's share of all tiles, else tiles. Single-signal plans always
+ * use tiles. Both schedules are deterministic; they differ only in the float64 rounding of
+ * the carried states. Host-only, no device work. */
+typedef enum { MORLET_SCHED_AUTO = 0, MORLET_SCHED_TILES = 1, MORLET_SCHED_ROWS = 2 } morlet_schedule;
+morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule schedule);
+
 /* Plan parameters (host outputs; any pointer may be NULL).
  *   cos_coef[K]: m_p (Morlet) or a_p (Gaussian); sin_coef[K]: l_p (0 for Gaussian);
  *   jac[4*K]: d(cos_coef)/dsigma, d(cos_coef)/dxi, d(sin_coef)/dsigma, d(sin_coef)/dxi

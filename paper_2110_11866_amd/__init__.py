@@ -50,6 +50,15 @@ class _PlanBase:
         self._ws = None
         return self
 
+    def set_schedule(self, schedule: str) -> "_PlanBase":
+        """Batched launches: "auto", "tiles" (look-back between tiles) or "rows" (a block
+        runs whole rows)."""
+        code = {"auto": _abi.MORLET_SCHED_AUTO, "tiles": _abi.MORLET_SCHED_TILES, "rows": _abi.MORLET_SCHED_ROWS}
+        if schedule not in code:
+            raise ValueError("schedule must be auto, tiles or rows")
+        _abi.morlet_plan_set_schedule(self.handle, code[schedule])
+        return self
+
     def info(self) -> dict:
         return _abi.morlet_plan_info(self.handle, self.K)
 

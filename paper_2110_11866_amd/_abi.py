@@ -29,6 +29,7 @@ SIGNATURES = {
     "morlet_plan_gauss": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
     "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
+    "morlet_plan_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
     "morlet_plan_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i32), _P(_i64), _P(_dbl), _P(_dbl), _P(_dbl),
                                         _P(_dbl), _P(_dbl)]),
     "morlet_workspace_size": (ctypes.c_int, [_vp, _P(_sz)]),
@@ -96,6 +97,13 @@ def morlet_plan_set(plan: int, mode: int, n0: int, accum: int) -> None:
 
 def morlet_plan_set_tile(plan: int, R: int) -> None:
     check(lib().morlet_plan_set_tile(plan, R))
+
+
+MORLET_SCHED_AUTO, MORLET_SCHED_TILES, MORLET_SCHED_ROWS = 0, 1, 2
+
+
+def morlet_plan_set_schedule(plan: int, schedule: int) -> None:
+    check(lib().morlet_plan_set_schedule(plan, schedule))
 
 
 def morlet_plan_info(plan: int, K: int) -> dict:

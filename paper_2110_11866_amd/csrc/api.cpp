@@ -118,6 +118,13 @@ void build_rows(morlet_plan_s* p) {
   }
   p->ntiles = tile0;
   p->ntiles_max = tmax;
+  // longest rows first: a block that takes a row runs all of its tiles, so the long rows
+  // must start early for the blocks to finish together
+  p->row_order.resize(p->rows.size());
+  for (size_t i = 0; i < p->rows.size(); ++i) p->row_order[i] = (int32_t)i;
+  std::stable_sort(p->row_order.begin(), p->row_order.end(),
+                   [&](int32_t a, int32_t b) { return p->rows[a].ntiles > p->rows[b].ntiles; });
+  p->max_row_tiles = p->rows.empty() ? 0 : p->rows[p->row_order[0]].ntiles;
 }
 
 void build_batched_tables(morlet_plan_s* p) {
@@ -135,7 +142,8 @@ morlet_status upload_batched(morlet_plan_s* p) {
   morlet_status s = upload_table(p);
   if (s != MORLET_OK || !p->d_tab) return s;
   const size_t rb = p->rows.size() * sizeof(mk::Row), tb = p->tile_row.size() * sizeof(int32_t);
-  const size_t need = rb + tb + 16;
+  const size_t ob = p->row_order.size() * sizeof(int32_t);
+  const size_t need = rb + tb + ob + 16;
   if (p->d_rows && p->rows_bytes < need) {
     (void)hipFree(p->d_rows);
     p->d_rows = nullptr;
@@ -149,7 +157,9 @@ morlet_status upload_batched(morlet_plan_s* p) {
     p->rows_bytes = need;
   }
   if ((rb && hipMemcpy(p->d_rows, p->rows.data(), rb, hipMemcpyHostToDevice) != hipSuccess) ||
-      (tb && hipMemcpy(static_cast<char*>(p->d_rows) + rb, p->tile_row.data(), tb, hipMemcpyHostToDevice) != hipSuccess)) {
+      (tb && hipMemcpy(static_cast<char*>(p->d_rows) + rb, p->tile_row.data(), tb, hipMemcpyHostToDevice) != hipSuccess) ||
+      (ob && hipMemcpy(static_cast<char*>(p->d_rows) + rb + tb, p->row_order.data(), ob, hipMemcpyHostToDevice) !=
+                 hipSuccess)) {
     (void)hipGetLastError();
     return fail(MORLET_ERR_HIP, "hipMemcpy of the row table failed");
   }
@@ -182,6 +192,9 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
     a.rows = static_cast<const mk::Row*>(plan->d_rows);
     a.tile_row = reinterpret_cast<const int32_t*>(static_cast<const char*>(plan->d_rows) +
                                                   plan->rows.size() * sizeof(mk::Row));
+    a.row_order = reinterpret_cast<const int32_t*>(static_cast<const char*>(plan->d_rows) +
+                                                   plan->rows.size() * sizeof(mk::Row) +
+                                                   plan->tile_row.size() * sizeof(int32_t));
     a.nrows = (int)plan->rows.size();
     if (a.nrows == 1) a.row0 = plan->rows[0];
   }
@@ -195,6 +208,17 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   if (occ <= 0) return fail(MORLET_ERR_UNSUPPORTED, "no kernel for this configuration");
   const int64_t cap = (int64_t)occ * plan->num_cus;
   a.grid = (int)(ntiles < cap ? ntiles : cap);
+  // Row-serial schedule when the longest row is no more than one block's share of the tiles:
+  // every block then runs whole rows, longest first, carrying the state from tile to tile
+  // in LDS, and no tile waits on another block.
+  a.serial = 0;
+  if (plan->batched && a.nrows > 1 && plan->row_serial != 0) {
+    const int64_t share = (ntiles + cap - 1) / cap;
+    if (plan->row_serial == 1 || plan->max_row_tiles <= share) {
+      a.serial = 1;
+      a.grid = (int)(a.nrows < cap ? a.nrows : cap);
+    }
+  }
   return MORLET_OK;
 }
 
@@ -366,6 +390,16 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
   mk::build_table(plan, &err);
   if (plan->d_tab) return upload_table(plan);
   return MORLET_OK;
+}
+
+morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule schedule) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  switch (schedule) {
+    case MORLET_SCHED_AUTO: plan->row_serial = -1; return MORLET_OK;
+    case MORLET_SCHED_TILES: plan->row_serial = 0; return MORLET_OK;
+    case MORLET_SCHED_ROWS: plan->row_serial = 1; return MORLET_OK;
+  }
+  return fail(MORLET_ERR_INVALID_ARG, "unknown schedule");
 }
 
 morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R) {

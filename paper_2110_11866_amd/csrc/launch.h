@@ -15,6 +15,8 @@ struct ScanLaunch {
   const Row* rows;              // device rows when nrows > 1
   int nrows;
   const int32_t* tile_row;      // device: row of every tile when nrows > 1
+  const int32_t* row_order;     // device: rows by decreasing tile count (row-serial schedule)
+  int serial;                   // 1: blocks take whole rows (no look-back); 0: tiles + look-back
   int64_t ntiles;
   const unsigned char* tabs;    // device constant tables, one per scale
   int64_t tab_stride;

@@ -31,6 +31,7 @@ struct morlet_plan_s {
   std::vector<double> jac;      // [4K]: dcc/dsigma, dcc/dxi, dsc/dsigma, dsc/dxi
   double relrmse = 0;
   int R = 16;             // samples per thread
+  int row_serial = -1;    // batched schedule: -1 automatic, 0 tiles with look-back, 1 whole rows
   int device = 0;
   int num_cus = 256;
   void* d_tab = nullptr;  // device copy of the constant table
@@ -43,8 +44,10 @@ struct morlet_plan_s {
   std::vector<ScaleParams> scales;
   std::vector<mk::Row> rows;               // B*S rows, signal-major
   std::vector<int32_t> tile_row;
+  std::vector<int32_t> row_order;          // rows by decreasing tile count (row-serial schedule)
+  int64_t max_row_tiles = 0;
   int64_t ntiles = 0, ntiles_max = 0;
-  void* d_rows = nullptr;                  // device rows followed by tile_row
+  void* d_rows = nullptr;                  // device rows, then tile_row, then row_order
   size_t rows_bytes = 0;
   // exact taps of the direct-convolution baseline (uploaded on its first call)
   void* d_direct = nullptr;

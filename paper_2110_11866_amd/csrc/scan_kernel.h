@@ -78,7 +78,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
   static_assert(!(MOM && VAR != kPg), "moment states only in the gradient pass");
 
   __shared__ uint32_t s_tile;
-  __shared__ double s_wagg[kWaves][2 * KS];
+  __shared__ double s_wagg[2][kWaves][2 * KS];   // wave aggregates (two buffers: row-serial tiles alternate)
+  __shared__ double s_c[2][2 * KS];              // row-serial: the block's state before its next tile
   __shared__ double s_xw[kWaves][2 * KS];
   __shared__ double s_e[kWaves][2 * KS];
   __shared__ double s_p[2 * KS];
@@ -98,22 +99,46 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
   const uint64_t tag = (epoch + 1) << 2;
   const TabLayout lay{K, R};
 
-  // A block claims its next tile only when it is ready to start it: a tile claimed early
-  // would hold back the look-back of every later tile of its group.
-  for (;;) {
-    if (tid == 0) s_tile = atomicAdd(&hdr->ticket, 1u);
-    __syncthreads();
-    const uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
-    if ((int64_t)tile >= P.ntiles) break;
-    Row row = P.row0;
-    if (P.nrows != 1) {
-      const cptr<Row> rp = (cptr<Row>)P.rows + __builtin_amdgcn_readfirstlane(((cptr<int32_t>)P.tile_row)[tile]);
-      row.x_off = rp->x_off; row.w_off = rp->w_off; row.N = rp->N; row.L = rp->L;
-      row.jout0 = rp->jout0; row.jend = rp->jend; row.tile0 = rp->tile0;
-      row.scale = rp->scale; row.ntiles = rp->ntiles;
-    }
+  auto load_row = [&](int32_t r, Row& row) {
+    const cptr<Row> rp = (cptr<Row>)P.rows + __builtin_amdgcn_readfirstlane(r);
+    row.x_off = rp->x_off; row.w_off = rp->w_off; row.N = rp->N; row.L = rp->L;
+    row.jout0 = rp->jout0; row.jend = rp->jend; row.tile0 = rp->tile0;
+    row.scale = rp->scale; row.ntiles = rp->ntiles;
+  };
 
-    const int64_t ti = (int64_t)tile - row.tile0;
+  // Two schedules. Tiles: a block claims its next tile only when it is ready to start it
+  // (a tile claimed early would hold back the look-back of every later tile of its group)
+  // and resolves the tile's incoming state by the look-back. Row-serial: a block claims a
+  // whole row (longest rows first) and runs its tiles in order, carrying the state in LDS.
+  Row row = P.row0;
+  int64_t ti = 0, row_left = 0;
+  for (;;) {
+    uint32_t tile;
+    if (P.serial) {
+      if (row_left == 0) {
+        if (tid == 0) s_tile = atomicAdd(&hdr->ticket, 1u);
+        __syncthreads();
+        const uint32_t r = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();   // every wave has read s_tile before thread 0 may claim again
+        if ((int64_t)r >= P.nrows) break;
+        load_row(((cptr<int32_t>)P.row_order)[r], row);
+        ti = 0;
+        row_left = row.ntiles;
+        if (row_left == 0) continue;
+      } else {
+        ++ti;
+      }
+      --row_left;
+      tile = (uint32_t)(row.tile0 + ti);
+    } else {
+      if (tid == 0) s_tile = atomicAdd(&hdr->ticket, 1u);
+      __syncthreads();
+      tile = __builtin_amdgcn_readfirstlane(s_tile);
+      if ((int64_t)tile >= P.ntiles) break;
+      if (P.nrows != 1) load_row(((cptr<int32_t>)P.tile_row)[tile], row);
+      ti = (int64_t)tile - row.tile0;
+    }
+    const int par = P.serial ? (int)(ti & 1) : 0;
     const int64_t jt = ti * T;
     const int64_t j0 = jt + (int64_t)tid * R;
     const unsigned char* tb = P.tabs + (int64_t)row.scale * P.tab_stride;
@@ -258,26 +283,65 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
     }
     if (lane == 63) {
 #pragma unroll
-      for (int i = 0; i < KS; ++i) { s_wagg[wid][2 * i] = br[i]; s_wagg[wid][2 * i + 1] = bi[i]; }
+      for (int i = 0; i < KS; ++i) { s_wagg[par][wid][2 * i] = br[i]; s_wagg[par][wid][2 * i + 1] = bi[i]; }
     }
     __syncthreads();
 
-    // 4. tile aggregate, deterministic look-back and per-wave carries (wave 0; lane i owns
-    //    state i; whole state vectors pass through LDS so a moment state can read its base)
-    if (wid == 0) {
-      // state `lane` of Op(d) v for a vector v held in LDS (entry e holds a^d, mo + e holds d a^d)
-      auto op_lds = [&](int e, const double* v, double& outr, double& outi) {
-        const int t = lane % K;
-        outr = 0; outi = 0;
-        cmac(outr, outi, tabd.re(e, t), tabd.im(e, t), v[2 * lane], v[2 * lane + 1]);
-        if (MOM && lane >= K) cmac(outr, outi, -tabd.re(mo + e, t), -tabd.im(mo + e, t), v[2 * t], v[2 * t + 1]);
-      };
+    // state `lane` of Op(d) v for a vector v held in LDS (entry e holds a^d, mo + e holds d a^d);
+    // whole state vectors pass through LDS so a moment state can read its base
+    auto op_lds = [&](int e, const double* v, double& outr, double& outi) {
+      const int t = lane % K;
+      outr = 0; outi = 0;
+      cmac(outr, outi, tabd.re(e, t), tabd.im(e, t), v[2 * lane], v[2 * lane + 1]);
+      if (MOM && lane >= K) cmac(outr, outi, -tabd.re(mo + e, t), -tabd.im(mo + e, t), v[2 * t], v[2 * t + 1]);
+    };
+    if (P.serial) {
+      // 4'. row-serial: P = the block's running state (zero at the row's start). Every wave
+      //     forms its own carry X_w = E_w + Op(64 R w) P, E_0 = 0, E_{w+1} = Op(64 R) E_w + agg_w
+      //     (lane i owns state i, the E_w vector lives in the wave's own s_e slot); wave 0
+      //     advances the running state to Op(T) P + A, A = sum_w Op(64 R (W-1-w)) agg_w.
+      const double* cin = &s_c[ti & 1][0];
+      if (lane < KS) { s_e[wid][2 * lane] = 0; s_e[wid][2 * lane + 1] = 0; }
+      wave_lds_sync();
+      for (int w = 0; w < wid; ++w) {
+        double cr = 0, ci = 0;
+        if (lane < KS) op_lds(lay.eWV(1), &s_e[wid][0], cr, ci);
+        wave_lds_sync();
+        if (lane < KS) {
+          s_e[wid][2 * lane] = cr + s_wagg[par][w][2 * lane];
+          s_e[wid][2 * lane + 1] = ci + s_wagg[par][w][2 * lane + 1];
+        }
+        wave_lds_sync();
+      }
+      if (lane < KS) {
+        double cr = 0, ci = 0;
+        if (ti > 0) op_lds(lay.eWV(wid), cin, cr, ci);
+        s_xw[wid][2 * lane] = s_e[wid][2 * lane] + cr;
+        s_xw[wid][2 * lane + 1] = s_e[wid][2 * lane + 1] + ci;
+      }
+      if (wid == 0 && lane < KS) {
+        double Ar = 0, Ai = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          double cr, ci;
+          op_lds(lay.eWV(kWaves - 1 - w), &s_wagg[par][w][0], cr, ci);
+          Ar += cr; Ai += ci;
+        }
+        double cr = 0, ci = 0;
+        if (ti > 0) op_lds(lay.eWV(kWaves), cin, cr, ci);
+        s_c[(ti + 1) & 1][2 * lane] = cr + Ar;
+        s_c[(ti + 1) & 1][2 * lane + 1] = ci + Ai;
+      }
+      wave_lds_sync();
+    } else if (wid == 0) {
+      // 4. tile aggregate, deterministic look-back and per-wave carries (wave 0; lane i owns
+      //    state i)
       double Ar = 0, Ai = 0;
       if (lane < KS) {
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
           double cr, ci;
-          op_lds(lay.eWV(kWaves - 1 - w), &s_wagg[w][0], cr, ci);
+          op_lds(lay.eWV(kWaves - 1 - w), &s_wagg[0][w][0], cr, ci);
           Ar += cr; Ai += ci;
         }
       }
@@ -353,14 +417,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
           s_xw[w][2 * lane + 1] = s_e[w][2 * lane + 1] + ci;
           if (w + 1 < kWaves) {
             op_lds(lay.eWV(1), &s_e[w][0], cr, ci);
-            s_e[w + 1][2 * lane] = cr + s_wagg[w][2 * lane];
-            s_e[w + 1][2 * lane + 1] = ci + s_wagg[w][2 * lane + 1];
+            s_e[w + 1][2 * lane] = cr + s_wagg[0][w][2 * lane];
+            s_e[w + 1][2 * lane + 1] = ci + s_wagg[0][w][2 * lane + 1];
           }
         }
         wave_lds_sync();
       }
     }
-    __syncthreads();
+    if (!P.serial) __syncthreads();
 
     // 5. thread carry (state just before the thread's first position): Op(R lane) X_w + E_l
     const bool has_out = (jt + T > row.jout0) && (row.jout0 + row.N > jt);
@@ -578,7 +642,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
     } else if constexpr (VAR == kPg) {
       if (tid < NRED) P.partials[(size_t)tile * NRED + tid] = 0.0;
     }
-    __syncthreads();
+    // Tiles: the next claim reuses s_tile and the LDS vectors. Row-serial: the alternating
+    // buffers and the barrier after the next tile's wave aggregates keep the waves at most
+    // one tile apart, which is all the sharing needs.
+    if (!P.serial) __syncthreads();
   }
 
   // last block of the launch re-arms the workspace for the next launch

@@ -131,6 +131,9 @@ def test_call_errors_before_launch():
         assert L.morlet_plan_set(h, 1, 65, 0) == _abi.MORLET_ERR_INVALID_ARG
         assert L.morlet_plan_set(h, 1, 0, 9) == _abi.MORLET_ERR_UNSUPPORTED
         assert L.morlet_forward(None, fake, 0, fake, fake, need, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_plan_set_schedule(h, 3) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_plan_set_schedule(None, 0) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_plan_set_schedule(h, _abi.MORLET_SCHED_ROWS) == _abi.MORLET_OK
     finally:
         _abi.morlet_destroy(h)
         _abi.morlet_destroy(hg)

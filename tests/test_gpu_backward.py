@@ -109,16 +109,17 @@ def test_backward_repeat_bitwise():
         assert torch.equal(gx, a[0][0]) and torch.equal(gp, a[0][1])
 
 
+@pytest.mark.parametrize("schedule", ["tiles", "rows"])
 @pytest.mark.parametrize("mode", ["sft", "asft"])
-def test_scalogram_backward_small(mode):
+def test_scalogram_backward_small(mode, schedule):
     import paper_2110_11866_amd as M
-    _announce("scalogram-backward", mode)
+    _announce("scalogram-backward", mode, schedule)
     lengths = [300, 5000, 1, 12000]
     sigmas = [4.0, 30.0, 200.0]
     xis = [6.0 / s for s in sigmas]
     rng = np.random.default_rng(5)
     x = rng.standard_normal(sum(lengths)).astype(np.float32)
-    plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=mode)
+    plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=mode).set_schedule(schedule)
     xt = torch.from_numpy(x).cuda()
     W = plan.forward(xt)
     g = torch.from_numpy((rng.standard_normal(W.numel()) + 1j * rng.standard_normal(W.numel()))
@@ -187,16 +188,17 @@ def test_autograd_layer_and_central_differences(mode):
         assert errs[1] < 1e-4 and errs[1] < errs[0], errs
 
 
-def test_differentiation_workload_sampled():
+@pytest.mark.parametrize("schedule", ["auto", "rows"])
+def test_differentiation_workload_sampled(schedule):
     # 64 signals x 32768 samples, 16 scales sigma = 8..2048, K = 5, Loss = sum w |W|^2 with
     # w ~ U[0,1] per (scale, n) shared over the batch; gradients for x (4 signals checked in
     # full) and for every (sigma_s, xi_s) (oracle summed over all 64 signals)
     import paper_2110_11866_amd as M
-    _announce("differentiation-workload")
+    _announce("differentiation-workload", schedule)
     x, sigmas, xis, w = workloads.differentiation_batch()
     B, N = x.shape
     S = len(sigmas)
-    plan = M.ScalogramPlan([N] * B, sigmas, xis, 5, 0.0)
+    plan = M.ScalogramPlan([N] * B, sigmas, xis, 5, 0.0).set_schedule(schedule)
     xt = torch.from_numpy(x.reshape(-1)).cuda()
     W = plan.forward(xt)
     wt = torch.from_numpy(np.tile(w.reshape(1, S, N), (B, 1, 1)).reshape(-1)).cuda()

@@ -47,19 +47,20 @@ def _check_rows(plan, W, x_used, rows, mode, tol):
     return worst
 
 
+@pytest.mark.parametrize("schedule", ["tiles", "rows"])
 @pytest.mark.parametrize("tile", [16, 32])
 @pytest.mark.parametrize("mode,accum,tol", [("sft", "f32", 1e-5), ("asft", "f32", 1e-5), ("asft", "compensated", 1e-6)])
-def test_small_ragged_batch_all_rows(mode, accum, tol, tile):
+def test_small_ragged_batch_all_rows(mode, accum, tol, tile, schedule):
     # ragged lengths including empty, shorter than the window, and multi-tile signals
     import paper_2110_11866_amd as M
-    _announce("ragged-small", mode, accum, tile)
+    _announce("ragged-small", mode, accum, tile, schedule)
     lengths = [0, 1, 37, 4096, 5000, 20000, 123, 65536]
     sigmas = [3.0, 10.0, 45.0, 300.0, 1500.0]
     xis = [6.0 / s for s in sigmas]
     rng = np.random.default_rng(12)
     x = rng.standard_normal(sum(lengths)).astype(np.float32)
     plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=mode, accum=accum)
-    plan.set_tile(tile)
+    plan.set_tile(tile).set_schedule(schedule)
     xt = torch.from_numpy(x).cuda()
     W = plan.forward(xt).cpu().numpy()
     W2 = plan.forward(xt).cpu().numpy()
@@ -82,15 +83,16 @@ def test_fixed_window_ratio():
     _check_rows(plan, W, xt.double().cpu().numpy(), [(b, s) for b in range(2) for s in range(2)], "sft", 1e-5)
 
 
-@pytest.mark.parametrize("mode,tile", [("sft", 16), ("asft", 16), ("asft", 32)])
-def test_full_ragged_scalogram_sampled_rows(mode, tile):
+@pytest.mark.parametrize("mode,tile,schedule", [("sft", 16, "auto"), ("asft", 16, "auto"), ("asft", 32, "auto"),
+                                                ("asft", 16, "tiles")])
+def test_full_ragged_scalogram_sampled_rows(mode, tile, schedule):
     # 256 pink-noise signals, lengths log-uniform in [4096, 262144], 32 scales 4..4096, K = 5,
     # error-optimal windows: the launch the benchmark times; 40 rows checked in full
     import paper_2110_11866_amd as M
-    _announce("ragged-full", mode, tile)
+    _announce("ragged-full", mode, tile, schedule)
     x, lengths, sigmas, xis = workloads.ragged_scalogram()
     plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode=mode)
-    plan.set_tile(tile)
+    plan.set_tile(tile).set_schedule(schedule)
     xt = torch.from_numpy(x).cuda()
     W = plan.forward(xt).cpu().numpy()
     torch.cuda.synchronize()
