@@ -84,11 +84,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
   __shared__ double s_e[kWaves][2 * KS];
   __shared__ double s_p[2 * KS];
   __shared__ double s_red[(VAR == kPg) ? kWaves * NRED : 1];
-  // output stage: per wave 64 threads x kSub outputs, each thread's sub-run padded by 16 bytes
+  // Per-wave LDS slab, each thread's slots padded by 16 bytes. Forward: the thread's R input
+  // pairs (y[j], y[j-2L]) stashed by step 2 for step 5, which then overwrites each pair with
+  // the position's output (every pair is read before its slot is written). Adjoint: the
+  // output stage only (kSub positions per store round).
   constexpr bool kCplxOut = VAR == kFwd && !GAUSS;
+  constexpr bool kStash = VAR == kFwd;
   constexpr int kSub = 16;                                  // positions per thread per store round
   static_assert(R % kSub == 0, "R must be a multiple of the store sub-run");
-  constexpr int kStride = kSub * (kCplxOut ? 2 : 1) + 4;   // floats per thread
+  constexpr int kStride = (kStash ? 2 * R : kSub * (kCplxOut ? 2 : 1)) + 4;   // floats per thread
   __shared__ __align__(16) float s_out[kWaves][(VAR == kPg) ? 4 : 64 * kStride];
 
   WsHeader* hdr = static_cast<WsHeader*>(P.ws);
@@ -239,11 +243,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
           }
         }
       };
+      float* stash = &s_out[wid][0] + lane * kStride;
+      auto keep = [&](int q, const float (&ya)[NS][4], const float (&yb)[NS][4]) {
+        if constexpr (kStash) {
+          *reinterpret_cast<float4*>(stash + 8 * q) = make_float4(ya[0][0], yb[0][0], ya[0][1], yb[0][1]);
+          *reinterpret_cast<float4*>(stash + 8 * q + 4) = make_float4(ya[0][2], yb[0][2], ya[0][3], yb[0][3]);
+        }
+      };
       if (fast_in) {
 #pragma unroll
         for (int q = 0; q < R / 4; ++q) {
           float ya[NS][4], yb[NS][4];
           load_quad_fast(j0 + 4 * q, ya, yb);
+          keep(q, ya, yb);
           step1(q, ya, yb);
         }
       } else {
@@ -251,6 +263,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
         for (int q = 0; q < R / 4; ++q) {
           float ya[NS][4], yb[NS][4];
           load_quad(j0 + 4 * q, ya, yb);
+          keep(q, ya, yb);
           step1(q, ya, yb);
         }
       }
@@ -559,37 +572,45 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
               o0[r] = (float)(gre * (A[0] - B[NS - 1]) + gim * (B[0] + A[NS - 1]));
             }
           }
-          const int qs = q % (kSub / 4);
+          // slot of the quad's outputs: sub-run relative (stage) or the whole run (stash)
+          const int qs = kStash ? q : q % (kSub / 4);
           if constexpr (kCplxOut) {
             *reinterpret_cast<float4*>(stg + 8 * qs) = make_float4(o0[0], o1[0], o0[1], o1[1]);
             *reinterpret_cast<float4*>(stg + 8 * qs + 4) = make_float4(o0[2], o1[2], o0[3], o1[3]);
           } else {
+            // a real output of position p goes to float p, whose pair (p / 2) was read by an
+            // earlier quad
             *reinterpret_cast<float4*>(stg + 4 * qs) = make_float4(o0[0], o0[1], o0[2], o0[3]);
           }
         };
         // store sub-run u: element e (0 <= e < 64 kSub) is lane e / kSub's position
-        // kSub u + e % kSub, output nw + (e / kSub) R + kSub u + e % kSub
+        // kSub u + e % kSub, output nw + (e / kSub) R + kSub u + e % kSub. Lane l handles
+        // e = G l + 64 G i (G = 2 complex or 4 real per 16-byte word; G = 1 when not whole or
+        // unaligned), so one base address per lane plus a fixed stride per i.
         auto flush = [&](int u) {
           wave_lds_sync();
-          const float* sw = &s_out[wid][0];
+          constexpr int C = kCplxOut ? 2 : 1;                 // floats per output
           const int64_t nw = jt + (int64_t)wid * 64 * R - row.jout0;   // output of the wave's first position
           const bool whole = nw >= 0 && nw + 64 * R <= row.N;
-          auto nof = [&](int e) { return nw + (int64_t)(e / kSub) * R + kSub * u + (e % kSub); };
-          auto at = [&](int e) { return sw + (e / kSub) * kStride + (e % kSub) * (kCplxOut ? 2 : 1); };
+          const float* sw = &s_out[wid][0] + (kStash ? kSub * u : 0) * C;
+          const int64_t n0u = nw + kSub * u;                  // output of lane 0's first element
           if constexpr (VAR == kFwd && !GAUSS) {
             float2* W = static_cast<float2*>(P.out) + row.w_off;
             if (whole && (reinterpret_cast<uintptr_t>(W + nw) & 15) == 0) {
+              constexpr int LPR = kSub / 2;                   // lanes per sub-run
+              const float* sp = sw + (lane / LPR) * kStride + 2 * (lane % LPR) * C;
+              float2* wp = W + n0u + (int64_t)(lane / LPR) * R + 2 * (lane % LPR);
 #pragma unroll
-              for (int i = 0; i < kSub / 2; ++i) {
-                const int e = 2 * lane + 128 * i;
-                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(at(e)), reinterpret_cast<v4f*>(W + nof(e)));
-              }
+              for (int i = 0; i < kSub / 2; ++i)
+                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(sp + i * (64 / LPR) * kStride),
+                                            reinterpret_cast<v4f*>(wp + (int64_t)i * (64 / LPR) * R));
             } else {
+              const float* sp = sw + (lane / kSub) * kStride + (lane % kSub) * C;
+              const int64_t nl = n0u + (int64_t)(lane / kSub) * R + (lane % kSub);
 #pragma unroll 1
               for (int i = 0; i < kSub; ++i) {
-                const int e = lane + 64 * i;
-                const int64_t n = nof(e);
-                if (n >= 0 && n < row.N) W[n] = *reinterpret_cast<const float2*>(at(e));
+                const int64_t n = nl + (int64_t)i * (64 / kSub) * R;
+                if (n >= 0 && n < row.N) W[n] = *reinterpret_cast<const float2*>(sp + i * (64 / kSub) * kStride);
               }
             }
           } else {
@@ -597,20 +618,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
             // forward (Gaussian): Y[n]; adjoint: written time-reversed, Y[N - 1 - n]
             constexpr bool rev = VAR == kAdj;
             if (whole && (reinterpret_cast<uintptr_t>(rev ? Y + (row.N - 4 - nw) : Y + nw) & 15) == 0) {
+              constexpr int LPR = kSub / 4;
+              const float* sp = sw + (lane / LPR) * kStride + 4 * (lane % LPR);
+              const int64_t nl = n0u + (int64_t)(lane / LPR) * R + 4 * (lane % LPR);
+              float* yp = rev ? Y + (row.N - 4 - nl) : Y + nl;
 #pragma unroll
               for (int i = 0; i < kSub / 4; ++i) {
-                const int e = 4 * lane + 256 * i;
-                const int64_t n = nof(e);
-                const v4f v = *reinterpret_cast<const v4f*>(at(e));
-                if constexpr (rev) __builtin_nontemporal_store(v.wzyx, reinterpret_cast<v4f*>(Y + (row.N - 4 - n)));
-                else __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(Y + n));
+                const v4f v = *reinterpret_cast<const v4f*>(sp + i * (64 / LPR) * kStride);
+                if constexpr (rev) __builtin_nontemporal_store(v.wzyx, reinterpret_cast<v4f*>(yp - (int64_t)i * (64 / LPR) * R));
+                else __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(yp + (int64_t)i * (64 / LPR) * R));
               }
             } else {
+              const float* sp = sw + (lane / kSub) * kStride + (lane % kSub);
+              const int64_t nl = n0u + (int64_t)(lane / kSub) * R + (lane % kSub);
 #pragma unroll 1
               for (int i = 0; i < kSub; ++i) {
-                const int e = lane + 64 * i;
-                const int64_t n = nof(e);
-                if (n >= 0 && n < row.N) Y[rev ? row.N - 1 - n : n] = *at(e);
+                const int64_t n = nl + (int64_t)i * (64 / kSub) * R;
+                if (n >= 0 && n < row.N) Y[rev ? row.N - 1 - n : n] = sp[i * (64 / kSub) * kStride];
               }
             }
           }
@@ -621,7 +645,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
         // path and the wave reconverges before the cooperative store
 #pragma unroll
         for (int u = 0; u < R / kSub; ++u) {
-          if (fast_in) {
+          if constexpr (kStash) {
+#pragma unroll
+            for (int q = u * (kSub / 4); q < (u + 1) * (kSub / 4); ++q) {
+              float ya[NS][4], yb[NS][4];
+              const float4 v0 = *reinterpret_cast<const float4*>(stg + 8 * q);
+              const float4 v1 = *reinterpret_cast<const float4*>(stg + 8 * q + 4);
+              ya[0][0] = v0.x; yb[0][0] = v0.y; ya[0][1] = v0.z; yb[0][1] = v0.w;
+              ya[0][2] = v1.x; yb[0][2] = v1.y; ya[0][3] = v1.z; yb[0][3] = v1.w;
+              step2(q, ya, yb);
+              __builtin_amdgcn_sched_barrier(0);   // keep each quad's LDS reads with its compute
+            }
+          } else if (fast_in) {
 #pragma unroll
             for (int q = u * (kSub / 4); q < (u + 1) * (kSub / 4); ++q) {
               float ya[NS][4], yb[NS][4];
