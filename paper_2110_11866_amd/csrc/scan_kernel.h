@@ -32,8 +32,10 @@
 //   1. each thread loads R consecutive inputs at j and j-2L and forms dy (coalesced runs);
 //   2. chunk sums B = sum_r a^{R-1-r} dy[r] (the thread's contribution to the state), in
 //      float64 like everything else that propagates along the row;
-//   3. inclusive scan of the chunk sums across the wavefront (6 shuffle levels, constants
-//      a^{R 2^d}, float64);
+//   3. inclusive scan of the chunk sums within each 16-lane row of the wavefront (4 DPP
+//      levels, constants a^{R 2^d}, float64); the four row totals combine through LDS into
+//      the wave aggregate and, once the wave's incoming state is known, into each row's
+//      incoming state;
 //   4. wave 0 forms the tile aggregate in float64, publishes it, and resolves the tile's
 //      exclusive prefix by a deterministic decoupled look-back: the aggregates of the
 //      earlier tiles of its 64-tile group plus the inclusive prefix of the previous
@@ -80,6 +82,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
   __shared__ uint32_t s_tile;
   __shared__ double s_wagg[2][kWaves][2 * KS];   // wave aggregates (two buffers: row-serial tiles alternate)
   __shared__ double s_c[2][2 * KS];              // row-serial: the block's state before its next tile
+  __shared__ double s_rt[kWaves][4][2 * KS];     // per wave: totals of its four 16-lane rows, then
+                                                 // the state at the start of rows 1..3
   __shared__ double s_xw[kWaves][2 * KS];
   __shared__ double s_e[kWaves][2 * KS];
   __shared__ double s_p[2 * KS];
@@ -269,37 +273,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
       }
     }
 
-    // 3. inclusive scan over the wave: S_l = sum_{m <= l} Op(R (l - m)) B_m, where Op(d)
-    //    multiplies a state by a^d (and, for a moment state, subtracts d a^d times its base)
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      const int off = 1 << d;
-      const bool take = lane >= off;
-      double ur[KS], ui[KS];
-#pragma unroll
-      for (int i = 0; i < KS; ++i) {
-        const int t = i % K;
-        ur[i] = __shfl_up(br[i], off, 64);
-        ui[i] = __shfl_up(bi[i], off, 64);
-        ur[i] = take ? ur[i] : 0.0;
-        ui[i] = take ? ui[i] : 0.0;
-        cmac(br[i], bi[i], tabd.re(lay.eTR(d), t), tabd.im(lay.eTR(d), t), ur[i], ui[i]);
-        if (MOM && i >= K) cmac(br[i], bi[i], -tabd.re(mo + lay.eTR(d), t), -tabd.im(mo + lay.eTR(d), t), ur[t], ui[t]);
-      }
-    }
-    double er[KS], ei[KS];
-#pragma unroll
-    for (int i = 0; i < KS; ++i) {
-      er[i] = __shfl_up(br[i], 1, 64);
-      ei[i] = __shfl_up(bi[i], 1, 64);
-      if (lane == 0) { er[i] = 0; ei[i] = 0; }
-    }
-    if (lane == 63) {
-#pragma unroll
-      for (int i = 0; i < KS; ++i) { s_wagg[par][wid][2 * i] = br[i]; s_wagg[par][wid][2 * i + 1] = bi[i]; }
-    }
-    __syncthreads();
-
     // state `lane` of Op(d) v for a vector v held in LDS (entry e holds a^d, mo + e holds d a^d);
     // whole state vectors pass through LDS so a moment state can read its base
     auto op_lds = [&](int e, const double* v, double& outr, double& outi) {
@@ -308,6 +281,54 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
       cmac(outr, outi, tabd.re(e, t), tabd.im(e, t), v[2 * lane], v[2 * lane + 1]);
       if (MOM && lane >= K) cmac(outr, outi, -tabd.re(mo + e, t), -tabd.im(mo + e, t), v[2 * t], v[2 * t + 1]);
     };
+
+    // 3. inclusive scan within each row of 16 lanes: S_l = sum_{m <= l, same row} Op(R (l - m)) B_m,
+    //    where Op(d) multiplies a state by a^d (and, for a moment state, subtracts d a^d times
+    //    its base). Row shifts are DPP moves, lanes shifted in from outside the row read zero.
+    //    Then the row-exclusive prefix E_l (S shifted by one lane) stays in registers and the
+    //    four row totals go to LDS.
+    auto row_shr = [](double v, int sh) -> double {
+      switch (sh) {   // dpp_ctrl row_shr:n = 0x110 + n; bound_ctrl: invalid source lanes read 0
+        case 1: return __builtin_amdgcn_update_dpp(0.0, v, 0x111, 0xF, 0xF, true);
+        case 2: return __builtin_amdgcn_update_dpp(0.0, v, 0x112, 0xF, 0xF, true);
+        case 4: return __builtin_amdgcn_update_dpp(0.0, v, 0x114, 0xF, 0xF, true);
+        default: return __builtin_amdgcn_update_dpp(0.0, v, 0x118, 0xF, 0xF, true);
+      }
+    };
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      double ur[KS], ui[KS];
+#pragma unroll
+      for (int i = 0; i < KS; ++i) { ur[i] = row_shr(br[i], 1 << d); ui[i] = row_shr(bi[i], 1 << d); }
+#pragma unroll
+      for (int i = 0; i < KS; ++i) {
+        const int t = i % K;
+        cmac(br[i], bi[i], tabd.re(lay.eTR(d), t), tabd.im(lay.eTR(d), t), ur[i], ui[i]);
+        if (MOM && i >= K) cmac(br[i], bi[i], -tabd.re(mo + lay.eTR(d), t), -tabd.im(mo + lay.eTR(d), t), ur[t], ui[t]);
+      }
+    }
+    double er[KS], ei[KS];
+#pragma unroll
+    for (int i = 0; i < KS; ++i) { er[i] = row_shr(br[i], 1); ei[i] = row_shr(bi[i], 1); }
+    const int rw = lane >> 4;   // row of the lane within its wave
+    if ((lane & 15) == 15) {
+#pragma unroll
+      for (int i = 0; i < KS; ++i) { s_rt[wid][rw][2 * i] = br[i]; s_rt[wid][rw][2 * i + 1] = bi[i]; }
+    }
+    wave_lds_sync();
+    // wave aggregate: sum_r Op(16 R (3 - r)) T_r (lane i owns state i)
+    if (lane < KS) {
+      double Ar = 0, Ai = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double cr, ci;
+        op_lds(lay.eLANE(16 * (3 - r)), &s_rt[wid][r][0], cr, ci);
+        Ar += cr; Ai += ci;
+      }
+      s_wagg[par][wid][2 * lane] = Ar;
+      s_wagg[par][wid][2 * lane + 1] = Ai;
+    }
+    __syncthreads();
     if (P.serial) {
       // 4'. row-serial: P = the block's running state (zero at the row's start). Every wave
       //     forms its own carry X_w = E_w + Op(64 R w) P, E_0 = 0, E_{w+1} = Op(64 R) E_w + agg_w
@@ -439,18 +460,32 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
     }
     if (!P.serial) __syncthreads();
 
-    // 5. thread carry (state just before the thread's first position): Op(R lane) X_w + E_l
+    // 5. thread carry (state just before the thread's first position): E_l + Op(R (l mod 16)) Z_r
+    //    with Z_r the state at the start of row r: Z_0 = X_w, Z_{r+1} = Op(16 R) Z_r + T_r.
+    //    Row-serial tiles: s_rt and s_xw belong to the wave, which reaches its next step 3
+    //    only after this one.
     const bool has_out = (jt + T > row.jout0) && (row.jout0 + row.N > jt);
     if (has_out) {
+      // Z_{r+1} overwrites T_r in place (each lane rewrites only its own state of it)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (lane < KS) {
+          double cr, ci;
+          op_lds(lay.eLANE(16), r == 0 ? &s_xw[wid][0] : &s_rt[wid][r - 1][0], cr, ci);
+          s_rt[wid][r][2 * lane] += cr;
+          s_rt[wid][r][2 * lane + 1] += ci;
+        }
+        wave_lds_sync();
+      }
+      const double* z = rw == 0 ? &s_xw[wid][0] : &s_rt[wid][rw - 1][0];
+      const int e = lay.eLANE(lane & 15);
       acc_t vr[KS], vi[KS];
 #pragma unroll
       for (int i = 0; i < KS; ++i) {
         const int t = i % K;
         double cr = er[i], ci = ei[i];
-        cmac(cr, ci, tabd.re(lay.eLANE(lane), t), tabd.im(lay.eLANE(lane), t), s_xw[wid][2 * i], s_xw[wid][2 * i + 1]);
-        if (MOM && i >= K)
-          cmac(cr, ci, -tabd.re(mo + lay.eLANE(lane), t), -tabd.im(mo + lay.eLANE(lane), t), s_xw[wid][2 * t],
-               s_xw[wid][2 * t + 1]);
+        cmac(cr, ci, tabd.re(e, t), tabd.im(e, t), z[2 * i], z[2 * i + 1]);
+        if (MOM && i >= K) cmac(cr, ci, -tabd.re(mo + e, t), -tabd.im(mo + e, t), z[2 * t], z[2 * t + 1]);
         vr[i] = (acc_t)cr;
         vi[i] = (acc_t)ci;
       }
