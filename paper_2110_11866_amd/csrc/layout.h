@@ -57,7 +57,10 @@ struct TabLayout {
   MK_HD int sDSIG() const { return nKRows() * K + 7; }  // d log(output scale) / d sigma = n0^2 / sigma^3 (ASFT)
   MK_HD int sDXI() const { return nKRows() * K + 8; }   // d arg(output factor) / d xi = n0 (ASFT Morlet)
   MK_HD int sDALPHA() const { return nKRows() * K + 9; }  // d alpha / d sigma = -2 n0 / sigma^3 (ASFT)
-  MK_HD int nValues() const { return nKRows() * K + 10; }
+  // per-term blocks (term t at vHC(t), 64-byte aligned): a_p^1, a_p^2, a_p^3, a_p^4 as
+  // (re, im) pairs, the constants of the four-position Horner step of the chunk sums
+  MK_HD int vHC(int t) const { return (nKRows() * K + 10 + 7) / 8 * 8 + 8 * t; }
+  MK_HD int nValues() const { return vHC(K); }
   MK_HD size_t f32Bytes() const { return ((size_t)nValues() * 4 + 255) / 256 * 256; }
   MK_HD size_t f64Bytes() const { return ((size_t)nValues() * 8 + 255) / 256 * 256; }
   MK_HD size_t bytes() const { return f32Bytes() + f64Bytes(); }

@@ -340,6 +340,15 @@ void fill_table(unsigned char* dst, int kind, int K, int R, int64_t L, int P_S, 
     putrow(lay.rCC(), i, cc[i]);
     putrow(lay.rSC(), i, sc[i]);
     for (int q = 0; q < 4; ++q) putrow(lay.rJ(q), i, jac.size() == (size_t)4 * K ? jac[q * K + i] : 0.0);
+    for (int k = 1; k <= 4; ++k) {
+      double re, im;
+      apow(p, k, L, alpha, re, im);
+      const int v = lay.vHC(i) + 2 * (k - 1);
+      tf[v] = (float)re;
+      tf[v + 1] = (float)im;
+      td[v] = re;
+      td[v + 1] = im;
+    }
     cx += sgn * cc[i] * dn;
   }
   const double D = std::exp(-2.0 * alpha * (double)L);

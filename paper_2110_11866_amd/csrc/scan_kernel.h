@@ -193,7 +193,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
         ld4_fast<DT>(xs, j - 2 * row.L, yb[0]);
       }
     };
-    bool fast_in = (j0 - 2 * row.L >= 0) && (j0 + R <= row.N) && (j0 + R <= row.jend);
+    // Positions past jend (the end of the row's last tile) are scanned like the others: they
+    // produce no output and their state is never carried further, so their inputs need no
+    // masking (in the gradient pass the cotangent is zero there).
+    bool fast_in = (j0 - 2 * row.L >= 0) && (j0 + R <= row.N);
     {
       if constexpr (VAR == kAdj) {
         const char* g = static_cast<const char*>(P.x) + row.w_off * (GAUSS ? 4 : 8);
@@ -226,11 +229,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
       auto step1 = [&](int q, const float (&ya)[NS][4], const float (&yb)[NS][4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const bool in = j0 + 4 * q + r < row.jend;
-          const double ddy = (MOM && in) ? (double)(2 * row.L) * Dd * (double)yb[0][r] : 0.0;
+          const double ddy = MOM ? (double)(2 * row.L) * Dd * (double)yb[0][r] : 0.0;
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
-            const double dyd = in ? (double)ya[s][r] - Dd * (double)yb[s][r] : 0.0;
+            const double dyd = (double)ya[s][r] - Dd * (double)yb[s][r];
 #pragma unroll
             for (int t = 0; t < K; ++t) {
               const int i = s * K + t;
@@ -254,7 +256,46 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
           *reinterpret_cast<float4*>(stash + 8 * q + 4) = make_float4(ya[0][2], yb[0][2], ya[0][3], yb[0][3]);
         }
       };
-      if (fast_in) {
+      if (fast_in && NS == 1 && !MOM) {
+        // every position of the run is in range: form all R differences first, then per term
+        // a Horner pass four positions at a time, B <- a^4 B + (a^3 dy_0 + a^2 dy_1 + a dy_2 + dy_3)
+        double dyd[R];
+#pragma unroll
+        for (int q = 0; q < R / 4; ++q) {
+          float ya[NS][4], yb[NS][4];
+          load_quad_fast(j0 + 4 * q, ya, yb);
+          keep(q, ya, yb);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dyd[4 * q + r] = (double)ya[0][r] - Dd * (double)yb[0][r];
+        }
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          // the term's own contiguous block (one scalar load): a^1 .. a^4
+          const int hc = lay.vHC(t);
+          const double a1r = tabd.scalar(hc), a1i = tabd.scalar(hc + 1);
+          const double a2r = tabd.scalar(hc + 2), a2i = tabd.scalar(hc + 3);
+          const double a3r = tabd.scalar(hc + 4), a3i = tabd.scalar(hc + 5);
+          const double a4r = tabd.scalar(hc + 6), a4i = tabd.scalar(hc + 7);
+          double Br = 0, Bi = 0;
+#pragma unroll
+          for (int q = 0; q < R / 4; ++q) {
+            const double d0 = dyd[4 * q], d1 = dyd[4 * q + 1], d2 = dyd[4 * q + 2], d3 = dyd[4 * q + 3];
+            const double cr = fma(a3r, d0, fma(a2r, d1, fma(a1r, d2, d3)));
+            const double ci = fma(a3i, d0, fma(a2i, d1, a1i * d2));
+            if (q == 0) {
+              Br = cr;
+              Bi = ci;
+            } else {
+              const double nr = fma(a4r, Br, fma(-a4i, Bi, cr));
+              Bi = fma(a4r, Bi, fma(a4i, Br, ci));
+              Br = nr;
+            }
+          }
+          br[t] = Br;
+          bi[t] = Bi;
+          __builtin_amdgcn_sched_barrier(0);   // one term's constants live at a time (SGPR budget)
+        }
+      } else if (fast_in) {
 #pragma unroll
         for (int q = 0; q < R / 4; ++q) {
           float ya[NS][4], yb[NS][4];
@@ -513,12 +554,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
           }
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const bool in = j0 + 4 * q + r < row.jend;
-            const acc_t dyr = in ? (acc_t)ya[0][r] - Dw * (acc_t)yb[0][r] : (acc_t)0;
+            const acc_t dyr = (acc_t)ya[0][r] - Dw * (acc_t)yb[0][r];
             const acc_t ybr = (acc_t)yb[0][r];
             const acc_t ur = (acc_t)gr[r] * gre + (acc_t)gi[r] * gim;
             const acc_t ui = (acc_t)gr[r] * gim - (acc_t)gi[r] * gre;
-            const acc_t ddy = (MOM && in) ? (acc_t)(2 * row.L) * Dw * ybr : (acc_t)0;
+            const acc_t ddy = MOM ? (acc_t)(2 * row.L) * Dw * ybr : (acc_t)0;
             acc_t A = cx * ybr, B = 0;
 #pragma unroll
             for (int t = 0; t < K; ++t) {
@@ -578,11 +618,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
           float o0[4], o1[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const bool in = j0 + 4 * q + r < row.jend;
             acc_t A[NS], B[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-              const acc_t dyr = in ? (acc_t)ya[s][r] - Dw * (acc_t)yb[s][r] : (acc_t)0;
+              const acc_t dyr = (acc_t)ya[s][r] - Dw * (acc_t)yb[s][r];
               A[s] = cx * (acc_t)yb[s][r];
               B[s] = 0;
 #pragma unroll
