@@ -17,6 +17,7 @@ Workloads (seeded, synthetic):
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -45,6 +46,29 @@ def _parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of this many MB (counter calibration for HBM bytes)")
     return ap.parse_args()
+
+
+def _csrc_sha256() -> str:
+    """Digest of the kernel sources (every .h/.hip/.cpp under the package's csrc)."""
+    d = os.path.join(ROOT, "paper_2110_11866_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def _measured_traffic(name: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter record, or
+    None when the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    return rec["traffic_bytes_per_launch"] if rec.get("csrc_sha256") == _csrc_sha256() else None
 
 
 def _timed(torch, fn, steps, warmup):
@@ -107,7 +131,9 @@ def bench_scalogram(args, torch, M):
                    "signals": len(lengths), "scales": S, "samples_x_scales": ss, "tile_R": args.tile,
                    "schedule": args.schedule},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _measured_traffic("scan_forward_scalogram_traffic.json")
+                     if (args.tile, args.schedule, args.mode) == (16, "auto", "asft") else None},
         "kernel_ms": kern_ms,
         "algorithmic_bytes_per_launch": algo_bytes,
     }
