@@ -116,6 +116,19 @@ morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R);
 typedef enum { MORLET_SCHED_AUTO = 0, MORLET_SCHED_TILES = 1, MORLET_SCHED_ROWS = 2 } morlet_schedule;
 morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule schedule);
 
+/* Autotuner: times this plan's forward launch on the caller's input x (device, dtype) for each
+ * tile shape (R = 16, 32) and, for a scalogram plan, each schedule (tiles, rows): one warm-up
+ * launch, then `reps` launches (1..1000) timed with HIP events on `stream`; keeps the fastest
+ * (ties: the earlier candidate) as the plan's tile shape and schedule. out (device) receives the
+ * trial outputs: any buffer of the forward's output size, overwritten. A setup call: it
+ * allocates and frees its own workspace and events, rebuilds the tables synchronously and
+ * synchronizes the stream, so it must not run under graph capture. R_out, schedule_out
+ * (nullable) report the choice (MORLET_SCHED_TILES or MORLET_SCHED_ROWS). Errors as
+ * morlet_forward, MORLET_ERR_ALLOC if the trial workspace cannot be allocated; on error the
+ * plan keeps its tile shape and schedule. */
+morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* out, int32_t reps,
+                                   int32_t* R_out, int32_t* schedule_out, void* stream);
+
 /* Plan parameters (host outputs; any pointer may be NULL).
  *   cos_coef[K]: m_p (Morlet) or a_p (Gaussian); sin_coef[K]: l_p (0 for Gaussian);
  *   jac[4*K]: d(cos_coef)/dsigma, d(cos_coef)/dxi, d(sin_coef)/dsigma, d(sin_coef)/dxi

@@ -62,6 +62,20 @@ class _PlanBase:
     def info(self) -> dict:
         return _abi.morlet_plan_info(self.handle, self.K)
 
+    def _out_like(self, x: torch.Tensor) -> torch.Tensor:
+        n = self.S * self.N if self.kind == "scalogram" else self.N
+        return torch.empty(n, dtype=torch.float32 if self.kind == "gauss" else torch.complex64, device=x.device)
+
+    def autotune(self, x: torch.Tensor, reps: int = 5) -> dict:
+        """Time the forward on x for each tile shape (and schedule, for scalograms) and keep
+        the fastest; returns {"R": 16 | 32, "schedule": "tiles" | "rows"}."""
+        self._check_x(x)
+        out = self._out_like(x)
+        R, sched = _abi.morlet_plan_autotune(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(),
+                                             int(reps), _stream())
+        self._ws = None
+        return {"R": R, "schedule": "rows" if sched == _abi.MORLET_SCHED_ROWS else "tiles"}
+
     def workspace_bytes(self) -> int:
         return _abi.morlet_workspace_size(self.handle)
 

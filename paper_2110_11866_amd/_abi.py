@@ -30,6 +30,7 @@ SIGNATURES = {
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
     "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
     "morlet_plan_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "morlet_plan_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _i32, _P(_i32), _P(_i32), _vp]),
     "morlet_plan_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i32), _P(_i64), _P(_dbl), _P(_dbl), _P(_dbl),
                                         _P(_dbl), _P(_dbl)]),
     "morlet_workspace_size": (ctypes.c_int, [_vp, _P(_sz)]),
@@ -104,6 +105,12 @@ MORLET_SCHED_AUTO, MORLET_SCHED_TILES, MORLET_SCHED_ROWS = 0, 1, 2
 
 def morlet_plan_set_schedule(plan: int, schedule: int) -> None:
     check(lib().morlet_plan_set_schedule(plan, schedule))
+
+
+def morlet_plan_autotune(plan: int, x: int, dtype: int, out: int, reps: int, stream: int) -> tuple[int, int]:
+    R, sched = ctypes.c_int32(), ctypes.c_int32()
+    check(lib().morlet_plan_autotune(plan, x, dtype, out, reps, ctypes.byref(R), ctypes.byref(sched), stream))
+    return R.value, sched.value
 
 
 def morlet_plan_info(plan: int, K: int) -> dict:

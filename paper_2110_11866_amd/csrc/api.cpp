@@ -449,6 +449,75 @@ morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int
   return MORLET_OK;
 }
 
+morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* out, int32_t reps,
+                                   int32_t* R_out, int32_t* schedule_out, void* stream) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (reps < 1 || reps > 1000) return fail(MORLET_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+  if ((int)dtype < 0 || (int)dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  const int oldR = plan->R, oldSched = plan->row_serial;
+  struct Cand { int R, rows; };
+  std::vector<Cand> cands = {{16, 0}, {32, 0}};
+  if (plan->batched) cands.insert(cands.end(), {{16, 1}, {32, 1}});
+  // one workspace serves every candidate: the largest of their sizes
+  size_t need = 0;
+  for (int R : {16, 32}) {
+    morlet_status st = morlet_plan_set_tile(plan, R);
+    size_t b = 0;
+    if (st == MORLET_OK) st = morlet_workspace_size(plan, &b);
+    if (st != MORLET_OK) {
+      (void)morlet_plan_set_tile(plan, oldR);
+      return st;
+    }
+    need = std::max(need, b);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc(&ws, need) != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ws) (void)hipFree(ws);
+    if (e0) (void)hipEventDestroy(e0);
+    (void)morlet_plan_set_tile(plan, oldR);
+    return fail(MORLET_ERR_ALLOC, "autotune: workspace or event allocation failed");
+  }
+  morlet_status st = MORLET_OK;
+  size_t best = 0;
+  float best_ms = 0.f;
+  for (size_t c = 0; c < cands.size() && st == MORLET_OK; ++c) {
+    st = morlet_plan_set_tile(plan, cands[c].R);
+    plan->row_serial = cands[c].rows;
+    if (st == MORLET_OK) st = morlet_workspace_init(ws, need, stream);
+    if (st == MORLET_OK) st = run_scan(plan, x, (int)dtype, out, ws, need, stream, plan->kind, plan->batched);
+    if (st != MORLET_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(MORLET_ERR_HIP, "autotune: event record failed"); break; }
+    for (int r = 0; r < reps && st == MORLET_OK; ++r)
+      st = run_scan(plan, x, (int)dtype, out, ws, need, stream, plan->kind, plan->batched);
+    float ms = 0.f;
+    if (st == MORLET_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = fail(MORLET_ERR_HIP, "autotune: event timing failed");
+    if (st == MORLET_OK && (c == 0 || ms < best_ms)) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(ws);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != MORLET_OK) {
+    (void)morlet_plan_set_tile(plan, oldR);
+    plan->row_serial = oldSched;
+    return st;
+  }
+  st = morlet_plan_set_tile(plan, cands[best].R);
+  plan->row_serial = plan->batched ? cands[best].rows : oldSched;
+  if (R_out) *R_out = cands[best].R;
+  if (schedule_out) *schedule_out = plan->batched ? (cands[best].rows ? MORLET_SCHED_ROWS : MORLET_SCHED_TILES) : MORLET_SCHED_TILES;
+  return st;
+}
+
 morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
   // sized for the longest scan range over every n0 the plan may use (n0 = 0)

@@ -2,6 +2,8 @@
 // workspace fill kernel.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <algorithm>
 
 #include "launch.h"
@@ -133,12 +135,23 @@ hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s)
 }
 
 int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int dtype) {
+  // resident blocks per CU of one kernel instantiation; queried once per instantiation (every
+  // device this library runs on is a gfx950) and kept, so launches make no runtime query
+  static std::atomic<int> cache[kMaxTerms + 1][2][3][2][2][2][3];
+  if (K < 1 || K > kMaxTerms || (R != 16 && R != 32) || variant < 0 || variant > 2 || wide < 0 || wide > 1 ||
+      kind < 0 || kind > 1 || mom < 0 || mom > 1 || dtype < 0 || dtype > 2)
+    return 0;
+  std::atomic<int>& slot = cache[K][R == 32][variant][wide][kind][mom][variant == kVarAdjoint ? 0 : dtype];
+  const int known = slot.load(std::memory_order_relaxed);
+  if (known > 0) return known;
   KernelFn fn = select_kernel(K, R, variant, wide, kind, mom, variant == kVarAdjoint ? 0 : dtype);
   if (!fn) return 0;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), kThreads, 0) != hipSuccess)
     return 1;
-  return n > 0 ? n : 1;
+  n = n > 0 ? n : 1;
+  slot.store(n, std::memory_order_relaxed);
+  return n;
 }
 
 hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s) { return launch_scan(a, kVarForward, 0, s); }

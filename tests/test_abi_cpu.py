@@ -134,6 +134,9 @@ def test_call_errors_before_launch():
         assert L.morlet_plan_set_schedule(h, 3) == _abi.MORLET_ERR_INVALID_ARG
         assert L.morlet_plan_set_schedule(None, 0) == _abi.MORLET_ERR_INVALID_ARG
         assert L.morlet_plan_set_schedule(h, _abi.MORLET_SCHED_ROWS) == _abi.MORLET_OK
+        assert L.morlet_plan_autotune(h, fake, 0, fake, 0, None, None, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_plan_autotune(h, fake, 7, fake, 3, None, None, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_plan_autotune(None, fake, 0, fake, 3, None, None, None) == _abi.MORLET_ERR_INVALID_ARG
     finally:
         _abi.morlet_destroy(h)
         _abi.morlet_destroy(hg)

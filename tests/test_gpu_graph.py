@@ -1,0 +1,126 @@
+"""Graph capture and the autotuner. A captured forward / backward is replayed several times,
+with eager work and synchronizations between replays and the input changed in place, and
+every replay is checked bitwise against the eager call on the same data (the scans are
+deterministic). The autotuner must leave a plan whose results still match the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import morlet_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2110_11866_amd  # noqa: F401
+    yield
+
+
+def _announce(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _replays(fn, xt, fresh, n=4):
+    """Capture fn() (which reads xt), then replay it n times on fresh inputs copied into xt,
+    comparing each replay with the eager call on the same input."""
+    torch.cuda.synchronize()
+    fn()                                  # warm-up outside the capture (first-use queries)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        captured = fn()
+    torch.cuda.synchronize()
+    for k in range(n):
+        xt.copy_(fresh(k))
+        junk = torch.randn(4096, device=xt.device).sum()   # unrelated eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [c.clone() for c in captured]
+        want = fn()
+        torch.cuda.synchronize()
+        for a, b in zip(got, want):
+            assert torch.equal(a, b), k
+        del junk
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_graph_forward_single(mode):
+    import paper_2110_11866_amd as M
+    _announce("graph-forward", mode)
+    N = 50000
+    rng = np.random.default_rng(21)
+    xt = torch.from_numpy(rng.standard_normal(N).astype(np.float32)).cuda()
+    plan = M.MorletPlan(N, 300.0, 6 / 300.0, 6, 1200, mode=mode)
+    ws = plan.workspace(xt.device)
+    out = torch.empty(N, dtype=torch.complex64, device=xt.device)
+    fresh = lambda k: torch.from_numpy(np.random.default_rng(100 + k).standard_normal(N).astype(np.float32)).cuda()
+    _replays(lambda: (plan.forward(xt, out=out, ws=ws),), xt, fresh)
+
+
+@pytest.mark.parametrize("schedule", ["tiles", "rows"])
+def test_graph_forward_scalogram(schedule):
+    import paper_2110_11866_amd as M
+    _announce("graph-scalogram", schedule)
+    lengths = [0, 37, 4096, 5000, 20000, 123, 65536]
+    sigmas = [3.0, 45.0, 1500.0]
+    plan = M.ScalogramPlan(lengths, sigmas, [6 / s for s in sigmas], 5, 0.0, mode="asft").set_schedule(schedule)
+    n = sum(lengths)
+    xt = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ws = plan.workspace(xt.device)
+    out = torch.empty(plan.S * n, dtype=torch.complex64, device=xt.device)
+    fresh = lambda k: torch.from_numpy(np.random.default_rng(200 + k).standard_normal(n).astype(np.float32)).cuda()
+    _replays(lambda: (plan.forward(xt, out=out, ws=ws),), xt, fresh)
+
+
+def test_graph_backward():
+    import paper_2110_11866_amd as M
+    _announce("graph-backward")
+    N = 30000
+    plan = M.MorletPlan(N, 100.0, 0.06, 5, 400, mode="asft")
+    xt = torch.zeros(N, dtype=torch.float32, device="cuda")
+    g = torch.from_numpy((np.random.default_rng(7).standard_normal(N) + 0j).astype(np.complex64)).cuda()
+    plan.workspace(xt.device, backward=True)
+    fresh = lambda k: torch.from_numpy(np.random.default_rng(300 + k).standard_normal(N).astype(np.float32)).cuda()
+    _replays(lambda: plan.backward(xt, g), xt, fresh)
+
+
+def test_autotune_single_and_scalogram():
+    import paper_2110_11866_amd as M
+    _announce("autotune")
+    N, sigma = 60000, 200.0
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(N).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    plan = M.MorletPlan(N, sigma, 6 / sigma, 5, 0, mode="asft")
+    choice = plan.autotune(xt, reps=3)
+    assert choice["R"] in (16, 32) and choice["schedule"] == "tiles"
+    got = plan.forward(xt).cpu().numpy()
+    info = plan.info()
+    p = O.plan_morlet(sigma, 6 / sigma, 5, info["L"], mode="asft", n0=info["n0"], P_S=info["P_S"])
+    want = O.forward(x.astype(np.float64), p)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-5
+
+    lengths = [5000, 300, 20000]
+    sigmas = [4.0, 30.0, 250.0]
+    sp = M.ScalogramPlan(lengths, sigmas, [6 / s for s in sigmas], 5, 0.0, mode="asft")
+    xs = rng.standard_normal(sum(lengths)).astype(np.float32)
+    xst = torch.from_numpy(xs).cuda()
+    choice = sp.autotune(xst, reps=2)
+    assert choice["R"] in (16, 32) and choice["schedule"] in ("tiles", "rows")
+    W = sp.forward(xst).cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    for b in range(len(lengths)):
+        for s in range(len(sigmas)):
+            info = sp.scale_info(s)
+            p = O.plan_morlet(sigmas[s], 6 / sigmas[s], 5, info["L"], mode="asft", n0=info["n0"], P_S=info["P_S"])
+            want = O.forward(xs[offs[b]:offs[b + 1]].astype(np.float64), p)
+            o = sp.out_offset(b, s)
+            got = W[o:o + lengths[b]]
+            assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-5, (b, s)
