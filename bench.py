@@ -1,6 +1,6 @@
 """Benchmark of the SFT/ASFT kernel-integral Morlet transform on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scalogram|paper_scale]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scalogram|paper_scale|differentiation]
 
 Prints one JSON line. A step is one pass of the transform over the workload's whole
 batch, with the inputs resident in HBM. The dominant kernel is timed with HIP events on
@@ -13,6 +13,7 @@ Workloads (seeded, synthetic):
                 windows, ASFT; complex64 output [signal][scale][n]        (default)
   paper_scale : one float32 signal, N = 102400 (three sinusoids + noise), sigma = 8192,
                 xi = 6/sigma, K = 6, L = 32768, ASFT
+  differentiation : forward + backward of the scalogram layer, 64 x 32768 signals, 16 scales
 """
 from __future__ import annotations
 
@@ -37,7 +38,7 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="scalogram", choices=["scalogram", "paper_scale"])
+    ap.add_argument("--workload", default="scalogram", choices=["scalogram", "paper_scale", "differentiation"])
     ap.add_argument("--mode", default="asft", choices=["sft", "asft"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", type=int, default=16, choices=[16, 32], help="samples per thread")
@@ -157,6 +158,50 @@ def bench_scalogram(args, torch, M):
     return line
 
 
+def bench_differentiation(args, torch, M):
+    """Forward + backward (signal, sigma and xi gradients) of the batched scalogram layer on
+    the differentiation workload; a step is one forward and one backward launch sequence."""
+    import workloads
+    x, sigmas, xis, w = workloads.differentiation_batch()
+    B, N = x.shape
+    S = len(sigmas)
+    dev = torch.device("cuda:0")
+    plan = M.ScalogramPlan([N] * B, sigmas, xis, 5, 0.0, mode=args.mode)
+    plan.set_tile(args.tile).set_schedule(args.schedule)
+    xt = torch.from_numpy(x.reshape(-1)).to(dev)
+    wt = torch.from_numpy(np.tile(w.reshape(1, S, N), (B, 1, 1)).reshape(-1)).to(dev)
+    out = torch.empty(S * B * N, dtype=torch.complex64, device=dev)
+    ws = plan.workspace(dev, backward=True)
+
+    def step():
+        W = plan.forward(xt, out=out, ws=ws)
+        g = 2 * wt * W
+        return plan.backward(xt, g)
+
+    ms_step, kern_ms = _timed(torch, step, args.steps, args.warmup)
+    ss = B * N * S
+    # forward: 8 B out + 4 B in per sample; loss cotangent (elementwise, torch): read W and w,
+    # write g; backward: read g (8 B) twice (adjoint, gradient pass) + x, write per-scale
+    # partials of dLoss/dx (4 B), read them back once, write dLoss/dx
+    algo_bytes = ss * 8 + B * N * 4 + ss * (8 + 4 + 8) + ss * (8 + 8 + 4 + 4) + B * N * (4 + 4)
+    achieved = algo_bytes / (kern_ms * 1e-3) / 1e9
+    return {
+        "metric": "Gsamples*scales/s (forward + backward of the Morlet scalogram layer)",
+        "value": ss / (ms_step * 1e-3) / 1e9,
+        "unit": "Gsamples*scales/s",
+        "ms_per_step": ms_step,
+        "dtype": "f32",
+        "config": {"workload": "differentiation: 64 x 32768 float32 N(0,1) signals, 16 scales sigma=8..2048 "
+                               f"geometric, xi=6/sigma, K=5, error-optimal windows, {args.mode}; "
+                               "loss sum w |W|^2, gradients for x, sigma_s, xi_s", "samples_x_scales": ss,
+                   "tile_R": args.tile, "schedule": args.schedule},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "kernel_ms": kern_ms,
+        "algorithmic_bytes_per_step": algo_bytes,
+    }
+
+
 def bench_paper_scale(args, torch, M):
     import workloads
     from oracle import morlet_oracle as O
@@ -233,7 +278,8 @@ def main():
         return
 
     import paper_2110_11866_amd as M
-    fn = bench_scalogram if args.workload == "scalogram" else bench_paper_scale
+    fn = {"scalogram": bench_scalogram, "paper_scale": bench_paper_scale,
+          "differentiation": bench_differentiation}[args.workload]
     line = fn(args, torch, M)
     full = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"),
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),

@@ -66,12 +66,14 @@ __global__ __launch_bounds__(256) void pg_finalize_kernel(ScanLaunch P, int K, d
   __shared__ double tot[4 * kMaxTerms + 3];
   double acc[4 * kMaxTerms + 3];
   for (int q = 0; q < NRED; ++q) acc[q] = 0.0;
-  int64_t k = 0;
-  for (int r = 0; r < P.nrows; ++r) {
-    const Row row = P.nrows == 1 ? P.row0 : P.rows[r];
-    if (row.scale != s) continue;
-    for (int64_t t = 0; t < row.ntiles; ++t, ++k) {
-      if ((k & 255) != tid) continue;
+  // the scale's rows: b S + s for every signal b of a batched launch (rows are signal-major,
+  // one block per scale), or the only row; thread tid sums tiles tid, tid + 256, ... of each
+  // row in order, then a fixed tree adds the threads
+  const int S = gridDim.x;
+  const int nb = P.nrows == 1 ? 1 : P.nrows / S;
+  for (int b = 0; b < nb; ++b) {
+    const Row row = P.nrows == 1 ? P.row0 : P.rows[(int64_t)b * S + s];
+    for (int64_t t = tid; t < row.ntiles; t += 256) {
       const double* pp = P.partials + (size_t)(row.tile0 + t) * NRED;
       for (int q = 0; q < NRED; ++q) acc[q] += pp[q];
     }
