@@ -229,7 +229,7 @@ int64_t plan_ntiles_max(morlet_plan_t plan) {
 // Backward workspace: header + tile states (2K complex states) | per-tile partials |
 // (batched) per-scale adjoint scratch [S][sum lengths] float32.
 struct BwdLayout {
-  size_t states_end, partials_off, scratch_off, total;
+  size_t states_end, partials_off, scratch_off, rowpart_off, total;
 };
 BwdLayout bwd_layout(morlet_plan_t plan) {
   const int64_t nt = plan_ntiles_max(plan);
@@ -239,7 +239,9 @@ BwdLayout bwd_layout(morlet_plan_t plan) {
   const size_t pbytes = (size_t)nt * mk::pg_partials(plan->K) * sizeof(double);
   b.scratch_off = (b.partials_off + pbytes + 255) / 256 * 256;
   const size_t sbytes = plan->batched ? (size_t)plan->S * (size_t)plan->N * sizeof(float) : 0;
-  b.total = b.scratch_off + sbytes;
+  b.rowpart_off = (b.scratch_off + sbytes + 255) / 256 * 256;
+  const size_t nrows = plan->batched ? plan->rows.size() : 1;
+  b.total = b.rowpart_off + nrows * mk::pg_partials(plan->K) * sizeof(double);
   return b;
 }
 
@@ -310,7 +312,9 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
   a.g = g;
   a.partials = reinterpret_cast<double*>(wsb + L.partials_off);
   e = mk::launch_scan(a, mk::kVarParamGrad, mom, s);
-  if (e == hipSuccess) e = mk::launch_pg_finalize(a, plan->batched ? plan->S : 1, gparams, s);
+  if (e == hipSuccess)
+    e = mk::launch_pg_finalize(a, plan->batched ? plan->S : 1, reinterpret_cast<double*>(wsb + L.rowpart_off),
+                               gparams, s);
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return MORLET_OK;
 }

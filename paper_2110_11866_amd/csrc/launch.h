@@ -33,8 +33,9 @@ enum ScanVariant { kVarForward = 0, kVarAdjoint = 1, kVarParamGrad = 2 };
 // alpha-derivative states for the ASFT sigma gradient).
 hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s);
 int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int dtype);
-// Sum per-tile partials into d/dsigma, d/dxi per scale (one block per scale).
-hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* gparams, hipStream_t s);
+// Sum per-tile partials into d/dsigma, d/dxi per scale: per-row sums into rowpart
+// [nrows][4K+3] (one block per row), then one block per scale over its rows.
+hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* rowpart, double* gparams, hipStream_t s);
 // out[b][n] = sum_s part[b][s][n] over the signals of a batched adjoint.
 hipError_t launch_sum_scales(const float* part, float* out, const Row* rows, int B, int S, int64_t total,
                              hipStream_t s);

@@ -59,35 +59,42 @@ __global__ void zero_fill_kernel(uint4* p, size_t n16, unsigned char* tail, size
 //   scale (n0^2/sigma^3 Re Q), the carrier phase (-n0 Im Q) and the decay
 //   dL/dalpha = sum_p sgn_p [m_p (e^{aL} (L S1_p + S3_p) - L e^{-aL} Sx) + l_p e^{aL} (L S2_p + S4_p)],
 //   dalpha/dsigma = -2 n0 / sigma^3.
-__global__ __launch_bounds__(256) void pg_finalize_kernel(ScanLaunch P, int K, double* gparams) {
+// Per-row sums of the tile partials (block r = row r): a row's tiles are consecutive, so its
+// partials are one contiguous [ntiles][NRED] block; thread (g, q) = (tid / NRED, tid % NRED)
+// adds value q of tiles g, g + G, ... (G = 256 / NRED groups, coalesced reads), and the G
+// group sums are added in order.
+__global__ __launch_bounds__(256) void pg_rows_kernel(ScanLaunch P, int K, double* rowpart) {
+  const int r = blockIdx.x, tid = threadIdx.x;
+  const int NRED = 4 * K + 3, G = 256 / NRED, g = tid / NRED, q = tid % NRED;
+  __shared__ double red[256];
+  const Row row = P.nrows == 1 ? P.row0 : P.rows[r];
+  double acc = 0.0;
+  if (g < G)
+    for (int64_t t = g; t < row.ntiles; t += G) acc += P.partials[(size_t)(row.tile0 + t) * NRED + q];
+  red[tid] = acc;
+  __syncthreads();
+  if (tid < NRED) {
+    double sum = 0.0;
+    for (int h = 0; h < G; ++h) sum += red[h * NRED + tid];
+    rowpart[(size_t)r * NRED + tid] = sum;
+  }
+}
+
+__global__ __launch_bounds__(256) void pg_finalize_kernel(ScanLaunch P, int K, const double* rowpart,
+                                                          double* gparams) {
   const int s = blockIdx.x, tid = threadIdx.x;
   const int NRED = 4 * K + 3;
-  __shared__ double red[256];
   __shared__ double tot[4 * kMaxTerms + 3];
-  double acc[4 * kMaxTerms + 3];
-  for (int q = 0; q < NRED; ++q) acc[q] = 0.0;
   // the scale's rows: b S + s for every signal b of a batched launch (rows are signal-major,
-  // one block per scale), or the only row; thread tid sums tiles tid, tid + 256, ... of each
-  // row in order, then a fixed tree adds the threads
+  // one block per scale), or the only row; summed in signal order
   const int S = gridDim.x;
   const int nb = P.nrows == 1 ? 1 : P.nrows / S;
-  for (int b = 0; b < nb; ++b) {
-    const Row row = P.nrows == 1 ? P.row0 : P.rows[(int64_t)b * S + s];
-    for (int64_t t = tid; t < row.ntiles; t += 256) {
-      const double* pp = P.partials + (size_t)(row.tile0 + t) * NRED;
-      for (int q = 0; q < NRED; ++q) acc[q] += pp[q];
-    }
+  if (tid < NRED) {
+    double sum = 0.0;
+    for (int b = 0; b < nb; ++b) sum += rowpart[((size_t)b * S + s) * NRED + tid];
+    tot[tid] = sum;
   }
-  for (int q = 0; q < NRED; ++q) {
-    red[tid] = acc[q];
-    __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-      if (tid < h) red[tid] += red[tid + h];
-      __syncthreads();
-    }
-    if (tid == 0) tot[q] = red[0];
-    __syncthreads();
-  }
+  __syncthreads();
   if (tid == 0) {
     const TabLayout lay{K, P.R};
     const double* td = reinterpret_cast<const double*>(P.tabs + (int64_t)s * P.tab_stride + P.f32_bytes);
@@ -160,8 +167,10 @@ hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s) { return laun
 
 int scan_forward_occupancy(int K, int R, int wide, int kind) { return scan_occupancy(K, R, kVarForward, wide, kind, 0, 0); }
 
-hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* gparams, hipStream_t s) {
-  hipLaunchKernelGGL(pg_finalize_kernel, dim3(nscales), dim3(256), 0, s, a, a.K, gparams);
+hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* rowpart, double* gparams, hipStream_t s) {
+  hipLaunchKernelGGL(pg_rows_kernel, dim3(a.nrows), dim3(256), 0, s, a, a.K, rowpart);
+  hipLaunchKernelGGL(pg_finalize_kernel, dim3(nscales), dim3(256), 0, s, a, a.K,
+                     static_cast<const double*>(rowpart), gparams);
   return hipGetLastError();
 }
 
