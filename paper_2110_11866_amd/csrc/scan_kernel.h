@@ -88,15 +88,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
   __shared__ double s_e[kWaves][2 * KS];
   __shared__ double s_p[2 * KS];
   __shared__ double s_red[(VAR == kPg) ? kWaves * NRED : 1];
-  // Per-wave LDS slab, each thread's slots padded by 16 bytes. Forward: the thread's R input
-  // pairs (y[j], y[j-2L]) stashed by step 2 for step 5, which then overwrites each pair with
-  // the position's output (every pair is read before its slot is written). Adjoint: the
-  // output stage only (kSub positions per store round).
+  // Per-wave LDS slab, each thread's slots padded by 16 bytes. Forward and adjoint: the
+  // thread's R input pairs (y[j], y[j-2L]; per stream for the adjoint's two) stashed by step 2
+  // for step 5, which then overwrites them with the outputs (every pair is read before its
+  // slot is written).
   constexpr bool kCplxOut = VAR == kFwd && !GAUSS;
-  constexpr bool kStash = VAR == kFwd;
+  constexpr bool kStash = VAR == kFwd || (VAR == kAdj && R == 16);   // R = 32 adjoint: 132 KB, one block per CU
   constexpr int kSub = 16;                                  // positions per thread per store round
   static_assert(R % kSub == 0, "R must be a multiple of the store sub-run");
-  constexpr int kStride = (kStash ? 2 * R : kSub * (kCplxOut ? 2 : 1)) + 4;   // floats per thread
+  constexpr int kStride = (kStash ? 2 * NS * R : kSub * (kCplxOut ? 2 : 1)) + 4;   // floats per thread
   __shared__ __align__(16) float s_out[kWaves][(VAR == kPg) ? 4 : 64 * kStride];
 
   WsHeader* hdr = static_cast<WsHeader*>(P.ws);
@@ -251,9 +251,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
       };
       float* stash = &s_out[wid][0] + lane * kStride;
       auto keep = [&](int q, const float (&ya)[NS][4], const float (&yb)[NS][4]) {
-        if constexpr (kStash) {
+        if constexpr (kStash && NS == 1) {
           *reinterpret_cast<float4*>(stash + 8 * q) = make_float4(ya[0][0], yb[0][0], ya[0][1], yb[0][1]);
           *reinterpret_cast<float4*>(stash + 8 * q + 4) = make_float4(ya[0][2], yb[0][2], ya[0][3], yb[0][3]);
+        } else if constexpr (kStash) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            *reinterpret_cast<float4*>(stash + 16 * q + 4 * r) = make_float4(ya[0][r], ya[1][r], yb[0][r], yb[1][r]);
         }
       };
       if (fast_in && NS == 1 && !MOM) {
@@ -652,8 +656,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
             *reinterpret_cast<float4*>(stg + 8 * qs) = make_float4(o0[0], o1[0], o0[1], o1[1]);
             *reinterpret_cast<float4*>(stg + 8 * qs + 4) = make_float4(o0[2], o1[2], o0[3], o1[3]);
           } else {
-            // a real output of position p goes to float p, whose pair (p / 2) was read by an
-            // earlier quad
+            // a real output of position p goes to float p, inside the stash of position
+            // p / (2 NS), which an earlier quad (or this one, before writing) has read
             *reinterpret_cast<float4*>(stg + 4 * qs) = make_float4(o0[0], o0[1], o0[2], o0[3]);
           }
         };
@@ -723,10 +727,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
 #pragma unroll
             for (int q = u * (kSub / 4); q < (u + 1) * (kSub / 4); ++q) {
               float ya[NS][4], yb[NS][4];
-              const float4 v0 = *reinterpret_cast<const float4*>(stg + 8 * q);
-              const float4 v1 = *reinterpret_cast<const float4*>(stg + 8 * q + 4);
-              ya[0][0] = v0.x; yb[0][0] = v0.y; ya[0][1] = v0.z; yb[0][1] = v0.w;
-              ya[0][2] = v1.x; yb[0][2] = v1.y; ya[0][3] = v1.z; yb[0][3] = v1.w;
+              if constexpr (NS == 1) {
+                const float4 v0 = *reinterpret_cast<const float4*>(stg + 8 * q);
+                const float4 v1 = *reinterpret_cast<const float4*>(stg + 8 * q + 4);
+                ya[0][0] = v0.x; yb[0][0] = v0.y; ya[0][1] = v0.z; yb[0][1] = v0.w;
+                ya[0][2] = v1.x; yb[0][2] = v1.y; ya[0][3] = v1.z; yb[0][3] = v1.w;
+              } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  const float4 v = *reinterpret_cast<const float4*>(stg + 16 * q + 4 * r);
+                  ya[0][r] = v.x; ya[NS - 1][r] = v.y; yb[0][r] = v.z; yb[NS - 1][r] = v.w;
+                }
+              }
               step2(q, ya, yb);
               __builtin_amdgcn_sched_barrier(0);   // keep each quad's LDS reads with its compute
             }
