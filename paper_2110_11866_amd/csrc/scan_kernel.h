@@ -93,11 +93,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
   // for step 5, which then overwrites them with the outputs (every pair is read before its
   // slot is written).
   constexpr bool kCplxOut = VAR == kFwd && !GAUSS;
-  constexpr bool kStash = VAR == kFwd || (VAR == kAdj && R == 16);   // R = 32 adjoint: 132 KB, one block per CU
+  // R = 32: the adjoint's pairs would take 132 KB (one block per CU), the gradient pass's 66 KB
+  constexpr bool kStash = VAR == kFwd || (VAR != kFwd && R == 16);
   constexpr int kSub = 16;                                  // positions per thread per store round
   static_assert(R % kSub == 0, "R must be a multiple of the store sub-run");
   constexpr int kStride = (kStash ? 2 * NS * R : kSub * (kCplxOut ? 2 : 1)) + 4;   // floats per thread
-  __shared__ __align__(16) float s_out[kWaves][(VAR == kPg) ? 4 : 64 * kStride];
+  __shared__ __align__(16) float s_out[kWaves][(VAR == kPg && !kStash) ? 4 : 64 * kStride];
 
   WsHeader* hdr = static_cast<WsHeader*>(P.ws);
   unsigned char* states = static_cast<unsigned char*>(P.ws) + sizeof(WsHeader);
@@ -548,7 +549,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
 #pragma unroll 1
         for (int q = 0; q < R / 4; ++q) {
           float ya[NS][4], yb[NS][4], gr[4], gi[4];
-          load_quad(j0 + 4 * q, ya, yb);
+          if constexpr (kStash) {
+            const float* stg = &s_out[wid][0] + lane * kStride;
+            const float4 v0 = *reinterpret_cast<const float4*>(stg + 8 * q);
+            const float4 v1 = *reinterpret_cast<const float4*>(stg + 8 * q + 4);
+            ya[0][0] = v0.x; yb[0][0] = v0.y; ya[0][1] = v0.z; yb[0][1] = v0.w;
+            ya[0][2] = v1.x; yb[0][2] = v1.y; ya[0][3] = v1.z; yb[0][3] = v1.w;
+          } else {
+            load_quad(j0 + 4 * q, ya, yb);
+          }
           if constexpr (GAUSS) {
             load4_f32(static_cast<const float*>(P.g) + row.w_off, nb + 4 * q, row.N, gr);
 #pragma unroll
