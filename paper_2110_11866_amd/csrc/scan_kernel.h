@@ -341,16 +341,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
         default: return __builtin_amdgcn_update_dpp(0.0, v, 0x118, 0xF, 0xF, true);
       }
     };
+    // one state (with its moment partner) at a time, so only its shifted copies are live
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-      double ur[KS], ui[KS];
 #pragma unroll
-      for (int i = 0; i < KS; ++i) { ur[i] = row_shr(br[i], 1 << d); ui[i] = row_shr(bi[i], 1 << d); }
-#pragma unroll
-      for (int i = 0; i < KS; ++i) {
+      for (int i = 0; i < (MOM ? K : KS); ++i) {
         const int t = i % K;
-        cmac(br[i], bi[i], tabd.re(lay.eTR(d), t), tabd.im(lay.eTR(d), t), ur[i], ui[i]);
-        if (MOM && i >= K) cmac(br[i], bi[i], -tabd.re(mo + lay.eTR(d), t), -tabd.im(mo + lay.eTR(d), t), ur[t], ui[t]);
+        const double ar = tabd.re(lay.eTR(d), t), ai = tabd.im(lay.eTR(d), t);
+        const double ur = row_shr(br[i], 1 << d), ui = row_shr(bi[i], 1 << d);
+        if constexpr (MOM) {
+          const double wr = row_shr(br[K + i], 1 << d), wi = row_shr(bi[K + i], 1 << d);
+          cmac(br[K + i], bi[K + i], ar, ai, wr, wi);
+          cmac(br[K + i], bi[K + i], -tabd.re(mo + lay.eTR(d), t), -tabd.im(mo + lay.eTR(d), t), ur, ui);
+        }
+        cmac(br[i], bi[i], ar, ai, ur, ui);
       }
     }
     double er[KS], ei[KS];
