@@ -41,7 +41,9 @@ import numpy as np
 from scipy.signal import fftconvolve, lfilter
 
 __all__ = [
-    "gaussian", "morlet", "Plan", "plan_morlet", "plan_gauss", "fit_morlet", "fit_gauss",
+    "gaussian", "gaussian_d1", "gaussian_d2", "fit_gauss_d1", "fit_gauss_d2", "plan_gauss_deriv",
+    "kterm_gauss_deriv",
+    "morlet", "Plan", "plan_morlet", "plan_gauss", "fit_morlet", "fit_gauss",
     "select_PS", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
     "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
     "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
@@ -58,6 +60,20 @@ def gaussian(sigma: float, k: np.ndarray) -> np.ndarray:
     gamma = 1.0 / (2.0 * sigma * sigma)
     k = np.asarray(k, dtype=np.float64)
     return math.sqrt(gamma / math.pi) * np.exp(-gamma * k * k)
+
+
+def gaussian_d1(sigma: float, k: np.ndarray) -> np.ndarray:
+    """G_D[k] = (-2 gamma k) G[k], the first differential of the Gaussian (Sec. II)."""
+    gamma = 1.0 / (2.0 * sigma * sigma)
+    k = np.asarray(k, dtype=np.float64)
+    return -2.0 * gamma * k * gaussian(sigma, k)
+
+
+def gaussian_d2(sigma: float, k: np.ndarray) -> np.ndarray:
+    """G_DD[k] = (4 gamma^2 k^2 - 2 gamma) G[k], the second differential (Sec. II)."""
+    gamma = 1.0 / (2.0 * sigma * sigma)
+    k = np.asarray(k, dtype=np.float64)
+    return (4.0 * gamma * gamma * k * k - 2.0 * gamma) * gaussian(sigma, k)
 
 
 def _morlet_consts(xi0: float) -> tuple[float, float]:
@@ -114,7 +130,7 @@ def dpsi_dtheta(sigma: float, xi: float, k: np.ndarray) -> tuple[np.ndarray, np.
 # --------------------------------------------------------------------------
 @dataclass
 class Plan:
-    kind: str                 # "morlet" or "gauss"
+    kind: str                 # "morlet", "gauss", "gd1" or "gd2" (Gaussian differentials)
     sigma: float
     xi: float                 # rad/sample (0 for the Gaussian)
     K: int                    # number of Fourier terms
@@ -173,6 +189,19 @@ def fit_gauss(sigma: float, K: int, L: int) -> np.ndarray:
     return _lstsq(Bc, gaussian(sigma, k))
 
 
+def fit_gauss_d1(sigma: float, K: int, L: int) -> np.ndarray:
+    """G_D[k] ~ sum_{p=1}^{K} b_p sin(beta p k) on [-L, L], b by MMSE (Sec. II-A, eq. mmse):
+    the odd differential takes the sine components of orders 1..K."""
+    k, _, Bs = _basis(L, np.arange(1, K + 1))
+    return _lstsq(Bs, gaussian_d1(sigma, k))
+
+
+def fit_gauss_d2(sigma: float, K: int, L: int) -> np.ndarray:
+    """G_DD[k] ~ sum_{p=0}^{K-1} d_p cos(beta p k) on [-L, L], d by MMSE (Sec. II-A)."""
+    k, Bc, _ = _basis(L, np.arange(K))
+    return _lstsq(Bc, gaussian_d2(sigma, k))
+
+
 def _ps_range(xi: float, K: int, L: int) -> range:
     """Candidate lowest orders. Orders alias modulo 2L, so P_S + K - 1 <= L.
     The carrier sits at order xi L / pi; windows that start more than K orders
@@ -221,6 +250,16 @@ def plan_gauss(sigma: float, K: int, L: int, mode: str = "sft", n0: int | None =
                 a, np.zeros(K))
 
 
+def plan_gauss_deriv(sigma: float, K: int, L: int, order: int) -> Plan:
+    """Gaussian differential smoothing, SFT (Sec. II-A): order 1 is x_GD with the sine
+    components of orders 1..K, order 2 is x_GDD with the cosine components 0..K-1."""
+    if order == 1:
+        return Plan("gd1", sigma, 0.0, K, L, 1, "sft", 0, np.zeros(K), fit_gauss_d1(sigma, K, L))
+    if order == 2:
+        return Plan("gd2", sigma, 0.0, K, L, 0, "sft", 0, fit_gauss_d2(sigma, K, L), np.zeros(K))
+    raise ValueError("order must be 1 or 2")
+
+
 # --------------------------------------------------------------------------
 # The K-term kernels as explicit taps (plain definitions the method equals)
 # --------------------------------------------------------------------------
@@ -238,6 +277,13 @@ def kterm_morlet(plan: Plan) -> np.ndarray:
 def kterm_gauss(plan: Plan) -> np.ndarray:
     """G_hat[k], k = -L..L (eq. aproGauss); real."""
     return _kterm(plan.cos_coef, plan.sin_coef, plan.P_S, plan.L).real
+
+
+def kterm_gauss_deriv(plan: Plan) -> np.ndarray:
+    """G_D_hat[k] = sum_p b_p sin(beta p k) (order 1) or G_DD_hat[k] = sum_p d_p cos(beta p k)
+    (order 2), k = -L..L (Sec. II-A); real."""
+    t = _kterm(plan.cos_coef, plan.sin_coef, plan.P_S, plan.L)
+    return t.imag if plan.kind == "gd1" else t.real
 
 
 def asft_kernel(plan: Plan) -> np.ndarray:
@@ -361,9 +407,21 @@ def forward(x: np.ndarray, plan: Plan) -> np.ndarray:
                            sum_p m_p ct_p[n-n0] + i l_p st_p[n-n0]
     Gauss,  SFT:  x_G[n] = sum_p a_p c_p[n]                            (eq. GsSFT)
     Gauss,  ASFT: x_G[n] = e^{-n0^2/(2 sigma^2)} sum_p a_p ct_p[n-n0]  (eq. GsASFT)
+    GD,     SFT:  x_GD[n] = sum_{p=1}^{K} b_p s_p[n]                 (Sec. II-A)
+    GDD,    SFT:  x_GDD[n] = sum_{p=0}^{K-1} d_p c_p[n]              (Sec. II-A)
     with c - i s = Z, so c = Re Z and s = -Im Z."""
     x = np.asarray(x, dtype=np.float64)
     N = x.shape[0]
+    if plan.kind in ("gd1", "gd2"):
+        if plan.mode != "sft":
+            raise ValueError("differential smoothing is built in SFT form only")
+        out = np.zeros(N)
+        for i, p in enumerate(plan.orders):
+            if N == 0:
+                break
+            Z = sft_component(x, int(p), plan.L)
+            out += plan.sin_coef[i] * (-Z.imag) if plan.kind == "gd1" else plan.cos_coef[i] * Z.real
+        return out
     acc = np.zeros(N, dtype=np.complex128)
     if N == 0:
         return acc if plan.kind == "morlet" else acc.real
@@ -380,11 +438,15 @@ def forward(x: np.ndarray, plan: Plan) -> np.ndarray:
     return acc if plan.kind == "morlet" else acc.real
 
 
-def forward_direct(x: np.ndarray, sigma: float, xi: float | None, L: int) -> np.ndarray:
-    """Truncated direct convolution with the exact kernel on [-L, L] (eq. xG; the
-    comparison method of Sec. V-B uses the window [-3 sigma, 3 sigma])."""
+def forward_direct(x: np.ndarray, sigma: float, xi: float | None, L: int, deriv: int = 0) -> np.ndarray:
+    """Truncated direct convolution with the exact kernel on [-L, L] (eqs. xG..xGDD; the
+    comparison method of Sec. V-B uses the window [-3 sigma, 3 sigma]). deriv = 1, 2 take
+    the Gaussian's first and second differentials."""
     k = np.arange(-L, L + 1)
-    h = gaussian(sigma, k) if xi is None else morlet(sigma, xi, k)
+    if xi is not None:
+        h = morlet(sigma, xi, k)
+    else:
+        h = (gaussian, gaussian_d1, gaussian_d2)[deriv](sigma, k)
     return conv_same(x, h, L)
 
 

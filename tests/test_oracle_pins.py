@@ -429,3 +429,90 @@ def test_adjoint_equals_transposed_matrix():
         g = rng.standard_normal(N) + 1j * rng.standard_normal(N)
         want = (A.conj().T @ g).real                                            # Re A^H g
         assert np.allclose(O.adjoint(g, pl), want, atol=1e-13)
+
+
+# ---------------------------------------------------------------- Gaussian differentials
+def _table1_deriv_err(sigma, P, L, deriv):
+    """e(G_D) or e(G_DD) of eq. mmseGEx at the fit of Sec. II-A: fit on [-L, L], zero outside,
+    error over [-3L, 3L]."""
+    pl = O.plan_gauss_deriv(sigma, P if deriv == 1 else P + 1, L, deriv)
+    k = np.arange(-3 * L, 3 * L + 1)
+    ghat = np.zeros(len(k))
+    inw = np.abs(k) <= L
+    ghat[inw] = O.kterm_gauss_deriv(pl)
+    g = (O.gaussian_d1 if deriv == 1 else O.gaussian_d2)(sigma, k)
+    return np.linalg.norm(ghat - g) / np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 6])
+def test_table1_sft_differential_fits(table1, P):
+    # the same beta as the row's e(G) optimum (Sec. II-E: "the same beta is used")
+    L = 256
+    r = minimize_scalar(lambda s: _table1_err(s, P + 1, L, "sft"), bounds=(L / 8, L / 1.5), method="bounded",
+                        options={"xatol": 1e-6})
+    eD = 100 * _table1_deriv_err(r.x, P, L, 1)
+    eDD = 100 * _table1_deriv_err(r.x, P, L, 2)
+    assert abs(eD / table1["sft_eGD_percent"][str(P)] - 1) < 0.02, eD
+    assert abs(eDD / table1["sft_eGDD_percent"][str(P)] - 1) < 0.02, eDD
+
+
+def test_differential_fits_match_closed_forms():
+    """Sines of orders 1..K < L are orthogonal on [-L, L] with norm^2 L, so b_p = <G_D, sin_p>/L;
+    the cosines 0..K-1 have Gram diag(2L, L, ...) + s s^T (s_p = (-1)^p), solved by
+    Sherman-Morrison."""
+    sigma, K, L = 9.0, 6, 36
+    k = np.arange(-L, L + 1, dtype=np.float64)
+    b = O.fit_gauss_d1(sigma, K, L)
+    ps = np.arange(1, K + 1)
+    b_cf = (np.sin(np.outer(k, ps) * math.pi / L) * O.gaussian_d1(sigma, k)[:, None]).sum(0) / L
+    assert np.allclose(b, b_cf, rtol=1e-10, atol=1e-15)
+    d = O.fit_gauss_d2(sigma, K, L)
+    pc = np.arange(K)
+    rhs = (np.cos(np.outer(k, pc) * math.pi / L) * O.gaussian_d2(sigma, k)[:, None]).sum(0)
+    dg = np.where(pc == 0, 2.0 * L, float(L))
+    sv = (-1.0) ** pc
+    d_cf = rhs / dg - (sv / dg) * (sv @ (rhs / dg)) / (1.0 + sv @ (sv / dg))
+    assert np.allclose(d, d_cf, rtol=1e-10, atol=1e-15)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("N,sigma,L,K", [(1, 2.0, 6, 3), (23, 3.0, 9, 4), (64, 5.0, 20, 6), (40, 1.5, 5, 5)])
+def test_differential_recurrence_equals_brute_force(order, N, sigma, L, K):
+    # the kernel-integral evaluation against an explicit double loop over the K-term taps
+    rng = np.random.default_rng(N + 7 * order)
+    x = rng.standard_normal(N)
+    pl = O.plan_gauss_deriv(sigma, K, L, order)
+    taps = np.zeros(2 * L + 1)
+    for j, kk in enumerate(range(-L, L + 1)):
+        for i, p in enumerate(pl.orders):
+            taps[j] += (pl.sin_coef[i] * math.sin(math.pi * p * kk / L) if order == 1
+                        else pl.cos_coef[i] * math.cos(math.pi * p * kk / L))
+    want = _brute(x, taps, L, 0)
+    assert np.allclose(O.forward(x, pl), want, rtol=1e-11, atol=1e-13)
+
+
+def test_differentials_of_a_constant():
+    """G_D_hat is odd, so a constant input gives exactly 0 in the interior; the constant column
+    is in the G_DD basis and the MMSE residual is orthogonal to it, so the interior output is
+    c * sum_{|k|<=L} G_DD[k] for any K."""
+    sigma, L, N, c = 6.0, 24, 200, 1.7
+    x = np.full(N, c)
+    inner = slice(L, N - L)
+    for K in (1, 3, 5):
+        y1 = O.forward(x, O.plan_gauss_deriv(sigma, K, L, 1))
+        assert np.abs(y1[inner]).max() < 1e-14
+        y2 = O.forward(x, O.plan_gauss_deriv(sigma, K, L, 2))
+        want = c * O.gaussian_d2(sigma, np.arange(-L, L + 1)).sum()
+        assert np.allclose(y2[inner], want, rtol=0, atol=1e-13)
+
+
+def test_differential_smoothing_close_to_direct():
+    # the K-term results approach the exact differential convolutions as K grows
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(3000)
+    sigma, L = 20.0, 80
+    for order in (1, 2):
+        direct = O.forward_direct(x, sigma, None, L, deriv=order)
+        errs = [np.linalg.norm(O.forward(x, O.plan_gauss_deriv(sigma, K, L, order)) - direct) / np.linalg.norm(direct)
+                for K in (2, 4, 6)]
+        assert errs[0] > errs[1] > errs[2] and errs[2] < 2e-3, errs
