@@ -1,6 +1,6 @@
 """Benchmark of the SFT/ASFT kernel-integral Morlet transform on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scalogram|paper_scale|differentiation]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scalogram|paper_scale|differentiation|gauss_deriv]
 
 Prints one JSON line. A step is one pass of the transform over the workload's whole
 batch, with the inputs resident in HBM. The dominant kernel is timed with HIP events on
@@ -14,6 +14,7 @@ Workloads (seeded, synthetic):
   paper_scale : one float32 signal, N = 102400 (three sinusoids + noise), sigma = 8192,
                 xi = 6/sigma, K = 6, L = 32768, ASFT
   differentiation : forward + backward of the scalogram layer, 64 x 32768 signals, 16 scales
+  gauss_deriv : first differential of Gaussian smoothing, one 2^26-sample signal, sigma = 64, K = 5
 """
 from __future__ import annotations
 
@@ -38,7 +39,8 @@ def _parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="scalogram", choices=["scalogram", "paper_scale", "differentiation"])
+    ap.add_argument("--workload", default="scalogram",
+                    choices=["scalogram", "paper_scale", "differentiation", "gauss_deriv"])
     ap.add_argument("--mode", default="asft", choices=["sft", "asft"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", type=int, default=16, choices=[16, 32], help="samples per thread")
@@ -202,6 +204,33 @@ def bench_differentiation(args, torch, M):
     }
 
 
+def bench_gauss_deriv(args, torch, M):
+    """First differential of Gaussian smoothing (x_GD, SFT) of one long float32 signal."""
+    N, sigma, K = 1 << 26, 64.0, 5
+    dev = torch.device("cuda:0")
+    x = torch.randn(N, generator=torch.Generator().manual_seed(11)).to(dev)
+    plan = M.GaussDerivPlan(N, sigma, K, 0, order=1)
+    plan.set_tile(args.tile)
+    out = torch.empty(N, dtype=torch.float32, device=dev)
+    ws = plan.workspace(dev)
+    ms_step, kern_ms = _timed(torch, lambda: plan.forward(x, out=out, ws=ws), args.steps, args.warmup)
+    algo_bytes = N * 4 + N * 4
+    achieved = algo_bytes / (kern_ms * 1e-3) / 1e9
+    return {
+        "metric": "Gsamples/s (first differential of Gaussian smoothing, SFT)",
+        "value": N / (ms_step * 1e-3) / 1e9,
+        "unit": "Gsamples/s",
+        "ms_per_step": ms_step,
+        "dtype": "f32",
+        "config": {"workload": f"gauss_deriv: one float32 N(0,1) signal, N=2^26, sigma={sigma:g}, K={K} sine "
+                               f"components, window L={plan.info()['L']} (error-optimal), float32 out",
+                   "tile_R": args.tile},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "kernel_ms": kern_ms,
+    }
+
+
 def bench_paper_scale(args, torch, M):
     import workloads
     from oracle import morlet_oracle as O
@@ -279,7 +308,7 @@ def main():
 
     import paper_2110_11866_amd as M
     fn = {"scalogram": bench_scalogram, "paper_scale": bench_paper_scale,
-          "differentiation": bench_differentiation}[args.workload]
+          "differentiation": bench_differentiation, "gauss_deriv": bench_gauss_deriv}[args.workload]
     line = fn(args, torch, M)
     full = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"),
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),

@@ -94,6 +94,21 @@ morlet_status morlet_plan(morlet_plan_t* out, int64_t N, double sigma, double xi
 morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int32_t K,
                                 int64_t L);
 
+/* Create a plan for the Gaussian's differentials applied to the signal (Sec. II-A):
+ *   order 1: x_GD[n]  = sum_{p=1}^{K} b_p s_p[n],   G_D[k]  = -2 gamma k G[k] ~ sum b_p sin(beta p k)
+ *   order 2: x_GDD[n] = sum_{p=0}^{K-1} d_p c_p[n], G_DD[k] = (4 gamma^2 k^2 - 2 gamma) G[k]
+ *                                                          ~ sum d_p cos(beta p k)
+ * gamma = 1/(2 sigma^2), b and d by MMSE on [-L, L] (eq. mmse). Run with gauss_smooth
+ * (float32 output). Same argument rules as morlet_plan_gauss, with K <= L for order 1;
+ * L = 0 takes the window of the Gaussian fit with the same top order (Table 1 uses one
+ * beta for G, G_D and G_DD). SFT only (morlet_plan_set rejects ASFT with
+ * MORLET_ERR_UNSUPPORTED), forward only (the backward calls return MORLET_ERR_UNSUPPORTED).
+ * morlet_plan_info reports b as sin_coef (order 1) or d as cos_coef (order 2); P_S is 1 or 0.
+ * Errors: MORLET_ERR_INVALID_ARG (also for an order other than 1 or 2), MORLET_ERR_ALLOC,
+ * MORLET_ERR_HIP. */
+morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigma, int32_t K, int64_t L,
+                                      int32_t order);
+
 /* Select SFT or ASFT, the ASFT shift n0 (0 = default; 1 <= n0 <= L otherwise) and the
  * accumulation precision. Rebuilds the device table (synchronously). */
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,

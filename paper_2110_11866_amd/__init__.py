@@ -13,7 +13,7 @@ from . import _abi
 from ._abi import (MORLET_ACC_COMPENSATED, MORLET_ACC_F32, MORLET_BF16, MORLET_F16, MORLET_F32,
                    MORLET_SCAN_ASFT, MORLET_SCAN_SFT, MorletError)
 
-__all__ = ["MorletPlan", "GaussPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
+__all__ = ["MorletPlan", "GaussPlan", "GaussDerivPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
            "MorletTransform"]
 
 _DT = {torch.float32: MORLET_F32, torch.float16: MORLET_F16, torch.bfloat16: MORLET_BF16}
@@ -192,6 +192,22 @@ class GaussPlan(_PlanBase):
         if want_params:
             self._check_x(x)
         return _bwd_common(self, _abi.gauss_smooth_backward, x if want_params else None, gy, want_params, 2)
+
+
+class GaussDerivPlan(GaussPlan):
+    """The Gaussian's differentials applied to the signal (Sec. II-A), SFT, forward only:
+    order 1 gives x_GD (sine components 1..K), order 2 gives x_GDD (cosine components 0..K-1)."""
+
+    def __init__(self, N: int, sigma: float, K: int, L: int = 0, order: int = 1, accum: str = "f32"):
+        _PlanBase.__init__(self, _abi.morlet_plan_gauss_deriv(int(N), float(sigma), int(K), int(L), int(order)),
+                           int(N), int(K))
+        self.sigma = float(sigma)
+        self.order = int(order)
+        if accum != "f32":
+            self.set("sft", 0, accum)
+
+    def backward(self, *args, **kwargs):
+        raise NotImplementedError("no backward pass for differential smoothing plans")
 
 
 class ScalogramPlan(_PlanBase):

@@ -27,6 +27,7 @@ _P = ctypes.POINTER
 SIGNATURES = {
     "morlet_plan": (ctypes.c_int, [_P(_vp), _i64, _dbl, _dbl, _i32, _i64]),
     "morlet_plan_gauss": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64]),
+    "morlet_plan_gauss_deriv": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64, _i32]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
     "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
     "morlet_plan_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -89,6 +90,12 @@ def morlet_plan(N: int, sigma: float, xi: float, K: int, L: int) -> int:
 def morlet_plan_gauss(N: int, sigma: float, K: int, L: int) -> int:
     h = ctypes.c_void_p()
     check(lib().morlet_plan_gauss(ctypes.byref(h), N, sigma, K, L))
+    return h.value
+
+
+def morlet_plan_gauss_deriv(N: int, sigma: float, K: int, L: int, order: int) -> int:
+    h = ctypes.c_void_p()
+    check(lib().morlet_plan_gauss_deriv(ctypes.byref(h), N, sigma, K, L, order))
     return h.value
 
 

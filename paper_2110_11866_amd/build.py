@@ -27,7 +27,7 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, "-c", *COMMON, *DEVICE_FLAGS, "-x", "hip", path, "-o", obj]
     else:
-        cmd = [HIPCC, "-c", *COMMON, path, "-o", obj]
+        cmd = [HIPCC, "-c", *COMMON, *DEVICE_FLAGS, path, "-o", obj]   # host code, same target
     subprocess.run(cmd, check=True)
     return obj
 

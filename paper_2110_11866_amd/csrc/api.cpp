@@ -176,7 +176,7 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   // the gradient pass always accumulates in float64: the chain rule through the fitted
   // coefficients cancels the per-term sums by orders of magnitude
   a.wide = variant == mk::kVarParamGrad ? 1 : plan->accum;
-  a.kind = plan->kind;
+  a.kind = (plan->kind == 1 && plan->deriv == 1) ? 2 : plan->kind;   // 2: real output from the sines
   a.row0.x_off = 0;
   a.row0.w_off = 0;
   a.row0.N = plan->N;
@@ -275,6 +275,7 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
                            void* ws, size_t ws_bytes, void* stream, int want_kind, bool want_batched) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
+  if (plan->deriv != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for differential smoothing plans");
   if (want_batched != plan->batched)
     return fail(MORLET_ERR_INVALID_ARG, want_batched ? "needs a scalogram plan" : "needs a single-signal plan");
   if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
@@ -371,9 +372,46 @@ morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int
   return finish_plan(p, out);
 }
 
+morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigma, int32_t K, int64_t L,
+                                      int32_t order) {
+  if (!out) return fail(MORLET_ERR_INVALID_ARG, "null output handle");
+  if (order != 1 && order != 2) return fail(MORLET_ERR_INVALID_ARG, "order must be 1 or 2");
+  morlet_status s = check_common(N, sigma, K, L);
+  if (s != MORLET_OK) return s;
+  if (L != 0 && (order == 1 ? L < K : L + 1 < K))
+    return fail(MORLET_ERR_INVALID_ARG, order == 1 ? "L must be >= K" : "L must be >= K - 1");
+  auto* p = new (std::nothrow) morlet_plan_s;
+  if (!p) return fail(MORLET_ERR_ALLOC, "out of host memory");
+  p->kind = 1;
+  p->deriv = order;
+  p->N = N;
+  p->sigma = sigma;
+  p->xi = 0.0;
+  p->K = K;
+  // L = 0: the window of the Gaussian fit with the same top order (orders 0..K for the first
+  // differential's sines 1..K, 0..K-1 for the second's cosines)
+  p->L = L ? L : mk::select_L(sigma, 0.0, order == 1 ? K + 1 : K, true);
+  p->P_S = order == 1 ? 1 : 0;
+  std::vector<double> g, zero, none;
+  mk::gauss_taps(sigma, p->L, g, order);
+  mk::Fit f;
+  if (order == 1) {
+    zero.assign(g.size(), 0.0);
+    f = mk::fit_orders(zero, g, p->L, 1, K);   // odd target: sine components 1..K
+  } else {
+    f = mk::fit_orders(g, none, p->L, 0, K);   // even target: cosine components 0..K-1
+  }
+  p->cc = f.cc;
+  p->sc = f.sc;
+  p->relrmse = f.relrmse;
+  return finish_plan(p, out);
+}
+
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, morlet_accum accum) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (mode != MORLET_SCAN_SFT && mode != MORLET_SCAN_ASFT) return fail(MORLET_ERR_UNSUPPORTED, "unknown scan mode");
+  if (plan->deriv != 0 && mode != MORLET_SCAN_SFT)
+    return fail(MORLET_ERR_UNSUPPORTED, "differential smoothing is built in SFT form only");
   if (accum != MORLET_ACC_F32 && accum != MORLET_ACC_COMPENSATED)
     return fail(MORLET_ERR_UNSUPPORTED, "unknown accumulation mode");
   if (n0 < 0 || (!plan->batched && n0 > plan->L))

@@ -143,11 +143,15 @@ void morlet_taps(double sigma, double xi, int64_t L, std::vector<double>& re, st
   }
 }
 
-void gauss_taps(double sigma, int64_t L, std::vector<double>& g) {
+void gauss_taps(double sigma, int64_t L, std::vector<double>& g, int deriv) {
   const double gamma = 1.0 / (2.0 * sigma * sigma);
   const double a = std::sqrt(gamma / kPi);
   g.resize(2 * L + 1);
-  for (int64_t k = -L; k <= L; ++k) g[L + k] = a * std::exp(-gamma * (double)k * (double)k);
+  for (int64_t k = -L; k <= L; ++k) {
+    const double kk = (double)k, G = a * std::exp(-gamma * kk * kk);
+    // G, G_D = (-2 gamma k) G, G_DD = (4 gamma^2 k^2 - 2 gamma) G (Sec. II)
+    g[L + k] = deriv == 0 ? G : deriv == 1 ? -2.0 * gamma * kk * G : (4.0 * gamma * gamma * kk * kk - 2.0 * gamma) * G;
+  }
 }
 
 Fit fit_orders(const std::vector<double>& tre, const std::vector<double>& tim, int64_t L, int P_S, int K) {
@@ -233,6 +237,7 @@ void jacobian(morlet_plan_s* p) {
   const int K = p->K;
   const int64_t L = p->L;
   p->jac.assign(4 * K, 0.0);
+  if (p->deriv != 0) return;   // differential smoothing has no parameter gradients
   std::vector<double> ds_re(2 * L + 1), ds_im(2 * L + 1), dx_re(2 * L + 1), dx_im(2 * L + 1);
   if (p->kind == 0) {
     // d psi / d sigma and d psi / d xi by the product rule on

@@ -17,7 +17,9 @@ struct ScaleParams {
 };
 
 struct morlet_plan_s {
-  int kind = 0;           // 0 Morlet, 1 Gaussian
+  int kind = 0;           // 0 Morlet, 1 Gaussian family (real output)
+  int deriv = 0;          // Gaussian family: 0 smoothing, 1 first differential (sine
+                          // components 1..K), 2 second differential (cosine components 0..K-1)
   int64_t N = 0;
   double sigma = 0, xi = 0;
   int K = 0;
@@ -63,7 +65,8 @@ struct Fit {
 
 // Kernel samples on k = -L..L (index k + L).
 void morlet_taps(double sigma, double xi, int64_t L, std::vector<double>& re, std::vector<double>& im);
-void gauss_taps(double sigma, int64_t L, std::vector<double>& g);
+// G[k] (deriv 0), G_D[k] (1) or G_DD[k] (2) for k = -L..L (Sec. II)
+void gauss_taps(double sigma, int64_t L, std::vector<double>& g, int deriv = 0);
 
 // MMSE fit of the given real targets on orders P_S..P_S+K-1 (cos part to `even`,
 // sin part to `odd`); relrmse against the combined complex target.

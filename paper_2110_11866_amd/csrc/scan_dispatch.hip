@@ -146,9 +146,9 @@ hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s)
 int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int dtype) {
   // resident blocks per CU of one kernel instantiation; queried once per instantiation (every
   // device this library runs on is a gfx950) and kept, so launches make no runtime query
-  static std::atomic<int> cache[kMaxTerms + 1][2][3][2][2][2][3];
+  static std::atomic<int> cache[kMaxTerms + 1][2][3][2][3][2][3];
   if (K < 1 || K > kMaxTerms || (R != 16 && R != 32) || variant < 0 || variant > 2 || wide < 0 || wide > 1 ||
-      kind < 0 || kind > 1 || mom < 0 || mom > 1 || dtype < 0 || dtype > 2)
+      kind < 0 || kind > 2 || mom < 0 || mom > 1 || dtype < 0 || dtype > 2)
     return 0;
   std::atomic<int>& slot = cache[K][R == 32][variant][wide][kind][mom][variant == kVarAdjoint ? 0 : dtype];
   const int known = slot.load(std::memory_order_relaxed);

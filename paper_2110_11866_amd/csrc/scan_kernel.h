@@ -70,10 +70,16 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
   zi = fma(cr, xi, fma(ci, xr, zi));
 }
 
-template <int VAR, int K, int R, bool WIDE, bool GAUSS, bool MOM, int DT>
+// KIND: 0 Morlet (complex64 out); 1 real output from the cosine components (Gaussian
+// smoothing, its second differential); 2 real output from the sine components (the
+// Gaussian's first differential, forward only)
+template <int VAR, int K, int R, bool WIDE, int KIND, bool MOM, int DT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR == kFwd && !WIDE) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
   using acc_t = typename std::conditional<WIDE, double, float>::type;
   constexpr int T = R * kThreads;
+  constexpr bool GAUSS = KIND != 0;                      // real output
+  constexpr bool SINE = KIND == 2;
+  static_assert(!SINE || VAR == kFwd, "sine-component output only in the forward scan");
   constexpr int NS = (VAR == kAdj && !GAUSS) ? 2 : 1;   // real input streams
   constexpr int KS = (NS == 2 || MOM) ? 2 * K : K;      // complex states per position
   constexpr int NRED = 4 * K + 3;                        // kPg partial sums per tile
@@ -639,7 +645,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
               const acc_t dyr = (acc_t)ya[s][r] - Dw * (acc_t)yb[s][r];
-              A[s] = cx * (acc_t)yb[s][r];
+              A[s] = SINE ? (acc_t)0 : cx * (acc_t)yb[s][r];
               B[s] = 0;
 #pragma unroll
               for (int t = 0; t < K; ++t) {
@@ -649,13 +655,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
                 const acc_t ni = fma(ar, vi[i], ai * vr[i]);
                 vr[i] = nr;
                 vi[i] = ni;
-                A[s] = fma(tab.row(lay.rMW(), t), nr, A[s]);
-                if (!GAUSS) B[s] = fma(tab.row(lay.rLW(), t), ni, B[s]);
+                if (!SINE) A[s] = fma(tab.row(lay.rMW(), t), nr, A[s]);
+                if (!GAUSS || SINE) B[s] = fma(tab.row(lay.rLW(), t), ni, B[s]);
               }
             }
             if constexpr (VAR == kFwd && !GAUSS) {
               o0[r] = (float)(gre * A[0] + gim * B[0]);
               o1[r] = (float)(gim * A[0] - gre * B[0]);
+            } else if constexpr (SINE) {
+              // sum_p b_p s_p with s_p = -(-1)^p e^{alpha L} Im v_p (the y[j-2L] term is real)
+              o0[r] = (float)(-gre * B[0]);
             } else if constexpr (VAR == kFwd || GAUSS) {
               o0[r] = (float)(gre * A[0]);
             } else {
@@ -805,6 +814,7 @@ KernelFn pick_scan(int var, int wide, int gauss, int mom, int dt) {
   if (var == V && wide == W && gauss == G && mom == M && dt == D) return (KernelFn)scan_kernel<V, K, R, W, G, M, D>;
 #define MK_PICK_DT(V, W, G, M) MK_PICK(V, W, G, M, 0) MK_PICK(V, W, G, M, 1) MK_PICK(V, W, G, M, 2)
   MK_PICK_DT(kFwd, 0, 0, 0) MK_PICK_DT(kFwd, 0, 1, 0) MK_PICK_DT(kFwd, 1, 0, 0) MK_PICK_DT(kFwd, 1, 1, 0)
+  MK_PICK_DT(kFwd, 0, 2, 0) MK_PICK_DT(kFwd, 1, 2, 0)
   MK_PICK(kAdj, 0, 0, 0, 0) MK_PICK(kAdj, 0, 1, 0, 0) MK_PICK(kAdj, 1, 0, 0, 0) MK_PICK(kAdj, 1, 1, 0, 0)
   MK_PICK_DT(kPg, 1, 0, 0) MK_PICK_DT(kPg, 1, 1, 0) MK_PICK_DT(kPg, 1, 0, 1) MK_PICK_DT(kPg, 1, 1, 1)
 #undef MK_PICK_DT

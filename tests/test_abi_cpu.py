@@ -68,6 +68,35 @@ def test_gauss_plan_matches_oracle():
         assert np.allclose(info["sin_coef"], 0.0)
 
 
+def test_differential_plans_match_oracle():
+    for sigma, K, L in [(16.0, 4, 64), (60.0, 6, 256), (3.0, 5, 9)]:
+        for order, fit in ((1, O.fit_gauss_d1), (2, O.fit_gauss_d2)):
+            h = _abi.morlet_plan_gauss_deriv(100, sigma, K, L, order)
+            info = _abi.morlet_plan_info(h, K)
+            _abi.morlet_destroy(h)
+            c = fit(sigma, K, L)
+            got, zero = (info["sin_coef"], info["cos_coef"]) if order == 1 else (info["cos_coef"], info["sin_coef"])
+            assert info["P_S"] == (1 if order == 1 else 0)
+            assert np.allclose(got, c, rtol=1e-10, atol=1e-15), (order, got, c)
+            assert np.allclose(zero, 0.0)
+
+
+def test_differential_plan_errors():
+    L = _abi.lib()
+    h = ctypes.c_void_p()
+    assert L.morlet_plan_gauss_deriv(ctypes.byref(h), 100, 4.0, 4, 16, 3) == _abi.MORLET_ERR_INVALID_ARG
+    assert L.morlet_plan_gauss_deriv(ctypes.byref(h), 100, 4.0, 6, 5, 1) == _abi.MORLET_ERR_INVALID_ARG
+    assert L.morlet_plan_gauss_deriv(ctypes.byref(h), 100, 4.0, 6, 5, 2) == _abi.MORLET_OK
+    hp = h.value
+    try:
+        assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 0, 0) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_SFT, 0, 1) == _abi.MORLET_OK
+        fake = 1 << 20
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+    finally:
+        _abi.morlet_destroy(hp)
+
+
 def test_jacobian_matches_oracle():
     sigma, xi, K, L = 8.0, 0.75, 5, 32
     h = _abi.morlet_plan(100, sigma, xi, K, L)

@@ -213,3 +213,27 @@ def test_paper_scale_within_truncation_bound_of_direct(mode):
     print(f"[result] {mode}: K-term vs direct {trunc / np.linalg.norm(wdir):.3e}", flush=True)
     assert np.linalg.norm(got - wdir) <= trunc + 1e-5 * np.linalg.norm(wk)
     assert rel_l2(gdir, wdir) <= 1e-5, rel_l2(gdir, wdir)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("N,sigma,K,L,tile,dtype,accum", [
+    (1024, 16.0, 4, 64, 16, torch.float32, "f32"),
+    (50000, 300.0, 6, 1200, 16, torch.float32, "f32"),
+    (77777, 2000.0, 5, 0, 32, torch.bfloat16, "f32"),
+    (9000, 1.5, 12, 12, 16, torch.float16, "f32"),
+    (50000, 300.0, 6, 1200, 16, torch.float32, "compensated"),
+])
+def test_gaussian_differential_parity(N, sigma, K, L, tile, dtype, accum, order):
+    # x_GD (sine components 1..K) and x_GDD (cosine components 0..K-1), SFT (Sec. II-A)
+    import paper_2110_11866_amd as M
+    _announce("gauss-deriv", order, N, sigma, K, L, tile, dtype, accum)
+    x = np.random.default_rng(N + order).standard_normal(N).astype(np.float32)
+    xt = torch.from_numpy(x).to("cuda").to(dtype)
+    plan = M.GaussDerivPlan(N, sigma, K, L, order=order, accum=accum)
+    plan.set_tile(tile)
+    got = plan.forward(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    info = plan.info()
+    p = O.plan_gauss_deriv(sigma, K, info["L"], order)
+    want = O.forward(xt.double().cpu().numpy(), p)
+    assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
