@@ -35,7 +35,8 @@ struct TabLayout {
   MK_HD int eLANE(int l) const { return 7 + R + l; }    // a_p^{R l}, l in [0, 64): per-lane carry phase
   MK_HD int eWV(int w) const { return 71 + R + w; }     // a_p^{64 R w}, w in [0, kWaves]: per-wave carry; w = kWaves gives a^T
   MK_HD int eLB(int k) const { return 72 + R + kWaves + k; }  // a_p^{T k}, k in [0, 64]: look-back weights
-  MK_HD int nComplex() const { return 72 + R + kWaves + 65; }
+  MK_HD int eLB2(int k) const { return 137 + R + kWaves + k; }  // a_p^{64 T k}, k in [0, 64]: group weights
+  MK_HD int nComplex() const { return 137 + R + kWaves + 65; }
   // entry nComplex() + e holds d a_p^d for the distance d of entry e (alpha-derivative)
   MK_HD int nComplexAll() const { return 2 * nComplex(); }
   // real K-rows, after the complex ones (row index in units of K values)
@@ -91,8 +92,11 @@ static_assert(sizeof(WsHeader) == 64, "header size");
 
 // Tile state: flag word, then K complex float64 aggregates, then K complex inclusive
 // prefixes. flag = (epoch + 1) << 2 | status.
-enum : uint64_t { kEmpty = 0, kAggregate = 1, kInclusive = 2 };
-MK_HD inline size_t tile_state_bytes(int K) { return ((size_t)(8 + 32 * K) + 63) / 64 * 64; }
+// tile status: aggregate published; inclusive prefix published (last tile of a super-group);
+// group aggregate published (last tile of any other group)
+enum : uint64_t { kEmpty = 0, kAggregate = 1, kInclusive = 2, kGroup = 3 };
+// flag, then K complex float64 each: aggregate, inclusive prefix, group aggregate
+MK_HD inline size_t tile_state_bytes(int K) { return ((size_t)(8 + 48 * K) + 63) / 64 * 64; }
 
 inline size_t workspace_bytes(int K, int64_t ntiles) {
   return sizeof(WsHeader) + tile_state_bytes(K) * (size_t)(ntiles > 0 ? ntiles : 0);

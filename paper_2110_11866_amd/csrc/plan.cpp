@@ -337,6 +337,7 @@ void fill_table(unsigned char* dst, int kind, int K, int R, int64_t L, int P_S, 
     for (int l = 0; l < 64; ++l) put(lay.eLANE(l), i, p, (int64_t)R * l);
     for (int w = 0; w <= kWaves; ++w) put(lay.eWV(w), i, p, (int64_t)64 * R * w);
     for (int k = 0; k <= 64; ++k) put(lay.eLB(k), i, p, T * k);
+    for (int k = 0; k <= 64; ++k) put(lay.eLB2(k), i, p, 64 * T * k);
     const double sgn = (p & 1) ? -1.0 : 1.0;
     const double up = std::exp(alpha * (double)L), dn = std::exp(-alpha * (double)L);
     putrow(lay.rMW(), i, sgn * cc[i] * up);

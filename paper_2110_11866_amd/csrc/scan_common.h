@@ -40,6 +40,7 @@ struct TileState {
   __device__ uint64_t* flag() const { return reinterpret_cast<uint64_t*>(b); }
   __device__ double* agg(int i, int c) const { return reinterpret_cast<double*>(b + 8) + 2 * i + c; }
   __device__ double* inc(int i, int c) const { return reinterpret_cast<double*>(b + 8) + 2 * K + 2 * i + c; }
+  __device__ double* gag(int i, int c) const { return reinterpret_cast<double*>(b + 8) + 4 * K + 2 * i + c; }
 };
 
 // ------------------------------------------------------------ input loads

@@ -74,7 +74,7 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
 // smoothing, its second differential); 2 real output from the sine components (the
 // Gaussian's first differential, forward only)
 template <int VAR, int K, int R, bool WIDE, int KIND, bool MOM, int DT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR == kFwd && !WIDE) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR == kFwd && !WIDE && R == 16) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
   using acc_t = typename std::conditional<WIDE, double, float>::type;
   constexpr int T = R * kThreads;
   constexpr bool GAUSS = KIND != 0;                      // real output
@@ -93,6 +93,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
   __shared__ double s_xw[kWaves][2 * KS];
   __shared__ double s_e[kWaves][2 * KS];
   __shared__ double s_p[2 * KS];
+  __shared__ double s_lb[2 * KS];                // look-back: a state vector on its way through Op
   __shared__ double s_red[(VAR == kPg) ? kWaves * NRED : 1];
   // Per-wave LDS slab, each thread's slots padded by 16 bytes. Forward and adjoint: the
   // thread's R input pairs (y[j], y[j-2L]; per stream for the adjoint's two) stashed by step 2
@@ -436,56 +437,107 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
         }
       }
       const TileState st{states + (size_t)tile * sbytes, KS};
-      // Tiles are grouped by 64 within the row. Tile i combines, in a fixed order, the
-      // aggregates of the earlier tiles of its group and the inclusive prefix of the previous
-      // group's last tile, so the float64 sums never depend on timing.
-      const int64_t grp0 = (ti / kLookback) * kLookback;
-      const int dd = (int)(ti - grp0);
-      const bool group_last = (ti % kLookback) == kLookback - 1;
+      // Three fixed levels within the row, so the float64 sums never depend on timing:
+      // tiles in groups of 64, groups in super-groups of 64. The exclusive prefix of tile ti
+      // (group g, position dd in it, position gd of g in its super-group) is
+      //   P = S1 + Op(T dd) Z,  S1 = sum_{k<dd} Op(T k) A_{ti-1-k}   (its group's earlier tiles)
+      //   Z = sum_{k<gd} Op(64 T k) GA_{g-1-k} + Op(64 T gd) I      (state at the end of group g-1)
+      // with A the tile aggregates, GA the group aggregates (published by each group's last
+      // tile as soon as its own group is known) and I the inclusive prefix published by the
+      // last tile of the previous super-group: the only serial chain is one link per
+      // 4096 tiles.
+      const int64_t g = ti / kLookback;
+      const int dd = (int)(ti - g * kLookback);
+      const int64_t sg0 = (g / kLookback) * kLookback;   // first group of the super-group
+      const int gd = (int)(g - sg0);
+      const bool group_last = dd == kLookback - 1;
+      const bool super_last = group_last && gd == kLookback - 1;
       if (lane < KS) { st_f64(st.agg(lane, 0), Ar); st_f64(st.agg(lane, 1), Ai); }
       release_order();
       if (lane == 0) st_u64(st.flag(), tag | kAggregate);
-      double Pr = 0, Pi = 0;
-      if (ti > 0) {
+      auto status_of = [&](int64_t rel) {   // status of the tile rel places before this one
+        const uint64_t f = ld_u64(TileState{states + (size_t)((int64_t)tile - rel) * sbytes, KS}.flag());
+        return ((f & ~3ull) == tag) ? (int)(f & 3ull) : 0;
+      };
+      // lane k's weighted contribution to state i from the state vector v of one predecessor
+      // (e: weight entry; the moment variant also reads the base state t of the same vector)
+      auto contrib = [&](int i, int e, const TileState& sk, int which, double& cr, double& ci) {
+        const int t = i % K;
+        auto ptr = [&](int s, int c) { return which == 0 ? sk.agg(s, c) : which == 1 ? sk.gag(s, c) : sk.inc(s, c); };
+        cmac(cr, ci, tabd.re(e, t), tabd.im(e, t), ld_f64(ptr(i, 0)), ld_f64(ptr(i, 1)));
+        if (MOM && i >= K) cmac(cr, ci, -tabd.re(mo + e, t), -tabd.im(mo + e, t), ld_f64(ptr(t, 0)), ld_f64(ptr(t, 1)));
+      };
+      // phase 1: the earlier tiles of the group
+      double S1r = 0, S1i = 0;
+      if (dd > 0) {
         for (;;) {
-          bool ok = true;
-          if (lane < dd || (lane == dd && grp0 > 0)) {
-            const uint64_t f = ld_u64(TileState{states + (size_t)((int64_t)tile - 1 - lane) * sbytes, KS}.flag());
-            const int status = ((f & ~3ull) == tag) ? (int)(f & 3ull) : 0;
-            ok = (lane < dd) ? (status >= 1) : (status == 2);
-          }
+          const bool ok = lane >= dd || status_of(1 + lane) >= 1;
           if (__ballot(!ok) == 0) break;
           __builtin_amdgcn_s_sleep(1);
         }
         acquire_order();
-        // lane k takes predecessor k's contribution Op(T k) v_k, one state at a time; a fixed
-        // butterfly sums them (lanes past the last predecessor contribute exact zeros, so the
-        // order never varies)
-        const int kmax = grp0 > 0 ? dd : dd - 1;
-        const TileState sk{states + (size_t)((int64_t)tile - 1 - lane) * sbytes, KS};
-        const bool agg_lane = lane < dd;
+        // lanes past the last predecessor point at the nearest one (never read)
+        const TileState sk{states + (size_t)((int64_t)tile - 1 - (lane < dd ? lane : 0)) * sbytes, KS};
 #pragma unroll
         for (int i = 0; i < KS; ++i) {
-          const int t = i % K;
           double cr = 0, ci = 0;
-          if (lane <= kmax) {
-            const double vr = ld_f64(agg_lane ? sk.agg(i, 0) : sk.inc(i, 0));
-            const double vi = ld_f64(agg_lane ? sk.agg(i, 1) : sk.inc(i, 1));
-            cmac(cr, ci, tabd.re(lay.eLB(lane), t), tabd.im(lay.eLB(lane), t), vr, vi);
-            if (MOM && i >= K) {
-              const double ur = ld_f64(agg_lane ? sk.agg(t, 0) : sk.inc(t, 0));
-              const double ui = ld_f64(agg_lane ? sk.agg(t, 1) : sk.inc(t, 1));
-              cmac(cr, ci, -tabd.re(mo + lay.eLB(lane), t), -tabd.im(mo + lay.eLB(lane), t), ur, ui);
-            }
-          }
+          if (lane < dd) contrib(i, lay.eLB(lane), sk, 0, cr, ci);
 #pragma unroll
           for (int off = 32; off >= 1; off >>= 1) { cr += __shfl_xor(cr, off, 64); ci += __shfl_xor(ci, off, 64); }
-          if (lane == i) { Pr = cr; Pi = ci; }
+          if (lane == i) { S1r = cr; S1i = ci; }
+        }
+      }
+      if (group_last && !super_last) {
+        // group aggregate GA = Op(T) S1 + A, independent of everything before the group
+        if (lane < KS) { s_lb[2 * lane] = S1r; s_lb[2 * lane + 1] = S1i; }
+        wave_lds_sync();
+        if (lane < KS) {
+          double cr, ci;
+          op_lds(lay.eWV(kWaves), s_lb, cr, ci);
+          st_f64(st.gag(lane, 0), cr + Ar);
+          st_f64(st.gag(lane, 1), ci + Ai);
+        }
+        release_order();
+        if (lane == 0) st_u64(st.flag(), tag | kGroup);
+      }
+      // phase 2: the state at the end of the previous group
+      double Pr = S1r, Pi = S1i;
+      if (g > 0) {
+        const bool has_inc = sg0 > 0;
+        for (;;) {
+          bool ok = true;
+          if (lane < gd) ok = status_of(ti - (kLookback * (g - 1 - lane) + kLookback - 1)) == (int)kGroup;
+          else if (lane == gd && has_inc) ok = status_of(ti - (kLookback * sg0 - 1)) == (int)kInclusive;
+          if (__ballot(!ok) == 0) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        acquire_order();
+        const int64_t rel = lane < gd ? ti - (kLookback * (g - 1 - lane) + kLookback - 1)
+                            : has_inc ? ti - (kLookback * sg0 - 1) : 1;   // 1: never read
+        const TileState sk{states + (size_t)((int64_t)tile - rel) * sbytes, KS};
+        double Zr = 0, Zi = 0;
+#pragma unroll
+        for (int i = 0; i < KS; ++i) {
+          double cr = 0, ci = 0;
+          if (lane < gd) contrib(i, lay.eLB2(lane), sk, 1, cr, ci);
+          else if (lane == gd && has_inc) contrib(i, lay.eLB2(gd), sk, 2, cr, ci);
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) { cr += __shfl_xor(cr, off, 64); ci += __shfl_xor(ci, off, 64); }
+          if (lane == i) { Zr = cr; Zi = ci; }
+        }
+        // P = S1 + Op(T dd) Z
+        if (lane < KS) { s_lb[2 * lane] = Zr; s_lb[2 * lane + 1] = Zi; }
+        wave_lds_sync();
+        if (lane < KS) {
+          double cr, ci;
+          op_lds(lay.eLB(dd), s_lb, cr, ci);
+          Pr += cr;
+          Pi += ci;
         }
       }
       if (lane < KS) { s_p[2 * lane] = Pr; s_p[2 * lane + 1] = Pi; }
       wave_lds_sync();
-      if (group_last) {
+      if (super_last) {
         if (lane < KS) {   // inclusive = Op(T) P + A
           double cr, ci;
           op_lds(lay.eWV(kWaves), s_p, cr, ci);

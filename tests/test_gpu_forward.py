@@ -237,3 +237,23 @@ def test_gaussian_differential_parity(N, sigma, K, L, tile, dtype, accum, order)
     p = O.plan_gauss_deriv(sigma, K, info["L"], order)
     want = O.forward(xt.double().cpu().numpy(), p)
     assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_long_row_crosses_super_groups(mode):
+    # one 17e6-sample row: 4153 tiles of 4096 positions, i.e. more than one super-group of
+    # 64 x 64 tiles in the look-back; checked in full, and bitwise on a repeat
+    import paper_2110_11866_amd as M
+    _announce("long-row", mode)
+    N, sigma, K, L = 17_000_000, 40.0, 4, 160
+    x = np.random.default_rng(17).standard_normal(N).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode)
+    a = plan.forward(xt)
+    b = plan.forward(xt)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    info = plan.info()
+    p = O.plan_morlet(sigma, 6.0 / sigma, K, L, mode=mode, n0=info["n0"] if mode == "asft" else None)
+    want = O.forward(x.astype(np.float64), p)
+    assert rel_l2(a.cpu().numpy(), want) <= 1e-5, rel_l2(a.cpu().numpy(), want)
