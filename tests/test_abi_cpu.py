@@ -192,3 +192,31 @@ def test_asft_shift_and_alpha_reported():
         assert _abi.morlet_plan_info(h, 4)["n0"] == 0
     finally:
         _abi.morlet_destroy(h)
+
+
+def test_plan_sweep_matches_oracle():
+    # seeded sweep over sigma, xi0, K and the window: P_S and the fitted coefficients of the
+    # library's host plan against the oracle's independent least-squares fit
+    rng = np.random.default_rng(2024)
+    for _ in range(40):
+        sigma = float(np.exp(rng.uniform(np.log(1.5), np.log(3000.0))))
+        K = int(rng.integers(1, 13))
+        xi0 = float(rng.uniform(1.0, 8.0))
+        L = max(K + 1, int(sigma * rng.uniform(1.5, 5.0)))
+        h = _abi.morlet_plan(100, sigma, xi0 / sigma, K, L)
+        info = _abi.morlet_plan_info(h, K)
+        _abi.morlet_destroy(h)
+        ps = O.select_PS(sigma, xi0 / sigma, K, L)
+        assert info["P_S"] == ps, (sigma, K, xi0, L)
+        m, l = O.fit_morlet(sigma, xi0 / sigma, K, L, ps)
+        scale = max(np.abs(m).max(), np.abs(l).max())
+        assert np.allclose(info["cos_coef"], m, rtol=1e-9, atol=1e-12 * scale), (sigma, K, xi0, L)
+        assert np.allclose(info["sin_coef"], l, rtol=1e-9, atol=1e-12 * scale), (sigma, K, xi0, L)
+        for order in (1, 2):
+            Kd = min(K, L - 1) if order == 1 else K
+            hd = _abi.morlet_plan_gauss_deriv(100, sigma, Kd, L, order)
+            di = _abi.morlet_plan_info(hd, Kd)
+            _abi.morlet_destroy(hd)
+            c = (O.fit_gauss_d1 if order == 1 else O.fit_gauss_d2)(sigma, Kd, L)
+            got = di["sin_coef"] if order == 1 else di["cos_coef"]
+            assert np.allclose(got, c, rtol=1e-9, atol=1e-12 * np.abs(c).max()), (order, sigma, Kd, L)
