@@ -250,14 +250,43 @@ def plan_gauss(sigma: float, K: int, L: int, mode: str = "sft", n0: int | None =
                 a, np.zeros(K))
 
 
-def plan_gauss_deriv(sigma: float, K: int, L: int, order: int) -> Plan:
-    """Gaussian differential smoothing, SFT (Sec. II-A): order 1 is x_GD with the sine
-    components of orders 1..K, order 2 is x_GDD with the cosine components 0..K-1."""
+def plan_gauss_deriv(sigma: float, K: int, L: int, order: int, mode: str = "sft",
+                     n0: int | None = None) -> Plan:
+    """Gaussian differential smoothing (Sec. II).
+
+    SFT: order 1 is x_GD with the sine components of orders 1..K, order 2 is x_GDD with the
+    cosine components of orders 0..K-1 (G_D is odd, G_DD even).
+
+    ASFT (Sec. II-B, eqs. siftGauss and gddAsft): the K terms are orders 0..K-1 and both
+    components are used. The attenuation e^{-alpha k} with alpha = n0 / sigma^2 moves the
+    Gaussian by n0, G[k + n0] = s e^{-alpha k} G[k] with s = e^{-n0^2/(2 sigma^2)}, and
+    differentiating that identity gives
+        G_D[k + n0]  = s e^{-alpha k} (G_D[k] - alpha G[k]),
+        G_DD[k + n0] = s e^{-alpha k} (G_DD[k] - 2 alpha G_D[k] + alpha^2 G[k]).
+    With G ~ sum a_p cos, G_D ~ sum b_p sin (p >= 1) and G_DD ~ sum d_p cos on [-L, L] the
+    result weights ct_p and st_p by
+        order 1: cos_coef = -alpha a_p,          sin_coef = b_p
+        order 2: cos_coef = d_p + alpha^2 a_p,   sin_coef = -2 alpha b_p
+    (the scale s is applied to the sum, as for the smoothing itself)."""
+    if order not in (1, 2):
+        raise ValueError("order must be 1 or 2")
+    kind = "gd1" if order == 1 else "gd2"
+    if mode == "sft":
+        if order == 1:
+            return Plan(kind, sigma, 0.0, K, L, 1, "sft", 0, np.zeros(K), fit_gauss_d1(sigma, K, L))
+        return Plan(kind, sigma, 0.0, K, L, 0, "sft", 0, fit_gauss_d2(sigma, K, L), np.zeros(K))
+    if mode != "asft":
+        raise ValueError("mode must be 'sft' or 'asft'")
+    if n0 is None:
+        n0 = default_n0(sigma)
+    alpha = n0 / (sigma * sigma)
+    a = fit_gauss(sigma, K, L)
+    b = np.concatenate([[0.0], fit_gauss_d1(sigma, K - 1, L) if K > 1 else np.zeros(0)])
     if order == 1:
-        return Plan("gd1", sigma, 0.0, K, L, 1, "sft", 0, np.zeros(K), fit_gauss_d1(sigma, K, L))
-    if order == 2:
-        return Plan("gd2", sigma, 0.0, K, L, 0, "sft", 0, fit_gauss_d2(sigma, K, L), np.zeros(K))
-    raise ValueError("order must be 1 or 2")
+        cc, sc = -alpha * a, b
+    else:
+        cc, sc = fit_gauss_d2(sigma, K, L) + alpha * alpha * a, -2.0 * alpha * b
+    return Plan(kind, sigma, 0.0, K, L, 0, "asft", int(n0), cc, sc)
 
 
 # --------------------------------------------------------------------------
@@ -281,8 +310,11 @@ def kterm_gauss(plan: Plan) -> np.ndarray:
 
 def kterm_gauss_deriv(plan: Plan) -> np.ndarray:
     """G_D_hat[k] = sum_p b_p sin(beta p k) (order 1) or G_DD_hat[k] = sum_p d_p cos(beta p k)
-    (order 2), k = -L..L (Sec. II-A); real."""
+    (order 2), k = -L..L (Sec. II-A); real. For an ASFT plan, the unattenuated
+    sum_p cos_coef_p cos(beta p k) + sin_coef_p sin(beta p k) that asft_kernel() weights."""
     t = _kterm(plan.cos_coef, plan.sin_coef, plan.P_S, plan.L)
+    if plan.mode == "asft":
+        return t.real + t.imag
     return t.imag if plan.kind == "gd1" else t.real
 
 
@@ -292,7 +324,12 @@ def asft_kernel(plan: Plan) -> np.ndarray:
       h[k] = e^{i xi n0} e^{-n0^2/(2 sigma^2)} e^{-alpha k} khat[k]
     (eqs. siftGauss and GsASFT, Sec. III-A; alpha^2/(4 gamma) = n0^2/(2 sigma^2))."""
     k = np.arange(-plan.L, plan.L + 1, dtype=np.float64)
-    base = kterm_morlet(plan) if plan.kind == "morlet" else kterm_gauss(plan).astype(np.complex128)
+    if plan.kind == "morlet":
+        base = kterm_morlet(plan)
+    elif plan.kind == "gauss":
+        base = kterm_gauss(plan).astype(np.complex128)
+    else:
+        base = kterm_gauss_deriv(plan).astype(np.complex128)
     scale = math.exp(-plan.n0 ** 2 / (2.0 * plan.sigma ** 2))
     ph = np.exp(1j * plan.xi * plan.n0) if plan.kind == "morlet" else 1.0
     return ph * scale * np.exp(-plan.alpha * k) * base
@@ -409,18 +446,24 @@ def forward(x: np.ndarray, plan: Plan) -> np.ndarray:
     Gauss,  ASFT: x_G[n] = e^{-n0^2/(2 sigma^2)} sum_p a_p ct_p[n-n0]  (eq. GsASFT)
     GD,     SFT:  x_GD[n] = sum_{p=1}^{K} b_p s_p[n]                 (Sec. II-A)
     GDD,    SFT:  x_GDD[n] = sum_{p=0}^{K-1} d_p c_p[n]              (Sec. II-A)
+    GD/GDD, ASFT: e^{-n0^2/(2 sigma^2)} sum_{p=0}^{K-1} cos_coef_p ct_p[n-n0]
+                                                 + sin_coef_p st_p[n-n0]  (eq. gddAsft)
     with c - i s = Z, so c = Re Z and s = -Im Z."""
     x = np.asarray(x, dtype=np.float64)
     N = x.shape[0]
     if plan.kind in ("gd1", "gd2"):
-        if plan.mode != "sft":
-            raise ValueError("differential smoothing is built in SFT form only")
         out = np.zeros(N)
         for i, p in enumerate(plan.orders):
             if N == 0:
                 break
-            Z = sft_component(x, int(p), plan.L)
-            out += plan.sin_coef[i] * (-Z.imag) if plan.kind == "gd1" else plan.cos_coef[i] * Z.real
+            if plan.mode == "sft":
+                Z = sft_component(x, int(p), plan.L)
+                out += plan.sin_coef[i] * (-Z.imag) if plan.kind == "gd1" else plan.cos_coef[i] * Z.real
+            else:
+                Zt = asft_component(x, int(p), plan.L, plan.alpha, np.arange(N) - plan.n0)
+                out += plan.cos_coef[i] * Zt.real + plan.sin_coef[i] * (-Zt.imag)
+        if plan.mode == "asft":
+            out *= math.exp(-plan.n0 ** 2 / (2.0 * plan.sigma ** 2))
         return out
     acc = np.zeros(N, dtype=np.complex128)
     if N == 0:
