@@ -101,9 +101,18 @@ morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int
  * gamma = 1/(2 sigma^2), b and d by MMSE on [-L, L] (eq. mmse). Run with gauss_smooth
  * (float32 output). Same argument rules as morlet_plan_gauss, with K <= L for order 1;
  * L = 0 takes the window of the Gaussian fit with the same top order (Table 1 uses one
- * beta for G, G_D and G_DD). SFT only (morlet_plan_set rejects ASFT with
- * MORLET_ERR_UNSUPPORTED), forward only (the backward calls return MORLET_ERR_UNSUPPORTED).
- * morlet_plan_info reports b as sin_coef (order 1) or d as cos_coef (order 2); P_S is 1 or 0.
+ * beta for G, G_D and G_DD). Forward only (the backward calls return
+ * MORLET_ERR_UNSUPPORTED). morlet_plan_info reports b as sin_coef (order 1) or d as
+ * cos_coef (order 2); P_S is 1 or 0.
+ * After morlet_plan_set(..., MORLET_SCAN_ASFT, n0, ...) the plan is refitted for the
+ * attenuated transform (eqs. siftGauss, gddAsft): the K terms become orders 0..K-1 (P_S = 0)
+ * with both components, a_p, b_p, d_p the fits of G (orders 0..K-1), G_D (sines 1..K-1) and
+ * G_DD (cosines 0..K-1), alpha = n0 / sigma^2, s = e^{-n0^2/(2 sigma^2)}:
+ *   order 1: x_GD[n]  = s sum_p (-alpha a_p) ct_p[n-n0] + b_p st_p[n-n0]
+ *   order 2: x_GDD[n] = s sum_p (d_p + alpha^2 a_p) ct_p[n-n0] - 2 alpha b_p st_p[n-n0]
+ * and morlet_plan_info reports those two weight vectors as cos_coef and sin_coef, and as
+ * kernel_relrmse the error of the attenuated taps against G_D[k + n0] (G_DD[k + n0]) on
+ * [-L, L]. Setting SFT again restores the SFT fit.
  * Errors: MORLET_ERR_INVALID_ARG (also for an order other than 1 or 2), MORLET_ERR_ALLOC,
  * MORLET_ERR_HIP. */
 morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigma, int32_t K, int64_t L,
@@ -114,10 +123,13 @@ morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigm
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,
                               morlet_accum accum);
 
-/* Tile shape of the scan kernels: R consecutive samples per thread (16 or 32; 256 threads
- * per block, so a tile covers 256 R scan positions). Default 16. Changes the workspace
- * size; rebuilds the device tables synchronously. Results do not depend on R beyond
- * float32 rounding. */
+/* Tile shape of the scan kernels: R consecutive samples per thread (4, 8, 16 or 32; 256
+ * threads per block, so a tile covers 256 R scan positions). Default 16. Small R gives short
+ * inputs more tiles (more blocks in flight, less serial work per thread); large R amortises
+ * the per-tile carries over more samples. Changes the workspace size; rebuilds the device
+ * tables synchronously. Results do not depend on R beyond float32 rounding.
+ * Errors: MORLET_ERR_UNSUPPORTED for another R or when a batched plan would exceed 2^31
+ * tiles (the plan keeps its tile shape). */
 morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R);
 
 /* How a batched plan's launch distributes its rows (signal x scale) over the persistent
@@ -132,9 +144,10 @@ typedef enum { MORLET_SCHED_AUTO = 0, MORLET_SCHED_TILES = 1, MORLET_SCHED_ROWS 
 morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule schedule);
 
 /* Autotuner: times this plan's forward launch on the caller's input x (device, dtype) for each
- * tile shape (R = 16, 32) and, for a scalogram plan, each schedule (tiles, rows): one warm-up
- * launch, then `reps` launches (1..1000) timed with HIP events on `stream`; keeps the fastest
- * (ties: the earlier candidate) as the plan's tile shape and schedule. out (device) receives the
+ * tile shape (R = 16, 32, 8, 4, in that order; a shape the plan cannot take is skipped) and,
+ * for a scalogram plan, each schedule (tiles, rows): one warm-up launch, then `reps` launches
+ * (1..1000) timed with HIP events on `stream`; keeps the fastest (ties: the earlier
+ * candidate) as the plan's tile shape and schedule. out (device) receives the
  * trial outputs: any buffer of the forward's output size, overwritten. A setup call: it
  * allocates and frees its own workspace and events, rebuilds the tables synchronously and
  * synchronizes the stream, so it must not run under graph capture. R_out, schedule_out

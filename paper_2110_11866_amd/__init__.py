@@ -45,7 +45,7 @@ class _PlanBase:
         return self
 
     def set_tile(self, R: int) -> "_PlanBase":
-        """Samples per thread of the scan kernels (16 or 32)."""
+        """Samples per thread of the scan kernels (4, 8, 16 or 32)."""
         _abi.morlet_plan_set_tile(self.handle, int(R))
         self._ws = None
         return self
@@ -195,16 +195,18 @@ class GaussPlan(_PlanBase):
 
 
 class GaussDerivPlan(GaussPlan):
-    """The Gaussian's differentials applied to the signal (Sec. II-A), SFT, forward only:
-    order 1 gives x_GD (sine components 1..K), order 2 gives x_GDD (cosine components 0..K-1)."""
+    """The Gaussian's differentials applied to the signal (Sec. II), forward only.
+    SFT: order 1 gives x_GD (sine components 1..K), order 2 gives x_GDD (cosine components
+    0..K-1). ASFT (eq. gddAsft): orders 0..K-1 with both components, shifted by n0."""
 
-    def __init__(self, N: int, sigma: float, K: int, L: int = 0, order: int = 1, accum: str = "f32"):
+    def __init__(self, N: int, sigma: float, K: int, L: int = 0, order: int = 1, mode: str = "sft",
+                 n0: int = 0, accum: str = "f32"):
         _PlanBase.__init__(self, _abi.morlet_plan_gauss_deriv(int(N), float(sigma), int(K), int(L), int(order)),
                            int(N), int(K))
         self.sigma = float(sigma)
         self.order = int(order)
-        if accum != "f32":
-            self.set("sft", 0, accum)
+        if mode != "sft" or n0 or accum != "f32":
+            self.set(mode, n0, accum)
 
     def backward(self, *args, **kwargs):
         raise NotImplementedError("no backward pass for differential smoothing plans")

@@ -18,14 +18,23 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
 
 HOST_SOURCES = ["plan.cpp", "api.cpp"]
-DEVICE_SOURCES = ["scan_dispatch.hip", "direct_conv.hip"] + ["scan_k%d.hip" % k for k in range(1, 13)]
+DEVICE_SOURCES = ["scan_dispatch.hip", "direct_conv.hip"]
+# scan kernel instantiation sets: scan_inst.hip once per (terms K, samples per thread R)
+TERMS = range(1, 13)
+TILES = (4, 8, 16, 32)
+INSTANCES = [("scan_inst.hip", k, r) for k in TERMS for r in TILES]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(item) -> str:
+    if isinstance(item, tuple):
+        src, k, r = item
+        obj = os.path.join(BUILD, "scan_k%d_r%d.o" % (k, r))
+        defs = ["-DMK_K=%d" % k, "-DMK_R=%d" % r]
+    else:
+        src, obj, defs = item, os.path.join(BUILD, os.path.splitext(item)[0] + ".o"), []
     path = os.path.join(CSRC, src)
     if src.endswith(".hip"):
-        cmd = [HIPCC, "-c", *COMMON, *DEVICE_FLAGS, "-x", "hip", path, "-o", obj]
+        cmd = [HIPCC, "-c", *COMMON, *DEVICE_FLAGS, *defs, "-x", "hip", path, "-o", obj]
     else:
         cmd = [HIPCC, "-c", *COMMON, *DEVICE_FLAGS, path, "-o", obj]   # host code, same target
     subprocess.run(cmd, check=True)
@@ -35,7 +44,8 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link libmorlet.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    srcs = DEVICE_SOURCES + HOST_SOURCES
+    # the largest instantiation sets first, so the long compiles start early
+    srcs = sorted(INSTANCES, key=lambda t: (-t[1], -t[2])) + DEVICE_SOURCES + HOST_SOURCES
     with ThreadPoolExecutor(max_workers=int(os.environ.get("MAX_JOBS", "8"))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"

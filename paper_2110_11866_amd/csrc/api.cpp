@@ -176,7 +176,9 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   // the gradient pass always accumulates in float64: the chain rule through the fitted
   // coefficients cancels the per-term sums by orders of magnitude
   a.wide = variant == mk::kVarParamGrad ? 1 : plan->accum;
-  a.kind = (plan->kind == 1 && plan->deriv == 1) ? 2 : plan->kind;   // 2: real output from the sines
+  // differentials: 2 real output from the sines (SFT, first), 1 from the cosines (SFT,
+  // second), 3 from both (ASFT)
+  a.kind = plan->deriv == 0 ? plan->kind : plan->mode == MORLET_SCAN_ASFT ? 3 : plan->deriv == 1 ? 2 : 1;
   a.row0.x_off = 0;
   a.row0.w_off = 0;
   a.row0.N = plan->N;
@@ -372,6 +374,82 @@ morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int
   return finish_plan(p, out);
 }
 
+// Coefficients of a differential plan for its scan mode (Sec. II).
+// SFT: the sines 1..K of G_D (order 1) or the cosines 0..K-1 of G_DD (order 2).
+// ASFT (eqs. siftGauss, gddAsft): orders 0..K-1 with both components. The attenuation moves
+// the Gaussian by n0, G[k + n0] = s e^{-alpha k} G[k] (alpha = n0 / sigma^2, s = e^{-n0^2 /
+// (2 sigma^2)}), so G_D[k + n0] = s e^{-alpha k} (G_D - alpha G)[k] and G_DD[k + n0] =
+// s e^{-alpha k} (G_DD - 2 alpha G_D + alpha^2 G)[k]; with G ~ sum a_p cos, G_D ~ sum b_p sin
+// and G_DD ~ sum d_p cos the weights of c_p and s_p are
+//   order 1: cc = -alpha a, sc = b;   order 2: cc = d + alpha^2 a, sc = -2 alpha b.
+// The scale s is the output factor the table already carries for every ASFT plan.
+static void fit_deriv(morlet_plan_s* p) {
+  const int K = p->K;
+  const int64_t L = p->L;
+  std::vector<double> g, none;
+  if (p->mode != MORLET_SCAN_ASFT) {
+    mk::gauss_taps(p->sigma, L, g, p->deriv);
+    mk::Fit f;
+    if (p->deriv == 1) {
+      const std::vector<double> zero(g.size(), 0.0);
+      f = mk::fit_orders(zero, g, L, 1, K);   // odd target: sine components 1..K
+    } else {
+      f = mk::fit_orders(g, none, L, 0, K);   // even target: cosine components 0..K-1
+    }
+    p->P_S = p->deriv == 1 ? 1 : 0;
+    p->cc = f.cc;
+    p->sc = f.sc;
+    p->relrmse = f.relrmse;
+    return;
+  }
+  const double alpha = (double)p->n0 / (p->sigma * p->sigma);
+  mk::gauss_taps(p->sigma, L, g, 0);
+  const std::vector<double> a = mk::fit_orders(g, none, L, 0, K).cc;
+  std::vector<double> b(K, 0.0);
+  if (K > 1) {
+    std::vector<double> gd;
+    mk::gauss_taps(p->sigma, L, gd, 1);
+    const std::vector<double> zero(gd.size(), 0.0);
+    const std::vector<double> bs = mk::fit_orders(zero, gd, L, 1, K - 1).sc;
+    for (int i = 0; i < K - 1; ++i) b[i + 1] = bs[i];
+  }
+  p->P_S = 0;
+  p->cc.assign(K, 0.0);
+  p->sc.assign(K, 0.0);
+  if (p->deriv == 1) {
+    for (int i = 0; i < K; ++i) {
+      p->cc[i] = -alpha * a[i];
+      p->sc[i] = b[i];
+    }
+  } else {
+    std::vector<double> gdd;
+    mk::gauss_taps(p->sigma, L, gdd, 2);
+    const std::vector<double> d = mk::fit_orders(gdd, none, L, 0, K).cc;
+    for (int i = 0; i < K; ++i) {
+      p->cc[i] = d[i] + alpha * alpha * a[i];
+      p->sc[i] = -2.0 * alpha * b[i];
+    }
+  }
+  // relative RMSE of the attenuated taps against the shifted differential on [-L, L]
+  const double s = std::exp(-(double)p->n0 * (double)p->n0 / (2.0 * p->sigma * p->sigma));
+  const double kPi = 3.14159265358979323846;
+  const double gamma = 1.0 / (2.0 * p->sigma * p->sigma), norm = std::sqrt(gamma / kPi);
+  double num = 0.0, den = 0.0;
+  for (int64_t k = -L; k <= L; ++k) {
+    double h = 0.0;
+    for (int i = 0; i < K; ++i) {
+      const double ph = kPi * (double)((i * k) % (2 * L)) / (double)L;
+      h += p->cc[i] * std::cos(ph) + p->sc[i] * std::sin(ph);
+    }
+    h *= s * std::exp(-alpha * (double)k);
+    const double u = (double)(k + p->n0), G = norm * std::exp(-gamma * u * u);
+    const double t = p->deriv == 1 ? -2.0 * gamma * u * G : (4.0 * gamma * gamma * u * u - 2.0 * gamma) * G;
+    num += (h - t) * (h - t);
+    den += t * t;
+  }
+  p->relrmse = den > 0.0 ? std::sqrt(num / den) : 0.0;
+}
+
 morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigma, int32_t K, int64_t L,
                                       int32_t order) {
   if (!out) return fail(MORLET_ERR_INVALID_ARG, "null output handle");
@@ -391,27 +469,13 @@ morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigm
   // L = 0: the window of the Gaussian fit with the same top order (orders 0..K for the first
   // differential's sines 1..K, 0..K-1 for the second's cosines)
   p->L = L ? L : mk::select_L(sigma, 0.0, order == 1 ? K + 1 : K, true);
-  p->P_S = order == 1 ? 1 : 0;
-  std::vector<double> g, zero, none;
-  mk::gauss_taps(sigma, p->L, g, order);
-  mk::Fit f;
-  if (order == 1) {
-    zero.assign(g.size(), 0.0);
-    f = mk::fit_orders(zero, g, p->L, 1, K);   // odd target: sine components 1..K
-  } else {
-    f = mk::fit_orders(g, none, p->L, 0, K);   // even target: cosine components 0..K-1
-  }
-  p->cc = f.cc;
-  p->sc = f.sc;
-  p->relrmse = f.relrmse;
+  fit_deriv(p);
   return finish_plan(p, out);
 }
 
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, morlet_accum accum) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (mode != MORLET_SCAN_SFT && mode != MORLET_SCAN_ASFT) return fail(MORLET_ERR_UNSUPPORTED, "unknown scan mode");
-  if (plan->deriv != 0 && mode != MORLET_SCAN_SFT)
-    return fail(MORLET_ERR_UNSUPPORTED, "differential smoothing is built in SFT form only");
   if (accum != MORLET_ACC_F32 && accum != MORLET_ACC_COMPENSATED)
     return fail(MORLET_ERR_UNSUPPORTED, "unknown accumulation mode");
   if (n0 < 0 || (!plan->batched && n0 > plan->L))
@@ -428,6 +492,7 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
   }
   if (n0 > 0) plan->n0_asft = n0;
   plan->n0 = (mode == MORLET_SCAN_ASFT) ? plan->n0_asft : 0;
+  if (plan->deriv != 0) fit_deriv(plan);   // the term set and weights follow the mode
   std::string err;
   mk::build_table(plan, &err);
   if (plan->d_tab) return upload_table(plan);
@@ -446,7 +511,7 @@ morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule sched
 
 morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
-  if (R != 16 && R != 32) return fail(MORLET_ERR_UNSUPPORTED, "R must be 16 or 32");
+  if (R != 4 && R != 8 && R != 16 && R != 32) return fail(MORLET_ERR_UNSUPPORTED, "R must be 4, 8, 16 or 32");
   if (R == plan->R) return MORLET_OK;
   const int oldR = plan->R;
   plan->R = R;
@@ -499,19 +564,27 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
   if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
   const int oldR = plan->R, oldSched = plan->row_serial;
   struct Cand { int R, rows; };
-  std::vector<Cand> cands = {{16, 0}, {32, 0}};
-  if (plan->batched) cands.insert(cands.end(), {{16, 1}, {32, 1}});
-  // one workspace serves every candidate: the largest of their sizes
+  std::vector<Cand> cands;
+  // one workspace serves every candidate: the largest of their sizes. A tile shape the plan
+  // cannot take (too many tiles for a batched plan) is left out; ties go to the earlier
+  // candidate, so the default shape comes first.
   size_t need = 0;
-  for (int R : {16, 32}) {
+  for (int R : {16, 32, 8, 4}) {
     morlet_status st = morlet_plan_set_tile(plan, R);
     size_t b = 0;
+    if (st == MORLET_ERR_UNSUPPORTED) continue;
     if (st == MORLET_OK) st = morlet_workspace_size(plan, &b);
     if (st != MORLET_OK) {
       (void)morlet_plan_set_tile(plan, oldR);
       return st;
     }
     need = std::max(need, b);
+    cands.push_back({R, 0});
+    if (plan->batched) cands.push_back({R, 1});
+  }
+  if (cands.empty()) {
+    (void)morlet_plan_set_tile(plan, oldR);
+    return fail(MORLET_ERR_UNSUPPORTED, "autotune: no tile shape fits this plan");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* ws = nullptr;

@@ -12,37 +12,28 @@
 namespace mk {
 
 using KernelFn = void (*)(ScanLaunch);
-KernelFn select_scan_k1(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k2(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k3(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k4(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k5(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k6(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k7(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k8(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k9(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k10(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k11(int R, int var, int wide, int gauss, int mom, int dt);
-KernelFn select_scan_k12(int R, int var, int wide, int gauss, int mom, int dt);
+// Selectors of the per-(K, R) instantiation sets, one object each (scan_inst.hip).
+using SelectFn = KernelFn (*)(int var, int wide, int kind, int mom, int dt);
+#define MK_DECL_R(K) \
+  KernelFn select_scan_k##K##_r4(int, int, int, int, int); KernelFn select_scan_k##K##_r8(int, int, int, int, int); \
+  KernelFn select_scan_k##K##_r16(int, int, int, int, int); KernelFn select_scan_k##K##_r32(int, int, int, int, int);
+MK_DECL_R(1) MK_DECL_R(2) MK_DECL_R(3) MK_DECL_R(4) MK_DECL_R(5) MK_DECL_R(6)
+MK_DECL_R(7) MK_DECL_R(8) MK_DECL_R(9) MK_DECL_R(10) MK_DECL_R(11) MK_DECL_R(12)
+#undef MK_DECL_R
 
 namespace {
 
-KernelFn select_kernel(int K, int R, int var, int wide, int gauss, int mom, int dt) {
-  switch (K) {
-    case 1: return select_scan_k1(R, var, wide, gauss, mom, dt);
-    case 2: return select_scan_k2(R, var, wide, gauss, mom, dt);
-    case 3: return select_scan_k3(R, var, wide, gauss, mom, dt);
-    case 4: return select_scan_k4(R, var, wide, gauss, mom, dt);
-    case 5: return select_scan_k5(R, var, wide, gauss, mom, dt);
-    case 6: return select_scan_k6(R, var, wide, gauss, mom, dt);
-    case 7: return select_scan_k7(R, var, wide, gauss, mom, dt);
-    case 8: return select_scan_k8(R, var, wide, gauss, mom, dt);
-    case 9: return select_scan_k9(R, var, wide, gauss, mom, dt);
-    case 10: return select_scan_k10(R, var, wide, gauss, mom, dt);
-    case 11: return select_scan_k11(R, var, wide, gauss, mom, dt);
-    case 12: return select_scan_k12(R, var, wide, gauss, mom, dt);
-    default: return nullptr;
-  }
+// index of a supported tile shape: R = 4, 8, 16, 32 -> 0..3, else -1
+int r_index(int R) { return R == 4 ? 0 : R == 8 ? 1 : R == 16 ? 2 : R == 32 ? 3 : -1; }
+
+KernelFn select_kernel(int K, int R, int var, int wide, int kind, int mom, int dt) {
+#define MK_ROW(K) {select_scan_k##K##_r4, select_scan_k##K##_r8, select_scan_k##K##_r16, select_scan_k##K##_r32}
+  static const SelectFn table[kMaxTerms][4] = {MK_ROW(1), MK_ROW(2), MK_ROW(3), MK_ROW(4),  MK_ROW(5),  MK_ROW(6),
+                                               MK_ROW(7), MK_ROW(8), MK_ROW(9), MK_ROW(10), MK_ROW(11), MK_ROW(12)};
+#undef MK_ROW
+  const int ri = r_index(R);
+  if (K < 1 || K > kMaxTerms || ri < 0) return nullptr;
+  return table[K - 1][ri](var, wide, kind, mom, dt);
 }
 
 __global__ void zero_fill_kernel(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
@@ -146,11 +137,11 @@ hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s)
 int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int dtype) {
   // resident blocks per CU of one kernel instantiation; queried once per instantiation (every
   // device this library runs on is a gfx950) and kept, so launches make no runtime query
-  static std::atomic<int> cache[kMaxTerms + 1][2][3][2][3][2][3];
-  if (K < 1 || K > kMaxTerms || (R != 16 && R != 32) || variant < 0 || variant > 2 || wide < 0 || wide > 1 ||
-      kind < 0 || kind > 2 || mom < 0 || mom > 1 || dtype < 0 || dtype > 2)
+  static std::atomic<int> cache[kMaxTerms + 1][4][3][2][4][2][3];
+  if (K < 1 || K > kMaxTerms || r_index(R) < 0 || variant < 0 || variant > 2 || wide < 0 || wide > 1 ||
+      kind < 0 || kind > 3 || mom < 0 || mom > 1 || dtype < 0 || dtype > 2)
     return 0;
-  std::atomic<int>& slot = cache[K][R == 32][variant][wide][kind][mom][variant == kVarAdjoint ? 0 : dtype];
+  std::atomic<int>& slot = cache[K][r_index(R)][variant][wide][kind][mom][variant == kVarAdjoint ? 0 : dtype];
   const int known = slot.load(std::memory_order_relaxed);
   if (known > 0) return known;
   KernelFn fn = select_kernel(K, R, variant, wide, kind, mom, variant == kVarAdjoint ? 0 : dtype);

@@ -1,0 +1,17 @@
+// One (K, R) set of scan kernel instantiations (see scan_kernel.h). The build compiles this
+// file once per pair, with -DMK_K=<terms> -DMK_R=<samples per thread>, so the pairs build in
+// parallel.
+#include "scan_kernel.h"
+
+#if !defined(MK_K) || !defined(MK_R)
+#error "compile with -DMK_K=<1..12> -DMK_R=<4|8|16|32>"
+#endif
+
+#define MK_SELECT_NAME_(k, r) select_scan_k##k##_r##r
+#define MK_SELECT_NAME(k, r) MK_SELECT_NAME_(k, r)
+
+namespace mk {
+KernelFn MK_SELECT_NAME(MK_K, MK_R)(int var, int wide, int kind, int mom, int dt) {
+  return pick_scan<MK_K, MK_R>(var, wide, kind, mom, dt);
+}
+}  // namespace mk

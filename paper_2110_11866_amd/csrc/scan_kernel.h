@@ -72,14 +72,16 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
 
 // KIND: 0 Morlet (complex64 out); 1 real output from the cosine components (Gaussian
 // smoothing, its second differential); 2 real output from the sine components (the
-// Gaussian's first differential, forward only)
+// Gaussian's first differential, forward only); 3 real output from both components (the
+// differentials by the attenuated transform, forward only)
 template <int VAR, int K, int R, bool WIDE, int KIND, bool MOM, int DT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR == kFwd && !WIDE && R == 16) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR == kFwd && !WIDE && R <= 16) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
   using acc_t = typename std::conditional<WIDE, double, float>::type;
   constexpr int T = R * kThreads;
   constexpr bool GAUSS = KIND != 0;                      // real output
   constexpr bool SINE = KIND == 2;
-  static_assert(!SINE || VAR == kFwd, "sine-component output only in the forward scan");
+  constexpr bool MIXED = KIND == 3;
+  static_assert(!(SINE || MIXED) || VAR == kFwd, "sine-component output only in the forward scan");
   constexpr int NS = (VAR == kAdj && !GAUSS) ? 2 : 1;   // real input streams
   constexpr int KS = (NS == 2 || MOM) ? 2 * K : K;      // complex states per position
   constexpr int NRED = 4 * K + 3;                        // kPg partial sums per tile
@@ -101,8 +103,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
   // slot is written).
   constexpr bool kCplxOut = VAR == kFwd && !GAUSS;
   // R = 32: the adjoint's pairs would take 132 KB (one block per CU), the gradient pass's 66 KB
-  constexpr bool kStash = VAR == kFwd || (VAR != kFwd && R == 16);
-  constexpr int kSub = 16;                                  // positions per thread per store round
+  constexpr bool kStash = VAR == kFwd || (VAR != kFwd && R <= 16);
+  constexpr int kSub = R < 16 ? R : 16;                     // positions per thread per store round
   static_assert(R % kSub == 0, "R must be a multiple of the store sub-run");
   constexpr int kStride = (kStash ? 2 * NS * R : kSub * (kCplxOut ? 2 : 1)) + 4;   // floats per thread
   __shared__ __align__(16) float s_out[kWaves][(VAR == kPg && !kStash) ? 4 : 64 * kStride];
@@ -708,7 +710,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
                 vr[i] = nr;
                 vi[i] = ni;
                 if (!SINE) A[s] = fma(tab.row(lay.rMW(), t), nr, A[s]);
-                if (!GAUSS || SINE) B[s] = fma(tab.row(lay.rLW(), t), ni, B[s]);
+                if (!GAUSS || SINE || MIXED) B[s] = fma(tab.row(lay.rLW(), t), ni, B[s]);
               }
             }
             if constexpr (VAR == kFwd && !GAUSS) {
@@ -717,6 +719,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
             } else if constexpr (SINE) {
               // sum_p b_p s_p with s_p = -(-1)^p e^{alpha L} Im v_p (the y[j-2L] term is real)
               o0[r] = (float)(-gre * B[0]);
+            } else if constexpr (MIXED) {
+              // sum_p cc_p c_p + sc_p s_p
+              o0[r] = (float)(gre * (A[0] - B[0]));
             } else if constexpr (VAR == kFwd || GAUSS) {
               o0[r] = (float)(gre * A[0]);
             } else {
@@ -866,7 +871,7 @@ KernelFn pick_scan(int var, int wide, int gauss, int mom, int dt) {
   if (var == V && wide == W && gauss == G && mom == M && dt == D) return (KernelFn)scan_kernel<V, K, R, W, G, M, D>;
 #define MK_PICK_DT(V, W, G, M) MK_PICK(V, W, G, M, 0) MK_PICK(V, W, G, M, 1) MK_PICK(V, W, G, M, 2)
   MK_PICK_DT(kFwd, 0, 0, 0) MK_PICK_DT(kFwd, 0, 1, 0) MK_PICK_DT(kFwd, 1, 0, 0) MK_PICK_DT(kFwd, 1, 1, 0)
-  MK_PICK_DT(kFwd, 0, 2, 0) MK_PICK_DT(kFwd, 1, 2, 0)
+  MK_PICK_DT(kFwd, 0, 2, 0) MK_PICK_DT(kFwd, 1, 2, 0) MK_PICK_DT(kFwd, 0, 3, 0) MK_PICK_DT(kFwd, 1, 3, 0)
   MK_PICK(kAdj, 0, 0, 0, 0) MK_PICK(kAdj, 0, 1, 0, 0) MK_PICK(kAdj, 1, 0, 0, 0) MK_PICK(kAdj, 1, 1, 0, 0)
   MK_PICK_DT(kPg, 1, 0, 0) MK_PICK_DT(kPg, 1, 1, 0) MK_PICK_DT(kPg, 1, 0, 1) MK_PICK_DT(kPg, 1, 1, 1)
 #undef MK_PICK_DT

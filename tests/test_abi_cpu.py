@@ -89,12 +89,44 @@ def test_differential_plan_errors():
     assert L.morlet_plan_gauss_deriv(ctypes.byref(h), 100, 4.0, 6, 5, 2) == _abi.MORLET_OK
     hp = h.value
     try:
-        assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 0, 0) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 6, 0) == _abi.MORLET_ERR_INVALID_ARG   # n0 > L
         assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_SFT, 0, 1) == _abi.MORLET_OK
         fake = 1 << 20
         assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 0, 0) == _abi.MORLET_OK
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
     finally:
         _abi.morlet_destroy(hp)
+
+
+def test_asft_differential_plans_match_oracle():
+    # refit on morlet_plan_set(ASFT): orders 0..K-1, both weight vectors as eq. gddAsft gives
+    # them, the reported error that of the attenuated taps against the shifted differential;
+    # SFT again restores the SFT fit
+    for sigma, K, L, n0 in [(16.0, 4, 64, 2), (60.0, 6, 256, 10), (3.0, 5, 9, 1), (40.0, 1, 120, 5)]:
+        for order in (1, 2):
+            h = _abi.morlet_plan_gauss_deriv(100, sigma, K, L, order)
+            try:
+                _abi.morlet_plan_set(h, _abi.MORLET_SCAN_ASFT, n0, 0)
+                info = _abi.morlet_plan_info(h, K)
+                pl = O.plan_gauss_deriv(sigma, K, L, order, mode="asft", n0=n0)
+                assert info["P_S"] == 0 and info["n0"] == n0
+                assert abs(info["alpha"] - n0 / sigma ** 2) < 1e-15
+                scale = max(np.abs(pl.cos_coef).max(), np.abs(pl.sin_coef).max())
+                assert np.allclose(info["cos_coef"], pl.cos_coef, rtol=1e-9, atol=1e-12 * scale), (order, sigma, K)
+                assert np.allclose(info["sin_coef"], pl.sin_coef, rtol=1e-9, atol=1e-12 * scale), (order, sigma, K)
+                k = np.arange(-L, L + 1)
+                want = (O.gaussian_d1 if order == 1 else O.gaussian_d2)(sigma, k + n0)
+                err = np.linalg.norm(O.asft_kernel(pl).real - want) / np.linalg.norm(want)
+                assert abs(info["kernel_relrmse"] / err - 1) < 1e-8, (info["kernel_relrmse"], err)
+                _abi.morlet_plan_set(h, _abi.MORLET_SCAN_SFT, 0, 0)
+                info = _abi.morlet_plan_info(h, K)
+                c = (O.fit_gauss_d1 if order == 1 else O.fit_gauss_d2)(sigma, K, L)
+                assert info["P_S"] == (1 if order == 1 else 0)
+                assert np.allclose(info["sin_coef"] if order == 1 else info["cos_coef"], c, rtol=1e-9,
+                                   atol=1e-12 * np.abs(c).max())
+            finally:
+                _abi.morlet_destroy(h)
 
 
 def test_jacobian_matches_oracle():
@@ -220,3 +252,19 @@ def test_plan_sweep_matches_oracle():
             c = (O.fit_gauss_d1 if order == 1 else O.fit_gauss_d2)(sigma, Kd, L)
             got = di["sin_coef"] if order == 1 else di["cos_coef"]
             assert np.allclose(got, c, rtol=1e-9, atol=1e-12 * np.abs(c).max()), (order, sigma, Kd, L)
+
+
+def test_tile_shapes_and_workspace():
+    # R in {4, 8, 16, 32}; the tile count (and the workspace's tile states) scales with 1/R
+    L = _abi.lib()
+    h = _abi.morlet_plan(100000, 50.0, 6.0 / 50.0, 5, 200)
+    try:
+        sizes = {}
+        for R in (4, 8, 16, 32):
+            assert L.morlet_plan_set_tile(h, R) == _abi.MORLET_OK
+            sizes[R] = _abi.morlet_workspace_size(h)
+        for R in (0, 2, 12, 64):
+            assert L.morlet_plan_set_tile(h, R) == _abi.MORLET_ERR_UNSUPPORTED
+        assert sizes[4] > sizes[8] > sizes[16] > sizes[32]
+    finally:
+        _abi.morlet_destroy(h)

@@ -39,7 +39,8 @@ def _oracle_plan(kind, sigma, K, info, mode):
     return O.plan_gauss(sigma, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None)
 
 
-CASES = [(1024, 16.0, 4, 64, 16), (50000, 300.0, 6, 1200, 16), (9000, 40.0, 5, 0, 16), (70001, 300.0, 5, 1200, 32)]
+CASES = [(1024, 16.0, 4, 64, 16), (50000, 300.0, 6, 1200, 16), (9000, 40.0, 5, 0, 16), (70001, 300.0, 5, 1200, 32),
+         (20000, 100.0, 5, 400, 8), (5000, 30.0, 4, 0, 4)]
 
 
 @pytest.mark.parametrize("accum", ["f32", "compensated"])

@@ -189,18 +189,37 @@ def test_tile32_parity(N, sigma, K, L, dtype, kind, mode, accum):
     assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
 
 
+@pytest.mark.parametrize("tile", [4, 8])
+@pytest.mark.parametrize("mode,accum", MODES)
+@pytest.mark.parametrize("kind", ["morlet", "gauss"])
+@pytest.mark.parametrize("N,sigma,K,L,dtype", [(50000, 300.0, 6, 1200, torch.float32),
+                                               (77777, 2000.0, 3, 8000, torch.bfloat16),
+                                               (9000, 1.5, 12, 12, torch.float16),
+                                               (1, 4.0, 2, 16, torch.float32),
+                                               (4099, 40.0, 5, 0, torch.float32)])
+def test_small_tile_parity(N, sigma, K, L, dtype, kind, mode, accum, tile):
+    # 4 or 8 positions per thread (1024- or 2048-position tiles, one store sub-run per thread)
+    _announce("small-tile", tile, N, sigma, K, L, dtype, kind, mode, accum)
+    x = np.random.default_rng(N + K + tile).standard_normal(N).astype(np.float32)
+    (got,), info, xu = run_gpu(x, kind, sigma, K, L, mode=mode, accum=accum, dtype=dtype, tile=tile)
+    want, _ = oracle_of(xu, kind, sigma, K, L, info, mode)
+    assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
+
+
+@pytest.mark.parametrize("tile", [16, 4])
 @pytest.mark.parametrize("mode", ["sft", "asft"])
-def test_paper_scale_within_truncation_bound_of_direct(mode):
+def test_paper_scale_within_truncation_bound_of_direct(mode, tile):
     # N = 102400, sigma = 8192, K = 6, L = 32768: the K-term result against the exact Morlet
     # convolution on [-L, L] (oracle, FFT convolution) is held to the oracle's own K-term
     # truncation error plus the float32 bar, ||W_gpu - W_dir|| <= ||W_K - W_dir|| + 1e-5 ||W_K||;
     # the GPU direct convolution of the same window matches the oracle's within 1e-5
     import paper_2110_11866_amd as M
-    _announce("paper-scale-vs-direct", mode)
+    _announce("paper-scale-vs-direct", mode, tile)
     N, sigma, K, L = 102400, 8192.0, 6, 32768
     x = workloads.paper_scale_signal(N)
     xt = torch.from_numpy(x).cuda()
     plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode)
+    plan.set_tile(tile)
     got = plan.forward(xt).cpu().numpy().astype(np.complex128)
     gdir = plan.direct(xt, L).cpu().numpy().astype(np.complex128)
     torch.cuda.synchronize()
@@ -211,6 +230,7 @@ def test_paper_scale_within_truncation_bound_of_direct(mode):
     wdir = O.forward_direct(xd, sigma, 6.0 / sigma, L)
     trunc = np.linalg.norm(wk - wdir)
     print(f"[result] {mode}: K-term vs direct {trunc / np.linalg.norm(wdir):.3e}", flush=True)
+    assert rel_l2(got, wk) <= 1e-5, rel_l2(got, wk)
     assert np.linalg.norm(got - wdir) <= trunc + 1e-5 * np.linalg.norm(wk)
     assert rel_l2(gdir, wdir) <= 1e-5, rel_l2(gdir, wdir)
 
@@ -222,6 +242,8 @@ def test_paper_scale_within_truncation_bound_of_direct(mode):
     (77777, 2000.0, 5, 0, 32, torch.bfloat16, "f32"),
     (9000, 1.5, 12, 12, 16, torch.float16, "f32"),
     (50000, 300.0, 6, 1200, 16, torch.float32, "compensated"),
+    (30000, 100.0, 5, 0, 8, torch.float32, "f32"),
+    (3000, 12.0, 3, 0, 4, torch.float32, "f32"),
 ])
 def test_gaussian_differential_parity(N, sigma, K, L, tile, dtype, accum, order):
     # x_GD (sine components 1..K) and x_GDD (cosine components 0..K-1), SFT (Sec. II-A)
@@ -235,6 +257,35 @@ def test_gaussian_differential_parity(N, sigma, K, L, tile, dtype, accum, order)
     torch.cuda.synchronize()
     info = plan.info()
     p = O.plan_gauss_deriv(sigma, K, info["L"], order)
+    want = O.forward(xt.double().cpu().numpy(), p)
+    assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("N,sigma,K,L,n0,tile,dtype,accum", [
+    (1024, 16.0, 4, 64, 2, 16, torch.float32, "f32"),
+    (200, 66.0, 5, 256, 10, 16, torch.float32, "f32"),        # Table 1's setup, N < L
+    (50000, 300.0, 6, 1200, 0, 16, torch.float32, "f32"),
+    (77777, 2000.0, 5, 0, 0, 32, torch.bfloat16, "f32"),
+    (9000, 3.0, 6, 12, 1, 16, torch.float16, "f32"),
+    (4099, 40.0, 1, 120, 5, 16, torch.float32, "f32"),         # one term: cosine of order 0 only
+    (50000, 300.0, 6, 1200, 0, 32, torch.float32, "compensated"),
+    (30000, 100.0, 5, 0, 0, 8, torch.float32, "f32"),
+    (3000, 12.0, 3, 0, 2, 4, torch.float32, "f32"),
+])
+def test_gaussian_differential_asft_parity(N, sigma, K, L, n0, tile, dtype, accum, order):
+    # x_GD and x_GDD by the attenuated transform (eq. gddAsft): orders 0..K-1, both components
+    import paper_2110_11866_amd as M
+    _announce("gauss-deriv-asft", order, N, sigma, K, L, n0, tile, dtype, accum)
+    x = np.random.default_rng(N + 3 * order).standard_normal(N).astype(np.float32)
+    xt = torch.from_numpy(x).to("cuda").to(dtype)
+    plan = M.GaussDerivPlan(N, sigma, K, L, order=order, mode="asft", n0=n0, accum=accum)
+    plan.set_tile(tile)
+    got = plan.forward(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    info = plan.info()
+    assert info["P_S"] == 0 and info["n0"] >= 1
+    p = O.plan_gauss_deriv(sigma, K, info["L"], order, mode="asft", n0=info["n0"])
     want = O.forward(xt.double().cpu().numpy(), p)
     assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
 

@@ -48,7 +48,7 @@ def _check_rows(plan, W, x_used, rows, mode, tol):
 
 
 @pytest.mark.parametrize("schedule", ["tiles", "rows"])
-@pytest.mark.parametrize("tile", [16, 32])
+@pytest.mark.parametrize("tile", [4, 8, 16, 32])
 @pytest.mark.parametrize("mode,accum,tol", [("sft", "f32", 1e-5), ("asft", "f32", 1e-5), ("asft", "compensated", 1e-6)])
 def test_small_ragged_batch_all_rows(mode, accum, tol, tile, schedule):
     # ragged lengths including empty, shorter than the window, and multi-tile signals
