@@ -30,7 +30,11 @@ are listed, with evidence, in the design notes of the repository):
     and the output is read n0 samples earlier (eqs. asfiir12K, GsASFT);
   * the Morlet ASFT formula of Sec. III-A is completed with the carrier phase
     e^{i xi n0} that the shift of eq. siftGauss introduces;
-  * x is zero outside [0, N-1] (one of the two extensions Sec. II names).
+  * x is zero outside [0, N-1] (one of the two extensions Sec. II names);
+  * the multiplication method (Sec. III-B) multiplies the carrier by the fit of
+    the wavelet's own envelope e^{-n^2/(2 sigma^2)}, i.e. the a_p of eq.
+    aproGauss divided by sqrt(gamma/pi), its kappa term is subtracted, and in
+    ASFT form only the carrier part takes the phase e^{i xi n0}.
 """
 from __future__ import annotations
 
@@ -47,6 +51,7 @@ __all__ = [
     "select_PS", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
     "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
     "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
+    "plan_multiply", "kterm_multiply", "freq_component",
 ]
 
 
@@ -130,7 +135,8 @@ def dpsi_dtheta(sigma: float, xi: float, k: np.ndarray) -> tuple[np.ndarray, np.
 # --------------------------------------------------------------------------
 @dataclass
 class Plan:
-    kind: str                 # "morlet", "gauss", "gd1" or "gd2" (Gaussian differentials)
+    kind: str                 # "morlet", "gauss", "gd1", "gd2" (Gaussian differentials) or
+                              # "mult" (Morlet by the multiplication method)
     sigma: float
     xi: float                 # rad/sample (0 for the Gaussian)
     K: int                    # number of Fourier terms
@@ -289,6 +295,18 @@ def plan_gauss_deriv(sigma: float, K: int, L: int, order: int, mode: str = "sft"
     return Plan(kind, sigma, 0.0, K, L, 0, "asft", int(n0), cc, sc)
 
 
+def plan_multiply(sigma: float, xi: float, P_M: int, L: int, mode: str = "sft",
+                  n0: int | None = None) -> Plan:
+    """Morlet wavelet by the multiplication method (Sec. III-B): the Gaussian envelope fitted
+    with the cosines of orders 0..P_M (K = P_M + 1 terms; cos_coef holds the a_p of eq.
+    aproGauss), multiplied by the carrier."""
+    a = fit_gauss(sigma, P_M + 1, L)
+    if mode == "asft" and n0 is None:
+        n0 = default_n0(sigma)
+    return Plan("mult", sigma, xi, P_M + 1, L, 0, mode, int(n0 or 0) if mode == "asft" else 0,
+                a, np.zeros(P_M + 1))
+
+
 # --------------------------------------------------------------------------
 # The K-term kernels as explicit taps (plain definitions the method equals)
 # --------------------------------------------------------------------------
@@ -318,12 +336,34 @@ def kterm_gauss_deriv(plan: Plan) -> np.ndarray:
     return t.imag if plan.kind == "gd1" else t.real
 
 
+def _mult_scale(plan: Plan) -> tuple[float, float]:
+    """C_xi / (pi^(1/4) sqrt(sigma)) / sqrt(gamma/pi) (the envelope is G / sqrt(gamma/pi)) and
+    kappa_xi, for the multiplication method."""
+    C, kappa = _morlet_consts(plan.xi * plan.sigma)
+    gamma = 1.0 / (2.0 * plan.sigma * plan.sigma)
+    return C / (math.pi ** 0.25 * math.sqrt(plan.sigma)) / math.sqrt(gamma / math.pi), kappa
+
+
+def kterm_multiply(plan: Plan) -> np.ndarray:
+    """psi_hat_M[k] = C' (e^{i xi k} - kappa) G_hat[k], k = -L..L (Sec. III-B): the sum
+    sum_{p=-P}^{P} a'_p e^{i omega_p k} with omega_p = xi + beta p equals e^{i xi k} G_hat[k]."""
+    ce, kappa = _mult_scale(plan)
+    k = np.arange(-plan.L, plan.L + 1, dtype=np.float64)
+    return ce * (np.exp(1j * plan.xi * k) - kappa) * kterm_gauss(plan)
+
+
 def asft_kernel(plan: Plan) -> np.ndarray:
     """Taps h[k], k = -L..L, of the ASFT result written as a plain convolution
     y[n] = sum_k h[k] x[n - n0 - k]:
       h[k] = e^{i xi n0} e^{-n0^2/(2 sigma^2)} e^{-alpha k} khat[k]
     (eqs. siftGauss and GsASFT, Sec. III-A; alpha^2/(4 gamma) = n0^2/(2 sigma^2))."""
     k = np.arange(-plan.L, plan.L + 1, dtype=np.float64)
+    if plan.kind == "mult":
+        # only the carrier part is shifted: ce s e^{-alpha k} (e^{i xi (k + n0)} - kappa) G_hat[k]
+        ce, kappa = _mult_scale(plan)
+        scale = math.exp(-plan.n0 ** 2 / (2.0 * plan.sigma ** 2))
+        return (ce * scale * np.exp(-plan.alpha * k) * (np.exp(1j * plan.xi * (k + plan.n0)) - kappa)
+                * kterm_gauss(plan))
     if plan.kind == "morlet":
         base = kterm_morlet(plan)
     elif plan.kind == "gauss":
@@ -436,6 +476,58 @@ def asft_component(x: np.ndarray, p: int, L: int, alpha: float, q: np.ndarray) -
     return math.exp(alpha * L) * np.conj(phase(p, q, L)) * diff
 
 
+def freq_component(x: np.ndarray, omega: float, L: int, alpha: float, q: np.ndarray) -> np.ndarray:
+    """Component at a real frequency (Sec. III-B), Z(omega)[q] = c(omega)[q] - i s(omega)[q]
+    = sum_{k=-L}^{L} x[q-k] e^{-alpha k} e^{-i omega k} (alpha = 0: SFT), by the kernel integral
+    of asft_component() with the phase e^{i omega j} evaluated in float64."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    j = np.arange(N)
+    ut = lfilter([1.0], [1.0, -math.exp(-alpha)], x * np.exp(1j * omega * j))
+
+    def U(idx):
+        idx = np.asarray(idx)
+        out = np.zeros(idx.shape, dtype=np.complex128)
+        inr = (idx >= 0) & (idx < N)
+        out[inr] = ut[idx[inr]]
+        hi = idx >= N
+        out[hi] = ut[N - 1] * np.exp(-alpha * (idx[hi] - (N - 1)))
+        return out
+
+    q = np.asarray(q, dtype=np.int64)
+    diff = U(q + L) - math.exp(-alpha * (2 * L + 1)) * U(q - L - 1)
+    return math.exp(alpha * L) * np.exp(-1j * omega * q) * diff
+
+
+def _forward_multiply(x: np.ndarray, plan: Plan) -> np.ndarray:
+    """x_M[n] = C' [ sum_{p=-P}^{P} a'_p (c(omega_p) + i s(omega_p)) - kappa sum_{p=0}^{P} a_p c_p ]
+    with a'_0 = a_0, a'_{+-p} = a_p / 2 and omega_p = xi + beta p (Sec. III-B). For real x,
+    c(omega) + i s(omega) = conj Z(omega). ASFT: the components are the attenuated ones read at
+    n - n0, the sum is scaled by e^{-n0^2/(2 sigma^2)} and the carrier sum by e^{i xi n0}."""
+    N = x.shape[0]
+    if N == 0:
+        return np.zeros(0, dtype=np.complex128)
+    q = np.arange(N) - plan.n0
+    P = plan.K - 1
+    a = plan.cos_coef
+    carrier = np.zeros(N, dtype=np.complex128)
+    for p in range(-P, P + 1):
+        ap = a[0] if p == 0 else 0.5 * a[abs(p)]
+        carrier += ap * np.conj(freq_component(x, plan.xi + plan.beta * p, plan.L, plan.alpha, q))
+    gauss = np.zeros(N)
+    for p in range(P + 1):
+        if plan.mode == "sft":
+            Z = sft_component(x, p, plan.L)
+        else:
+            Z = asft_component(x, p, plan.L, plan.alpha, q)
+        gauss += a[p] * Z.real
+    ce, kappa = _mult_scale(plan)
+    if plan.mode == "asft":
+        s = math.exp(-plan.n0 ** 2 / (2.0 * plan.sigma ** 2))
+        return ce * s * (np.exp(1j * plan.xi * plan.n0) * carrier - kappa * gauss)
+    return ce * (carrier - kappa * gauss)
+
+
 def forward(x: np.ndarray, plan: Plan) -> np.ndarray:
     """Method result.
 
@@ -448,9 +540,12 @@ def forward(x: np.ndarray, plan: Plan) -> np.ndarray:
     GDD,    SFT:  x_GDD[n] = sum_{p=0}^{K-1} d_p c_p[n]              (Sec. II-A)
     GD/GDD, ASFT: e^{-n0^2/(2 sigma^2)} sum_{p=0}^{K-1} cos_coef_p ct_p[n-n0]
                                                  + sin_coef_p st_p[n-n0]  (eq. gddAsft)
+    Mult:         _forward_multiply (Sec. III-B)
     with c - i s = Z, so c = Re Z and s = -Im Z."""
     x = np.asarray(x, dtype=np.float64)
     N = x.shape[0]
+    if plan.kind == "mult":
+        return _forward_multiply(x, plan)
     if plan.kind in ("gd1", "gd2"):
         out = np.zeros(N)
         for i, p in enumerate(plan.orders):

@@ -584,3 +584,115 @@ def test_asft_differentials_close_to_direct():
                 / np.linalg.norm(direct) for K in (3, 5, 7)]
         assert errs[0] > errs[1] > errs[2] and errs[2] < 5e-3, errs
 
+
+
+# ---------------------------------------------------------------- multiplication method
+def _mult_taps_from_sum(pl):
+    """Taps of Sec. III-B written out term by term, as (carrier, kappa part):
+    C' sum_{p=-P}^{P} a'_p e^{i omega_p k} with omega_p = xi + beta p, and
+    -C' kappa sum_{p=0}^{P} a_p cos(beta p k), on the envelope's scale."""
+    L, P = pl.L, pl.K - 1
+    xi0 = pl.xi * pl.sigma
+    C = (1 + math.exp(-xi0 ** 2) - 2 * math.exp(-0.75 * xi0 ** 2)) ** -0.5
+    kappa = math.exp(-0.5 * xi0 ** 2)
+    ce = C / (math.pi ** 0.25 * math.sqrt(pl.sigma)) / math.sqrt(1.0 / (2 * pl.sigma ** 2) / math.pi)
+    car = np.zeros(2 * L + 1, dtype=np.complex128)
+    kap = np.zeros(2 * L + 1)
+    for j, kk in enumerate(range(-L, L + 1)):
+        for p in range(-P, P + 1):
+            ap = pl.cos_coef[0] if p == 0 else 0.5 * pl.cos_coef[abs(p)]
+            w = (pl.xi + math.pi * p / L) * kk
+            car[j] += ce * ap * complex(math.cos(w), math.sin(w))
+        for p in range(P + 1):
+            kap[j] -= ce * kappa * pl.cos_coef[p] * math.cos(math.pi * p * kk / L)
+    return car, kap
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+@pytest.mark.parametrize("N,sigma,xi0,L,PM", [(1, 3.0, 6.0, 9, 2), (37, 4.0, 2.0, 12, 3), (64, 6.0, 6.0, 20, 4),
+                                              (50, 2.0, 1.0, 5, 2)])
+def test_multiply_recurrence_equals_brute_force(mode, N, sigma, xi0, L, PM):
+    # SFT: taps car + kap; ASFT: s e^{-alpha k} (e^{i xi n0} car + kap), read n0 earlier
+    rng = np.random.default_rng(N + PM)
+    x = rng.standard_normal(N)
+    pl = O.plan_multiply(sigma, xi0 / sigma, PM, L, mode=mode, n0=2 if mode == "asft" else None)
+    car, kap = _mult_taps_from_sum(pl)
+    if mode == "sft":
+        taps = car + kap
+    else:
+        k = np.arange(-L, L + 1)
+        s = math.exp(-pl.n0 ** 2 / (2 * sigma ** 2))
+        taps = s * np.exp(-pl.n0 / sigma ** 2 * k) * (np.exp(1j * pl.xi * pl.n0) * car + kap)
+    want = _brute(x.astype(np.complex128), taps, L, pl.n0)
+    assert np.allclose(O.forward(x, pl), want, rtol=1e-11, atol=1e-13)
+
+
+def _best_relrmse(fn, Ls):
+    return min(fn(L) for L in Ls)
+
+
+def _mult_kernel_err(sigma, xi0, PM, L):
+    pl = O.plan_multiply(sigma, xi0 / sigma, PM, L)
+    k = np.arange(-5 * L, 5 * L + 1)
+    t = np.zeros(len(k), dtype=np.complex128)
+    t[np.abs(k) <= L] = O.kterm_multiply(pl)
+    psi = O.morlet(sigma, xi0 / sigma, k)
+    return np.linalg.norm(t - psi) / np.linalg.norm(psi)
+
+
+def _direct_kernel_err(sigma, xi0, PD, L):
+    pl = O.plan_morlet(sigma, xi0 / sigma, PD, L)
+    k = np.arange(-5 * L, 5 * L + 1)
+    t = np.zeros(len(k), dtype=np.complex128)
+    t[np.abs(k) <= L] = O.kterm_morlet(pl)
+    psi = O.morlet(sigma, xi0 / sigma, k)
+    return np.linalg.norm(t - psi) / np.linalg.norm(psi)
+
+
+@pytest.mark.parametrize("PM", [2, 3])
+def test_multiply_vs_direct_as_in_fig_mse1(PM):
+    """Sec. V-A (Fig. MSE1, sigma = 60, window chosen per method for the smallest relative RMSE
+    on [-5L, 5L]): with P_D = 2 P_M + 1 the two methods are about equally accurate for
+    xi0 >= 6, and the multiplication method is clearly worse for small xi0."""
+    sigma = 60.0
+    Ls = range(120, 301, 12)
+    for xi0 in (6.0, 20.0):
+        em = _best_relrmse(lambda L: _mult_kernel_err(sigma, xi0, PM, L), Ls)
+        ed = _best_relrmse(lambda L: _direct_kernel_err(sigma, xi0, 2 * PM + 1, L), Ls)
+        assert 0.4 < em / ed < 1.5, (xi0, em, ed)
+    for xi0 in (1.0, 2.0):
+        em = _best_relrmse(lambda L: _mult_kernel_err(sigma, xi0, PM, L), Ls)
+        ed = _best_relrmse(lambda L: _direct_kernel_err(sigma, xi0, 2 * PM + 1, L), Ls)
+        assert em / ed > 3.0, (xi0, em, ed)
+
+
+def test_multiply_envelope_converges_to_the_wavelet():
+    # with more terms the fitted kernel approaches psi itself; printed without the envelope
+    # normalisation 1 / sqrt(gamma / pi) it would stay ~100 % off
+    sigma, L = 20.0, 80
+    errs = [_mult_kernel_err(sigma, 6.0, PM, L) for PM in (2, 4, 6)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 5e-3, errs
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_multiply_equals_demodulated_gaussian_smoothing(mode):
+    """x_M[n] = C' [e^{i xi n} (G_hat * u)[n] - kappa (G_hat * x)[n]], u[m] = e^{-i xi m} x[m]: the
+    real-frequency components of Sec. III-B against two real Gaussian smoothings of the
+    demodulated signal (eq. GsSFT / GsASFT), an independent route through the oracle."""
+    rng = np.random.default_rng(8)
+    N, sigma, L, PM = 2000, 25.0, 75, 3
+    xi = 5.0 / sigma
+    x = rng.standard_normal(N)
+    n0 = 4 if mode == "asft" else None
+    pl = O.plan_multiply(sigma, xi, PM, L, mode=mode, n0=n0)
+    pg = O.plan_gauss(sigma, PM + 1, L, mode=mode, n0=n0)
+    m = np.arange(N)
+    gc = O.forward(x * np.cos(xi * m), pg)
+    gs = O.forward(-x * np.sin(xi * m), pg)
+    gx = O.forward(x, pg)
+    xi0 = xi * sigma
+    C = (1 + math.exp(-xi0 ** 2) - 2 * math.exp(-0.75 * xi0 ** 2)) ** -0.5
+    ce = C / (math.pi ** 0.25 * math.sqrt(sigma)) / math.sqrt(1.0 / (2 * sigma ** 2) / math.pi)
+    want = ce * (np.exp(1j * xi * m) * (gc + 1j * gs) - math.exp(-0.5 * xi0 ** 2) * gx)
+    got = O.forward(x, pl)
+    assert np.allclose(got, want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
