@@ -1,6 +1,7 @@
 """Benchmark of the SFT/ASFT kernel-integral Morlet transform on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scalogram|paper_scale|differentiation|gauss_deriv]
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+                [--workload scalogram|paper_scale|differentiation|gauss_deriv|multiply]
 
 Prints one JSON line. A step is one pass of the transform over the workload's whole
 batch, with the inputs resident in HBM. The dominant kernel is timed with HIP events on
@@ -15,6 +16,8 @@ Workloads (seeded, synthetic):
                 xi = 6/sigma, K = 6, L = 32768, ASFT
   differentiation : forward + backward of the scalogram layer, 64 x 32768 signals, 16 scales
   gauss_deriv : first differential of Gaussian smoothing, one 2^26-sample signal, sigma = 64, top order 5
+  multiply    : Morlet transform by the multiplication method (P_M = 2) of one 2^24-sample signal,
+                sigma = 64, xi = 6/sigma, beside the direct method with P_D = 2 P_M + 1 = 5
 """
 from __future__ import annotations
 
@@ -40,7 +43,7 @@ def _parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scalogram",
-                    choices=["scalogram", "paper_scale", "differentiation", "gauss_deriv"])
+                    choices=["scalogram", "paper_scale", "differentiation", "gauss_deriv", "multiply"])
     ap.add_argument("--mode", default="asft", choices=["sft", "asft"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", type=int, default=16, choices=[4, 8, 16, 32], help="samples per thread")
@@ -235,6 +238,44 @@ def bench_gauss_deriv(args, torch, M):
     }
 
 
+def bench_multiply(args, torch, M):
+    """Morlet transform of one long float32 signal by the multiplication method (three
+    Gaussian rows in one scan launch between the demodulation and remodulation kernels),
+    with the direct method of the same accuracy class (P_D = 2 P_M + 1) timed beside it."""
+    N, sigma, PM = 1 << 24, 64.0, 2
+    xi = 6.0 / sigma
+    dev = torch.device("cuda:0")
+    x = torch.randn(N, generator=torch.Generator().manual_seed(13)).to(dev)
+    plan = M.MultiplyPlan(N, sigma, xi, PM, mode=args.mode)
+    plan.set_tile(args.tile)
+    out = torch.empty(N, dtype=torch.complex64, device=dev)
+    ws = plan.workspace(dev)
+    ms_step, kern_ms = _timed(torch, lambda: plan.forward(x, out=out, ws=ws), args.steps, args.warmup)
+    info = plan.info()
+    direct = M.MorletPlan(N, sigma, xi, 2 * PM + 1, info["L"], mode=args.mode)
+    direct.set_tile(args.tile)
+    wsd = direct.workspace(dev)
+    _, kern_d = _timed(torch, lambda: direct.forward(x, out=out, ws=wsd), args.steps, args.warmup)
+    # whole path: 4 B in + 8 B out per sample (algorithmic); the composite moves 60 B
+    algo_bytes = N * (4 + 8)
+    achieved = algo_bytes / (kern_ms * 1e-3) / 1e9
+    return {
+        "metric": f"Gsamples/s (Morlet transform by the multiplication method, {args.mode.upper()})",
+        "value": N / (ms_step * 1e-3) / 1e9,
+        "unit": "Gsamples/s",
+        "ms_per_step": ms_step,
+        "dtype": "f32",
+        "config": {"workload": f"multiply: one float32 N(0,1) signal, N=2^24, sigma={sigma:g}, xi=6/sigma, P_M={PM} "
+                               f"(K={PM + 1} envelope terms), window L={info['L']}, {args.mode}, complex64 out",
+                   "tile_R": args.tile},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "scope": "whole path (demodulate, three-row scan, remodulate) against 12 B per sample"},
+        "kernel_ms": kern_ms,
+        "direct_method": {"P_D": 2 * PM + 1, "kernel_ms": kern_d, "ratio": kern_ms / kern_d},
+    }
+
+
 def bench_paper_scale(args, torch, M):
     import workloads
     from oracle import morlet_oracle as O
@@ -312,7 +353,8 @@ def main():
 
     import paper_2110_11866_amd as M
     fn = {"scalogram": bench_scalogram, "paper_scale": bench_paper_scale,
-          "differentiation": bench_differentiation, "gauss_deriv": bench_gauss_deriv}[args.workload]
+          "differentiation": bench_differentiation, "gauss_deriv": bench_gauss_deriv,
+          "multiply": bench_multiply}[args.workload]
     line = fn(args, torch, M)
     full = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"),
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),

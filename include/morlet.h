@@ -118,6 +118,26 @@ morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int
 morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigma, int32_t K, int64_t L,
                                       int32_t order);
 
+/* Create a plan for the Morlet wavelet transform by the multiplication method (Sec. III-B):
+ * the wavelet's Gaussian envelope is fitted with the cosines of orders 0..P_M on [-L, L]
+ * (eq. aproGauss, K = P_M + 1 terms) and the carrier multiplies it,
+ *   psi_hat_M[k] = C' (e^{i xi k} - kappa_xi) G_hat[k],  C' = C_xi / (pi^{1/4} sqrt(sigma)) / sqrt(gamma/pi),
+ * which is the paper's sum over the real frequencies omega_p = xi + beta p, p = -P_M..P_M.
+ * Evaluated as x_M[n] = C' [e^{i xi n} (G_hat * u)[n] - kappa_xi (G_hat * x)[n]] with
+ * u[m] = e^{-i xi m} x[m]: a demodulation kernel, one scan launch over three rows (Re u, Im u,
+ * x) and a remodulation kernel. Run with morlet_forward (complex64 out); the workspace holds
+ * the scan's tile states and 6 N float32 (morlet_workspace_size). morlet_plan_set selects
+ * SFT/ASFT (ASFT: the smoothings are read n0 earlier and scaled by e^{-n0^2/(2 sigma^2)}; only
+ * the carrier part takes the phase e^{i xi n0}, so the result approximates psi[k + n0]
+ * exactly) and the accumulation precision; morlet_plan_set_tile, _set_schedule and
+ * _autotune apply. morlet_plan_info reports a_p as cos_coef (sin_coef zero), P_S = 0 and the
+ * error of psi_hat_M against psi on [-L, L] as kernel_relrmse. L = 0 takes the error-optimal
+ * window of the Gaussian fit. Forward only (backward calls return MORLET_ERR_UNSUPPORTED).
+ * Errors: MORLET_ERR_INVALID_ARG (N < 0 or N > 2^38, sigma or xi not finite and > 0,
+ * P_M < 0 or P_M + 1 > MORLET_MAX_TERMS, 0 < L < P_M), MORLET_ERR_ALLOC, MORLET_ERR_HIP. */
+morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, double xi, int32_t P_M,
+                                   int64_t L);
+
 /* Select SFT or ASFT, the ASFT shift n0 (0 = default; 1 <= n0 <= L otherwise) and the
  * accumulation precision. Rebuilds the device table (synchronously). */
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,

@@ -13,7 +13,7 @@ from . import _abi
 from ._abi import (MORLET_ACC_COMPENSATED, MORLET_ACC_F32, MORLET_BF16, MORLET_F16, MORLET_F32,
                    MORLET_SCAN_ASFT, MORLET_SCAN_SFT, MorletError)
 
-__all__ = ["MorletPlan", "GaussPlan", "GaussDerivPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
+__all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
            "MorletTransform"]
 
 _DT = {torch.float32: MORLET_F32, torch.float16: MORLET_F16, torch.bfloat16: MORLET_BF16}
@@ -161,6 +161,29 @@ class MorletPlan(_PlanBase):
         if want_params:
             self._check_x(x)
         return _bwd_common(self, _abi.morlet_backward, x if want_params else None, gW, want_params, 2)
+
+
+class MultiplyPlan(MorletPlan):
+    """Morlet transform by the multiplication method (Sec. III-B): the Gaussian envelope
+    fitted with the cosines of orders 0..P_M (K = P_M + 1 terms) times the carrier, evaluated
+    as three Gaussian smoothings (demodulated real and imaginary parts, and the signal) in one
+    scan launch between a demodulation and a remodulation kernel. Forward only."""
+
+    kind = "morlet"
+
+    def __init__(self, N: int, sigma: float, xi: float, P_M: int, L: int = 0, mode: str = "sft",
+                 n0: int = 0, accum: str = "f32"):
+        _PlanBase.__init__(self, _abi.morlet_plan_multiply(int(N), float(sigma), float(xi), int(P_M), int(L)),
+                           int(N), int(P_M) + 1)
+        self.sigma, self.xi, self.P_M = float(sigma), float(xi), int(P_M)
+        if mode != "sft" or n0 or accum != "f32":
+            self.set(mode, n0, accum)
+
+    def direct(self, *args, **kwargs):
+        raise NotImplementedError("the direct-convolution baseline needs a direct-method plan")
+
+    def backward(self, *args, **kwargs):
+        raise NotImplementedError("no backward pass for multiplication-method plans")
 
 
 class GaussPlan(_PlanBase):

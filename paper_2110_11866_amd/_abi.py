@@ -28,6 +28,7 @@ SIGNATURES = {
     "morlet_plan": (ctypes.c_int, [_P(_vp), _i64, _dbl, _dbl, _i32, _i64]),
     "morlet_plan_gauss": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64]),
     "morlet_plan_gauss_deriv": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64, _i32]),
+    "morlet_plan_multiply": (ctypes.c_int, [_P(_vp), _i64, _dbl, _dbl, _i32, _i64]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
     "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
     "morlet_plan_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -96,6 +97,12 @@ def morlet_plan_gauss(N: int, sigma: float, K: int, L: int) -> int:
 def morlet_plan_gauss_deriv(N: int, sigma: float, K: int, L: int, order: int) -> int:
     h = ctypes.c_void_p()
     check(lib().morlet_plan_gauss_deriv(ctypes.byref(h), N, sigma, K, L, order))
+    return h.value
+
+
+def morlet_plan_multiply(N: int, sigma: float, xi: float, P_M: int, L: int) -> int:
+    h = ctypes.c_void_p()
+    check(lib().morlet_plan_multiply(ctypes.byref(h), N, sigma, xi, P_M, L))
     return h.value
 
 

@@ -273,9 +273,55 @@ morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, 
   return MORLET_OK;
 }
 
+// Workspace of a multiplication-method plan: the three-row scan's tile states, then the rows'
+// inputs u (3N float32) and their smoothings g (3N float32), each 256-byte aligned.
+struct MultLayout {
+  size_t u_off, g_off, total;
+};
+MultLayout mult_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  MultLayout m;
+  m.u_off = up(mk::workspace_bytes(plan->K, plan->ntiles_max));
+  m.g_off = up(m.u_off + 3 * (size_t)plan->mult_N * sizeof(float));
+  m.total = m.g_off + 3 * (size_t)plan->mult_N * sizeof(float);
+  return m;
+}
+
+// Multiplication method (Sec. III-B): demodulate, three-row Gaussian scan, remodulate.
+morlet_status run_multiply(morlet_plan_t plan, const void* x, int dtype, void* W, void* ws, size_t ws_bytes,
+                           void* stream) {
+  if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  const int64_t N = plan->mult_N;
+  if (N == 0) return MORLET_OK;
+  if (!x || !W || !ws) return fail(MORLET_ERR_INVALID_ARG, "null x, output or workspace pointer");
+  if (plan->ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  const MultLayout m = mult_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* u = reinterpret_cast<float*>(wsb + m.u_off);
+  float* g = reinterpret_cast<float*>(wsb + m.g_off);
+  hipError_t e = mk::launch_mm_demodulate(x, dtype, u, N, plan->xi, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  mk::ScanLaunch a;
+  const morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0, 0);
+  if (st != MORLET_OK) return st;
+  a.x = u;
+  a.dtype = 0;
+  a.out = g;
+  e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e == hipSuccess)
+    e = mk::launch_mm_remodulate(g, static_cast<float2*>(W), N, plan->xi, plan->mult_ce,
+                                 plan->mult_ce * plan->mult_kappa, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
+}
+
 morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const void* g, float* gx, double* gparams,
                            void* ws, size_t ws_bytes, void* stream, int want_kind, bool want_batched) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->multiply) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for multiplication-method plans");
   if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
   if (plan->deriv != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for differential smoothing plans");
   if (want_batched != plan->batched)
@@ -473,6 +519,86 @@ morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigm
   return finish_plan(p, out);
 }
 
+morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, double xi, int32_t P_M, int64_t L) {
+  if (!out) return fail(MORLET_ERR_INVALID_ARG, "null output handle");
+  if (P_M < 0 || P_M + 1 > MORLET_MAX_TERMS) return fail(MORLET_ERR_INVALID_ARG, "P_M must be in [0, MORLET_MAX_TERMS - 1]");
+  const int K = P_M + 1;
+  morlet_status s = check_common(N, sigma, K, L);
+  if (s != MORLET_OK) return s;
+  if (N > ((int64_t)1 << 38)) return fail(MORLET_ERR_INVALID_ARG, "N must be <= 2^38 for the multiplication method");
+  if (!finite_pos(xi)) return fail(MORLET_ERR_INVALID_ARG, "xi must be finite and > 0");
+  if (L != 0 && L + 1 < K) return fail(MORLET_ERR_INVALID_ARG, "L must be >= P_M");
+  auto* p = new (std::nothrow) morlet_plan_s;
+  if (!p) return fail(MORLET_ERR_ALLOC, "out of host memory");
+  p->kind = 1;   // the scan runs in Gaussian form
+  p->multiply = true;
+  p->mult_N = N;
+  p->sigma = sigma;
+  p->xi = xi;
+  p->K = K;
+  p->L = L ? L : mk::select_L(sigma, 0.0, K, true);
+  p->P_S = 0;
+  std::vector<double> g, none;
+  mk::gauss_taps(sigma, p->L, g);
+  const mk::Fit f = mk::fit_orders(g, none, p->L, 0, K);
+  p->cc = f.cc;
+  p->sc.assign(K, 0.0);
+  p->jac.assign(4 * (size_t)K, 0.0);
+  const double xi0 = xi * sigma, gamma = 1.0 / (2.0 * sigma * sigma), kPi = 3.14159265358979323846;
+  const double C = 1.0 / std::sqrt(1.0 + std::exp(-xi0 * xi0) - 2.0 * std::exp(-0.75 * xi0 * xi0));
+  p->mult_kappa = std::exp(-0.5 * xi0 * xi0);
+  p->mult_ce = C / (std::pow(kPi, 0.25) * std::sqrt(sigma)) / std::sqrt(gamma / kPi);
+  // error of psi_hat_M[k] = ce (e^{i xi k} - kappa) G_hat[k] against the wavelet on [-L, L]
+  {
+    std::vector<double> re, im;
+    mk::morlet_taps(sigma, xi, p->L, re, im);
+    double num = 0.0, den = 0.0;
+    for (int64_t k = -p->L; k <= p->L; ++k) {
+      double gh = 0.0;
+      for (int i = 0; i < K; ++i) gh += f.cc[i] * std::cos(kPi * (double)((i * k) % (2 * p->L)) / (double)p->L);
+      const double hr = p->mult_ce * (std::cos(xi * (double)k) - p->mult_kappa) * gh;
+      const double hi = p->mult_ce * std::sin(xi * (double)k) * gh;
+      const double dr = hr - re[p->L + k], di = hi - im[p->L + k];
+      num += dr * dr + di * di;
+      den += re[p->L + k] * re[p->L + k] + im[p->L + k] * im[p->L + k];
+    }
+    p->relrmse = den > 0.0 ? std::sqrt(num / den) : 0.0;
+  }
+  // three rows of length N, one Gaussian scale
+  p->batched = true;
+  p->B = 3;
+  p->S = 1;
+  p->N = 3 * N;
+  p->R = 16;
+  p->lengths.assign(3, N);
+  p->offsets = {0, N, 2 * N};
+  ScaleParams sp;
+  sp.sigma = sigma;
+  sp.xi = 0.0;
+  sp.L = p->L;
+  sp.P_S = 0;
+  sp.n0_asft = default_n0(sigma, p->L);
+  sp.cc = f.cc;
+  sp.sc.assign(K, 0.0);
+  sp.jac.assign(4 * (size_t)K, 0.0);
+  sp.relrmse = f.relrmse;
+  p->scales = {sp};
+  p->n0_asft = sp.n0_asft;
+  build_rows(p);
+  if (p->ntiles > ((int64_t)1 << 31)) {
+    delete p;
+    return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  }
+  build_batched_tables(p);
+  s = upload_batched(p);
+  if (s != MORLET_OK) {
+    morlet_destroy(p);
+    return s;
+  }
+  *out = p;
+  return MORLET_OK;
+}
+
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, morlet_accum accum) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (mode != MORLET_SCAN_SFT && mode != MORLET_SCAN_ASFT) return fail(MORLET_ERR_UNSUPPORTED, "unknown scan mode");
@@ -544,11 +670,14 @@ morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R) {
 morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int64_t* n0, double* alpha,
                                double* cos_coef, double* sin_coef, double* jac, double* kernel_relrmse) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
-  if (plan->batched) return fail(MORLET_ERR_INVALID_ARG, "use morlet_scalogram_scale_info for a scalogram plan");
+  if (plan->batched && !plan->multiply)
+    return fail(MORLET_ERR_INVALID_ARG, "use morlet_scalogram_scale_info for a scalogram plan");
+  // a multiplication-method plan keeps its shift with its one scale
+  const int64_t n0v = plan->multiply ? (plan->mode == 1 ? plan->scales[0].n0_asft : 0) : plan->n0;
   if (L) *L = plan->L;
   if (P_S) *P_S = plan->P_S;
-  if (n0) *n0 = plan->n0;
-  if (alpha) *alpha = plan->mode == 1 ? (double)plan->n0 / (plan->sigma * plan->sigma) : 0.0;
+  if (n0) *n0 = n0v;
+  if (alpha) *alpha = plan->mode == 1 ? (double)n0v / (plan->sigma * plan->sigma) : 0.0;
   if (cos_coef) std::memcpy(cos_coef, plan->cc.data(), sizeof(double) * plan->K);
   if (sin_coef) std::memcpy(sin_coef, plan->sc.data(), sizeof(double) * plan->K);
   if (jac) std::memcpy(jac, plan->jac.data(), sizeof(double) * 4 * plan->K);
@@ -603,11 +732,14 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
     st = morlet_plan_set_tile(plan, cands[c].R);
     plan->row_serial = cands[c].rows;
     if (st == MORLET_OK) st = morlet_workspace_init(ws, need, stream);
-    if (st == MORLET_OK) st = run_scan(plan, x, (int)dtype, out, ws, need, stream, plan->kind, plan->batched);
+    auto trial = [&]() {
+      return plan->multiply ? run_multiply(plan, x, (int)dtype, out, ws, need, stream)
+                            : run_scan(plan, x, (int)dtype, out, ws, need, stream, plan->kind, plan->batched);
+    };
+    if (st == MORLET_OK) st = trial();
     if (st != MORLET_OK) break;
     if (hipEventRecord(e0, s) != hipSuccess) { st = fail(MORLET_ERR_HIP, "autotune: event record failed"); break; }
-    for (int r = 0; r < reps && st == MORLET_OK; ++r)
-      st = run_scan(plan, x, (int)dtype, out, ws, need, stream, plan->kind, plan->batched);
+    for (int r = 0; r < reps && st == MORLET_OK; ++r) st = trial();
     float ms = 0.f;
     if (st == MORLET_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -636,7 +768,8 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
 morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
   // sized for the longest scan range over every n0 the plan may use (n0 = 0)
-  *bytes = mk::workspace_bytes(plan->K, plan->batched ? plan->ntiles_max : tiles_for(plan->N + plan->L, plan->R));
+  *bytes = plan->multiply ? mult_layout(plan).total
+                          : mk::workspace_bytes(plan->K, plan->batched ? plan->ntiles_max : tiles_for(plan->N + plan->L, plan->R));
   return MORLET_OK;
 }
 
@@ -649,6 +782,7 @@ morlet_status morlet_workspace_init(void* ws, size_t ws_bytes, void* stream) {
 
 morlet_status morlet_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W, void* ws,
                              size_t ws_bytes, void* stream) {
+  if (plan && plan->multiply) return run_multiply(plan, x, (int)dtype, W, ws, ws_bytes, stream);
   return run_scan(plan, x, (int)dtype, W, ws, ws_bytes, stream, 0, false);
 }
 

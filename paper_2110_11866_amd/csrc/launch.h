@@ -52,4 +52,11 @@ hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s);
 int scan_forward_occupancy(int K, int R, int wide, int kind);
 hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
 
+// Multiplication method (Sec. III-B), around a three-row Gaussian scan: u = [x cos(xi m),
+// -x sin(xi m), x] (float32, 3N), and W[n] = ce (e^{i xi n} (g[n] + i g[N + n]) - kappa g[2N + n])
+// with cek = ce kappa, from the rows' smoothings g (3N).
+hipError_t launch_mm_demodulate(const void* x, int dtype, float* u, int64_t N, double xi, hipStream_t s);
+hipError_t launch_mm_remodulate(const float* g, float2* W, int64_t N, double xi, double ce, double cek,
+                                hipStream_t s);
+
 }  // namespace mk

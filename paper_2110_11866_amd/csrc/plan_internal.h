@@ -54,6 +54,12 @@ struct morlet_plan_s {
   // exact taps of the direct-convolution baseline (uploaded on its first call)
   void* d_direct = nullptr;
   int64_t direct_H = -1;
+  // Morlet by the multiplication method (Sec. III-B): a batched Gaussian plan over three rows
+  // of the signal's length (the demodulated signal's real and imaginary parts, and the signal),
+  // the carrier applied around the scan
+  bool multiply = false;
+  int64_t mult_N = 0;                  // signal length
+  double mult_ce = 0, mult_kappa = 0;  // C_xi / (pi^(1/4) sqrt(sigma)) / sqrt(gamma / pi), kappa_xi
 };
 
 namespace mk {

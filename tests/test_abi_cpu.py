@@ -268,3 +268,52 @@ def test_tile_shapes_and_workspace():
         assert sizes[4] > sizes[8] > sizes[16] > sizes[32]
     finally:
         _abi.morlet_destroy(h)
+
+
+def test_multiply_plan_matches_oracle():
+    # envelope fit a_p (orders 0..P_M), window as the Gaussian fit's, and the reported kernel
+    # error of psi_hat_M = C' (e^{i xi k} - kappa) G_hat against psi on [-L, L]
+    for sigma, xi0, PM, L in [(16.0, 6.0, 3, 0), (60.0, 2.0, 2, 200), (300.0, 6.0, 4, 0)]:
+        h = _abi.morlet_plan_multiply(1000, sigma, xi0 / sigma, PM, L)
+        try:
+            info = _abi.morlet_plan_info(h, PM + 1)
+            _abi.morlet_plan_set(h, _abi.MORLET_SCAN_ASFT, 0, 0)
+            ia = _abi.morlet_plan_info(h, PM + 1)
+        finally:
+            _abi.morlet_destroy(h)
+        if L == 0:
+            hg = _abi.morlet_plan_gauss(1000, sigma, PM + 1, 0)
+            L = _abi.morlet_plan_info(hg, PM + 1)["L"]
+            _abi.morlet_destroy(hg)
+        assert info["L"] == L and info["P_S"] == 0 and info["n0"] == 0
+        pl = O.plan_multiply(sigma, xi0 / sigma, PM, L)
+        assert np.allclose(info["cos_coef"], pl.cos_coef, rtol=1e-10, atol=1e-14)
+        assert np.allclose(info["sin_coef"], 0.0)
+        k = np.arange(-L, L + 1)
+        psi = O.morlet(sigma, xi0 / sigma, k)
+        err = np.linalg.norm(O.kterm_multiply(pl) - psi) / np.linalg.norm(psi)
+        assert abs(info["kernel_relrmse"] / err - 1) < 1e-8, (info["kernel_relrmse"], err)
+        assert ia["n0"] == O.default_n0(sigma) and abs(ia["alpha"] - ia["n0"] / sigma ** 2) < 1e-15
+
+
+def test_multiply_plan_errors_and_workspace():
+    L = _abi.lib()
+    h = ctypes.c_void_p()
+    bad = [(100, 4.0, 0.5, -1, 0), (100, 4.0, 0.5, 12, 0), (100, 4.0, 0.0, 2, 0), (100, 4.0, 0.5, 3, 2),
+           (-1, 4.0, 0.5, 2, 0), (100, -4.0, 0.5, 2, 0)]
+    for args in bad:
+        assert L.morlet_plan_multiply(ctypes.byref(h), *args) == _abi.MORLET_ERR_INVALID_ARG, args
+    assert L.morlet_plan_multiply(ctypes.byref(h), 5000, 20.0, 0.3, 3, 0) == _abi.MORLET_OK
+    hp = h.value
+    try:
+        assert _abi.morlet_workspace_size(hp) >= 6 * 5000 * 4
+        fake = 1 << 20
+        assert L.morlet_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.gauss_smooth(hp, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_direct_forward(hp, fake, 0, fake, 0, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_forward(hp, fake, 0, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
+        assert L.morlet_forward(hp, fake, 5, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        for R in (4, 8, 16, 32):
+            assert L.morlet_plan_set_tile(hp, R) == _abi.MORLET_OK
+    finally:
+        _abi.morlet_destroy(hp)
