@@ -51,7 +51,7 @@ __all__ = [
     "select_PS", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
     "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
     "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
-    "plan_multiply", "kterm_multiply", "freq_component",
+    "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d",
 ]
 
 
@@ -666,3 +666,18 @@ def param_grads(x: np.ndarray, g: np.ndarray, plan: Plan) -> np.ndarray:
                 dW = dW.real
         out[t] = np.sum((np.conj(g) * dW).real)
     return out
+
+
+# --------------------------------------------------------------------------
+# Images: separable 2-D Gaussian smoothing (Sec. IV: the lines of an image are filtered
+# independently, rows then columns)
+# --------------------------------------------------------------------------
+def gauss_smooth_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
+    """y = G_y *_columns (G_x *_rows img) for an H x W image (row-major, x along a row), each
+    line by forward() with the axis's plan."""
+    img = np.asarray(img, dtype=np.float64)
+    H, W = img.shape
+    rows = np.stack([forward(img[r], plan_x) for r in range(H)]) if H and W else np.zeros((H, W))
+    out = np.stack([forward(rows[:, c], plan_y) for c in range(W)], axis=1) if H and W else np.zeros((H, W))
+    return out
+

@@ -696,3 +696,51 @@ def test_multiply_equals_demodulated_gaussian_smoothing(mode):
     want = ce * (np.exp(1j * xi * m) * (gc + 1j * gs) - math.exp(-0.5 * xi0 ** 2) * gx)
     got = O.forward(x, pl)
     assert np.allclose(got, want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
+
+
+# ---------------------------------------------------------------- images (separable 2-D)
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+@pytest.mark.parametrize("H,W", [(1, 1), (5, 3), (9, 14)])
+def test_gauss_2d_equals_brute_force_outer_product(mode, H, W):
+    """Rows then columns equals one 2-D convolution with the outer product of the two axes'
+    taps, y[r, c] = sum_{i, j} hy[i] hx[j] img[r - sy - i, c - sx - j], written as a double loop."""
+    rng = np.random.default_rng(H * 31 + W)
+    img = rng.standard_normal((H, W))
+    px = O.plan_gauss(2.0, 3, 5, mode=mode, n0=1 if mode == "asft" else None)
+    py = O.plan_gauss(3.0, 4, 8, mode=mode, n0=2 if mode == "asft" else None)
+    hx, sx = (O.asft_kernel(px).real, px.n0) if mode == "asft" else (O.kterm_gauss(px), 0)
+    hy, sy = (O.asft_kernel(py).real, py.n0) if mode == "asft" else (O.kterm_gauss(py), 0)
+    want = np.zeros((H, W))
+    for r in range(H):
+        for c in range(W):
+            acc = 0.0
+            for i in range(-py.L, py.L + 1):
+                for j in range(-px.L, px.L + 1):
+                    rr, cc = r - sy - i, c - sx - j
+                    if 0 <= rr < H and 0 <= cc < W:
+                        acc += hy[i + py.L] * hx[j + px.L] * img[rr, cc]
+            want[r, c] = acc
+    assert np.allclose(O.gauss_smooth_2d(img, px, py), want, rtol=1e-11, atol=1e-13)
+
+
+def test_gauss_2d_constant_image_interior():
+    # the constant column is in each axis's basis: interior = c * sum G_x[k] * sum G_y[k] exactly
+    H, W, c = 60, 70, 2.5
+    px, py = O.plan_gauss(3.0, 3, 9), O.plan_gauss(4.0, 5, 14)
+    y = O.gauss_smooth_2d(np.full((H, W), c), px, py)
+    want = c * O.gaussian(3.0, np.arange(-9, 10)).sum() * O.gaussian(4.0, np.arange(-14, 15)).sum()
+    assert np.allclose(y[14:H - 14, 9:W - 9], want, rtol=0, atol=1e-13)
+
+
+def test_gauss_2d_separable_cosine_image():
+    # img = cos(w1 r) cos(w2 c) is an eigenfunction in the interior: y = G_hat_y(w1) G_hat_x(w2) img,
+    # with G_hat(w) = sum_{|k|<=L} G_hat[k] cos(w k) (Dirichlet form of the even K-term kernel)
+    H, W = 90, 80
+    w1, w2 = 0.31, 0.77
+    r, c = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    img = np.cos(w1 * r) * np.cos(w2 * c)
+    px, py = O.plan_gauss(2.5, 4, 8), O.plan_gauss(3.5, 4, 11)
+    gx = sum(O.kterm_gauss(px)[k + 8] * math.cos(w2 * k) for k in range(-8, 9))
+    gy = sum(O.kterm_gauss(py)[k + 11] * math.cos(w1 * k) for k in range(-11, 12))
+    y = O.gauss_smooth_2d(img, px, py)
+    assert np.allclose(y[11:H - 11, 8:W - 8], gx * gy * img[11:H - 11, 8:W - 8], rtol=0, atol=1e-12)
