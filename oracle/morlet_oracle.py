@@ -235,7 +235,8 @@ def select_PS(sigma: float, xi: float, K: int, L: int) -> int:
 
 
 def default_n0(sigma: float) -> int:
-    return max(1, int(round(sigma / 8.0)))
+    """Default ASFT shift max(1, round(sigma / 8)), halves rounded up."""
+    return max(1, int(math.floor(sigma / 8.0 + 0.5)))
 
 
 def plan_morlet(sigma: float, xi: float, K: int, L: int, mode: str = "sft",
