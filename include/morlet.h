@@ -138,6 +138,35 @@ morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigm
 morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, double xi, int32_t P_M,
                                    int64_t L);
 
+/* Create a plan for separable 2-D Gaussian smoothing of an H x W image (row-major, x along a
+ * row): the lines of an image are filtered independently (Sec. IV), so
+ *   y = G_y *_columns (G_x *_rows img),
+ * each axis by eq. aproGauss with orders 0..K-1 on its own window [-L_x, L_x], [-L_y, L_y]
+ * (0: the error-optimal window of the fit), zero outside the image. Evaluated as one scan
+ * launch over the H rows, a transpose, one scan launch over the W rows of the transposed
+ * image and a transpose back. morlet_plan_set (SFT/ASFT with one n0 for both axes, 0 = each
+ * axis's default; accumulation), _set_tile and _set_schedule apply to both axes; autotune
+ * and the backward calls return MORLET_ERR_UNSUPPORTED; morlet_plan_info returns
+ * MORLET_ERR_INVALID_ARG (use morlet_image_axis_info). Errors: MORLET_ERR_INVALID_ARG (H or
+ * W < 0 or > 2^24, H W > 2^36, sigma not finite and > 0, K outside [1, MORLET_MAX_TERMS],
+ * 0 < L < K - 1), MORLET_ERR_UNSUPPORTED (more than 2^31 tiles on an axis),
+ * MORLET_ERR_ALLOC, MORLET_ERR_HIP. */
+morlet_status morlet_plan_gauss2d(morlet_plan_t* out, int64_t H, int64_t W, double sigma_y, double sigma_x,
+                                  int32_t K, int64_t L_y, int64_t L_x);
+
+/* 2-D smoothing: x (device, H x W elements of dtype, row-major) -> y (device float32, H x W).
+ * The workspace (morlet_workspace_size, zero-filled once) holds the larger axis's tile states
+ * and two H x W float32 buffers. Stream-ordered, no allocation or synchronization. Errors as
+ * gauss_smooth; MORLET_ERR_INVALID_ARG for a plan that is not an image plan. */
+morlet_status gauss_smooth2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, float* y, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* Per-axis parameters of an image plan: axis 0 filters along x (the rows), axis 1 along y.
+ * L: window half width; n0: ASFT shift in use (0 for SFT); cos_coef[K]: a_p; kernel_relrmse:
+ * error of the fitted Gaussian on [-L, L]. Outputs are nullable. */
+morlet_status morlet_image_axis_info(morlet_plan_t plan, int32_t axis, int64_t* L, int64_t* n0, double* cos_coef,
+                                     double* kernel_relrmse);
+
 /* Select SFT or ASFT, the ASFT shift n0 (0 = default; 1 <= n0 <= L otherwise) and the
  * accumulation precision. Rebuilds the device table (synchronously). */
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,

@@ -13,7 +13,7 @@ from . import _abi
 from ._abi import (MORLET_ACC_COMPENSATED, MORLET_ACC_F32, MORLET_BF16, MORLET_F16, MORLET_F32,
                    MORLET_SCAN_ASFT, MORLET_SCAN_SFT, MorletError)
 
-__all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
+__all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2DPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
            "MorletTransform"]
 
 _DT = {torch.float32: MORLET_F32, torch.float16: MORLET_F16, torch.bfloat16: MORLET_BF16}
@@ -233,6 +233,52 @@ class GaussDerivPlan(GaussPlan):
 
     def backward(self, *args, **kwargs):
         raise NotImplementedError("no backward pass for differential smoothing plans")
+
+
+class Gauss2DPlan(_PlanBase):
+    """Separable 2-D Gaussian smoothing of an H x W image (row-major, x along a row): the
+    lines are filtered independently (Sec. IV), rows then columns, each axis with K cosine
+    terms on its own window (0: error-optimal). Forward only."""
+
+    kind = "image"
+
+    def __init__(self, H: int, W: int, sigma_y: float, sigma_x: float, K: int, L_y: int = 0, L_x: int = 0,
+                 mode: str = "sft", n0: int = 0, accum: str = "f32"):
+        h = _abi.morlet_plan_gauss2d(int(H), int(W), float(sigma_y), float(sigma_x), int(K), int(L_y), int(L_x))
+        super().__init__(h, int(H) * int(W), int(K))
+        self.H, self.W = int(H), int(W)
+        self.sigma_y, self.sigma_x = float(sigma_y), float(sigma_x)
+        if mode != "sft" or n0 or accum != "f32":
+            self.set(mode, n0, accum)
+
+    def info(self) -> dict:
+        raise TypeError("use axis_info(0) (x, along rows) or axis_info(1) (y) for an image plan")
+
+    def axis_info(self, axis: int) -> dict:
+        return _abi.morlet_image_axis_info(self.handle, int(axis), self.K)
+
+    def _check_x(self, x: torch.Tensor) -> None:
+        if not x.is_cuda:
+            raise ValueError("x must be a device tensor")
+        if x.numel() != self.N or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous tensor of {self.H} x {self.W} pixels")
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+        self._check_x(x)
+        if out is None:
+            out = torch.empty((self.H, self.W), dtype=torch.float32, device=x.device)
+        if out.dtype != torch.float32 or out.numel() != self.N or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor of H x W elements")
+        w = self.workspace(x.device) if ws is None else ws
+        _abi.gauss_smooth2d(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(), w.data_ptr(),
+                            w.numel(), _stream())
+        return out
+
+    def autotune(self, *args, **kwargs):
+        raise NotImplementedError("autotune does not take image plans")
+
+    def backward(self, *args, **kwargs):
+        raise NotImplementedError("no backward pass for image plans")
 
 
 class ScalogramPlan(_PlanBase):

@@ -29,6 +29,9 @@ SIGNATURES = {
     "morlet_plan_gauss": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64]),
     "morlet_plan_gauss_deriv": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64, _i32]),
     "morlet_plan_multiply": (ctypes.c_int, [_P(_vp), _i64, _dbl, _dbl, _i32, _i64]),
+    "morlet_plan_gauss2d": (ctypes.c_int, [_P(_vp), _i64, _i64, _dbl, _dbl, _i32, _i64, _i64]),
+    "gauss_smooth2d": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    "morlet_image_axis_info": (ctypes.c_int, [_vp, _i32, _P(_i64), _P(_i64), _P(_dbl), _P(_dbl)]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
     "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
     "morlet_plan_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -104,6 +107,23 @@ def morlet_plan_multiply(N: int, sigma: float, xi: float, P_M: int, L: int) -> i
     h = ctypes.c_void_p()
     check(lib().morlet_plan_multiply(ctypes.byref(h), N, sigma, xi, P_M, L))
     return h.value
+
+
+def morlet_plan_gauss2d(H: int, W: int, sigma_y: float, sigma_x: float, K: int, L_y: int, L_x: int) -> int:
+    h = ctypes.c_void_p()
+    check(lib().morlet_plan_gauss2d(ctypes.byref(h), H, W, sigma_y, sigma_x, K, L_y, L_x))
+    return h.value
+
+
+def gauss_smooth2d(plan: int, x_ptr: int, dtype: int, y_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    check(lib().gauss_smooth2d(plan, x_ptr, dtype, y_ptr, ws_ptr, ws_bytes, stream))
+
+
+def morlet_image_axis_info(plan: int, axis: int, K: int) -> dict:
+    L, n0, rel = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+    cc = (ctypes.c_double * K)()
+    check(lib().morlet_image_axis_info(plan, axis, ctypes.byref(L), ctypes.byref(n0), cc, ctypes.byref(rel)))
+    return {"L": L.value, "n0": n0.value, "cos_coef": list(cc), "kernel_relrmse": rel.value}
 
 
 def morlet_plan_set(plan: int, mode: int, n0: int, accum: int) -> None:

@@ -166,6 +166,48 @@ morlet_status upload_batched(morlet_plan_s* p) {
   return MORLET_OK;
 }
 
+// A batched Gaussian plan over B rows of equal length (one scale, orders 0..K-1 on [-L, L],
+// L = 0: the fit's error-optimal window): the scan behind the multiplication method and the
+// two axes of an image plan. On error the plan is left for the caller to destroy.
+morlet_status init_gauss_rows(morlet_plan_s* p, int B, int64_t len, double sigma, int K, int64_t L) {
+  p->kind = 1;
+  p->sigma = sigma;
+  p->K = K;
+  p->L = L ? L : mk::select_L(sigma, 0.0, K, true);
+  p->P_S = 0;
+  std::vector<double> g, none;
+  mk::gauss_taps(sigma, p->L, g);
+  const mk::Fit f = mk::fit_orders(g, none, p->L, 0, K);
+  p->cc = f.cc;
+  p->sc.assign(K, 0.0);
+  p->jac.assign(4 * (size_t)K, 0.0);
+  p->relrmse = f.relrmse;
+  p->batched = true;
+  p->B = B;
+  p->S = 1;
+  p->N = (int64_t)B * len;
+  p->R = 16;
+  p->lengths.assign(B, len);
+  p->offsets.resize(B);
+  for (int b = 0; b < B; ++b) p->offsets[b] = (int64_t)b * len;
+  ScaleParams sp;
+  sp.sigma = sigma;
+  sp.xi = 0.0;
+  sp.L = p->L;
+  sp.P_S = 0;
+  sp.n0_asft = default_n0(sigma, p->L);
+  sp.cc = f.cc;
+  sp.sc.assign(K, 0.0);
+  sp.jac.assign(4 * (size_t)K, 0.0);
+  sp.relrmse = f.relrmse;
+  p->scales = {sp};
+  p->n0_asft = sp.n0_asft;
+  build_rows(p);
+  if (p->ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  build_batched_tables(p);
+  return upload_batched(p);
+}
+
 // Fill the launch descriptor for this plan (rows, tables, tiles, workspace, grid).
 morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int variant, int mom, int dtype) {
   const int64_t jend = plan->N + plan->L - plan->n0;
@@ -250,6 +292,7 @@ BwdLayout bwd_layout(morlet_plan_t plan) {
 morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, void* ws, size_t ws_bytes,
                        void* stream, int want_kind, bool want_batched = false) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "an image plan runs with gauss_smooth2d");
   if (plan->kind != want_kind)
     return fail(MORLET_ERR_INVALID_ARG, want_kind == 0 ? "morlet_forward needs a Morlet plan"
                                                        : "gauss_smooth needs a Gaussian plan");
@@ -318,10 +361,64 @@ morlet_status run_multiply(morlet_plan_t plan, const void* x, int dtype, void* W
   return MORLET_OK;
 }
 
+// Workspace of an image plan: the larger of the two axes' tile states, then two H x W float32
+// buffers (the row pass's output, the transposed image).
+struct ImageLayout {
+  size_t a_off, b_off, total;
+};
+ImageLayout image_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t px = (size_t)plan->img_H * (size_t)plan->img_W * sizeof(float);
+  ImageLayout m;
+  m.a_off = up(std::max(mk::workspace_bytes(plan->K, plan->axis[0]->ntiles_max),
+                        mk::workspace_bytes(plan->K, plan->axis[1]->ntiles_max)));
+  m.b_off = up(m.a_off + px);
+  m.total = m.b_off + px;
+  return m;
+}
+
+// Separable 2-D Gaussian smoothing: rows (x -> A), transpose (A -> B), rows of the transposed
+// image (B -> A), transpose back (A -> y). Both scans share the workspace's tile states: they
+// run in stream order and each launch re-arms the header for the next.
+morlet_status run_image2d(morlet_plan_t plan, const void* x, int dtype, float* y, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  const int64_t H = plan->img_H, W = plan->img_W;
+  if (H == 0 || W == 0) return MORLET_OK;
+  if (!x || !y || !ws) return fail(MORLET_ERR_INVALID_ARG, "null x, output or workspace pointer");
+  const ImageLayout m = image_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small");
+  if (!plan->axis[0]->d_tab || !plan->axis[1]->d_tab)
+    return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* A = reinterpret_cast<float*>(wsb + m.a_off);
+  float* B = reinterpret_cast<float*>(wsb + m.b_off);
+  mk::ScanLaunch a;
+  morlet_status st = make_launch(plan->axis[0], a, ws, mk::kVarForward, 0, dtype);
+  if (st != MORLET_OK) return st;
+  a.x = x;
+  a.dtype = dtype;
+  a.out = A;
+  hipError_t e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e == hipSuccess) e = mk::launch_transpose(A, B, H, W, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  st = make_launch(plan->axis[1], a, ws, mk::kVarForward, 0, 0);
+  if (st != MORLET_OK) return st;
+  a.x = B;
+  a.dtype = 0;
+  a.out = A;
+  e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e == hipSuccess) e = mk::launch_transpose(A, y, W, H, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
+}
+
 morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const void* g, float* gx, double* gparams,
                            void* ws, size_t ws_bytes, void* stream, int want_kind, bool want_batched) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (plan->multiply) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for multiplication-method plans");
+  if (plan->image2d) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for image plans");
   if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
   if (plan->deriv != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for differential smoothing plans");
   if (want_batched != plan->batched)
@@ -530,20 +627,15 @@ morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, 
   if (L != 0 && L + 1 < K) return fail(MORLET_ERR_INVALID_ARG, "L must be >= P_M");
   auto* p = new (std::nothrow) morlet_plan_s;
   if (!p) return fail(MORLET_ERR_ALLOC, "out of host memory");
-  p->kind = 1;   // the scan runs in Gaussian form
   p->multiply = true;
   p->mult_N = N;
-  p->sigma = sigma;
   p->xi = xi;
-  p->K = K;
-  p->L = L ? L : mk::select_L(sigma, 0.0, K, true);
-  p->P_S = 0;
-  std::vector<double> g, none;
-  mk::gauss_taps(sigma, p->L, g);
-  const mk::Fit f = mk::fit_orders(g, none, p->L, 0, K);
-  p->cc = f.cc;
-  p->sc.assign(K, 0.0);
-  p->jac.assign(4 * (size_t)K, 0.0);
+  // the scan runs in Gaussian form over three rows (Re u, Im u, x)
+  s = init_gauss_rows(p, 3, N, sigma, K, L);
+  if (s != MORLET_OK) {
+    morlet_destroy(p);
+    return s;
+  }
   const double xi0 = xi * sigma, gamma = 1.0 / (2.0 * sigma * sigma), kPi = 3.14159265358979323846;
   const double C = 1.0 / std::sqrt(1.0 + std::exp(-xi0 * xi0) - 2.0 * std::exp(-0.75 * xi0 * xi0));
   p->mult_kappa = std::exp(-0.5 * xi0 * xi0);
@@ -555,7 +647,7 @@ morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, 
     double num = 0.0, den = 0.0;
     for (int64_t k = -p->L; k <= p->L; ++k) {
       double gh = 0.0;
-      for (int i = 0; i < K; ++i) gh += f.cc[i] * std::cos(kPi * (double)((i * k) % (2 * p->L)) / (double)p->L);
+      for (int i = 0; i < K; ++i) gh += p->cc[i] * std::cos(kPi * (double)((i * k) % (2 * p->L)) / (double)p->L);
       const double hr = p->mult_ce * (std::cos(xi * (double)k) - p->mult_kappa) * gh;
       const double hi = p->mult_ce * std::sin(xi * (double)k) * gh;
       const double dr = hr - re[p->L + k], di = hi - im[p->L + k];
@@ -564,33 +656,38 @@ morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, 
     }
     p->relrmse = den > 0.0 ? std::sqrt(num / den) : 0.0;
   }
-  // three rows of length N, one Gaussian scale
-  p->batched = true;
-  p->B = 3;
-  p->S = 1;
-  p->N = 3 * N;
-  p->R = 16;
-  p->lengths.assign(3, N);
-  p->offsets = {0, N, 2 * N};
-  ScaleParams sp;
-  sp.sigma = sigma;
-  sp.xi = 0.0;
-  sp.L = p->L;
-  sp.P_S = 0;
-  sp.n0_asft = default_n0(sigma, p->L);
-  sp.cc = f.cc;
-  sp.sc.assign(K, 0.0);
-  sp.jac.assign(4 * (size_t)K, 0.0);
-  sp.relrmse = f.relrmse;
-  p->scales = {sp};
-  p->n0_asft = sp.n0_asft;
-  build_rows(p);
-  if (p->ntiles > ((int64_t)1 << 31)) {
+  *out = p;
+  return MORLET_OK;
+}
+
+morlet_status morlet_plan_gauss2d(morlet_plan_t* out, int64_t H, int64_t W, double sigma_y, double sigma_x,
+                                  int32_t K, int64_t L_y, int64_t L_x) {
+  if (!out) return fail(MORLET_ERR_INVALID_ARG, "null output handle");
+  if (H < 0 || W < 0 || H > ((int64_t)1 << 24) || W > ((int64_t)1 << 24) || H * W > ((int64_t)1 << 36))
+    return fail(MORLET_ERR_INVALID_ARG, "H, W must be in [0, 2^24] with H W <= 2^36");
+  morlet_status s = check_common(W, sigma_x, K, L_x);
+  if (s == MORLET_OK) s = check_common(H, sigma_y, K, L_y);
+  if (s != MORLET_OK) return s;
+  if ((L_x != 0 && L_x + 1 < K) || (L_y != 0 && L_y + 1 < K)) return fail(MORLET_ERR_INVALID_ARG, "L must be >= K - 1");
+  auto* p = new (std::nothrow) morlet_plan_s;
+  auto* ax = new (std::nothrow) morlet_plan_s;
+  auto* ay = new (std::nothrow) morlet_plan_s;
+  if (!p || !ax || !ay) {
     delete p;
-    return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+    delete ax;
+    delete ay;
+    return fail(MORLET_ERR_ALLOC, "out of host memory");
   }
-  build_batched_tables(p);
-  s = upload_batched(p);
+  p->kind = 1;
+  p->image2d = true;
+  p->img_H = H;
+  p->img_W = W;
+  p->K = K;
+  p->N = H * W;
+  p->axis[0] = ax;
+  p->axis[1] = ay;
+  s = init_gauss_rows(ax, (int)H, W, sigma_x, K, L_x);
+  if (s == MORLET_OK) s = init_gauss_rows(ay, (int)W, H, sigma_y, K, L_y);
   if (s != MORLET_OK) {
     morlet_destroy(p);
     return s;
@@ -599,8 +696,36 @@ morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, 
   return MORLET_OK;
 }
 
+morlet_status gauss_smooth2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, float* y, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (!plan || !plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d needs an image plan");
+  return run_image2d(plan, x, (int)dtype, y, ws, ws_bytes, stream);
+}
+
+morlet_status morlet_image_axis_info(morlet_plan_t plan, int32_t axis, int64_t* L, int64_t* n0, double* cos_coef,
+                                     double* kernel_relrmse) {
+  if (!plan || !plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "needs an image plan");
+  if (axis != 0 && axis != 1) return fail(MORLET_ERR_INVALID_ARG, "axis must be 0 (x, along rows) or 1 (y)");
+  const morlet_plan_s* a = plan->axis[axis];
+  const ScaleParams& sp = a->scales[0];
+  if (L) *L = sp.L;
+  if (n0) *n0 = a->mode == 1 ? sp.n0_asft : 0;
+  if (cos_coef) std::memcpy(cos_coef, sp.cc.data(), sizeof(double) * a->K);
+  if (kernel_relrmse) *kernel_relrmse = sp.relrmse;
+  return MORLET_OK;
+}
+
 morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, morlet_accum accum) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->image2d) {
+    morlet_status st = morlet_plan_set(plan->axis[0], mode, n0, accum);
+    if (st == MORLET_OK) st = morlet_plan_set(plan->axis[1], mode, n0, accum);
+    if (st == MORLET_OK) {
+      plan->mode = (int)mode;
+      plan->accum = (int)accum;
+    }
+    return st;
+  }
   if (mode != MORLET_SCAN_SFT && mode != MORLET_SCAN_ASFT) return fail(MORLET_ERR_UNSUPPORTED, "unknown scan mode");
   if (accum != MORLET_ACC_F32 && accum != MORLET_ACC_COMPENSATED)
     return fail(MORLET_ERR_UNSUPPORTED, "unknown accumulation mode");
@@ -627,6 +752,10 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
 
 morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule schedule) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->image2d) {
+    const morlet_status st = morlet_plan_set_schedule(plan->axis[0], schedule);
+    return st == MORLET_OK ? morlet_plan_set_schedule(plan->axis[1], schedule) : st;
+  }
   switch (schedule) {
     case MORLET_SCHED_AUTO: plan->row_serial = -1; return MORLET_OK;
     case MORLET_SCHED_TILES: plan->row_serial = 0; return MORLET_OK;
@@ -637,6 +766,17 @@ morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule sched
 
 morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->image2d) {
+    // both axes or neither: a shape the second axis cannot take restores the first
+    const int oldR = plan->axis[0]->R;
+    morlet_status st = morlet_plan_set_tile(plan->axis[0], R);
+    if (st == MORLET_OK) {
+      st = morlet_plan_set_tile(plan->axis[1], R);
+      if (st != MORLET_OK) (void)morlet_plan_set_tile(plan->axis[0], oldR);
+    }
+    if (st == MORLET_OK) plan->R = R;
+    return st;
+  }
   if (R != 4 && R != 8 && R != 16 && R != 32) return fail(MORLET_ERR_UNSUPPORTED, "R must be 4, 8, 16 or 32");
   if (R == plan->R) return MORLET_OK;
   const int oldR = plan->R;
@@ -672,6 +812,7 @@ morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (plan->batched && !plan->multiply)
     return fail(MORLET_ERR_INVALID_ARG, "use morlet_scalogram_scale_info for a scalogram plan");
+  if (plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "use morlet_image_axis_info for an image plan");
   // a multiplication-method plan keeps its shift with its one scale
   const int64_t n0v = plan->multiply ? (plan->mode == 1 ? plan->scales[0].n0_asft : 0) : plan->n0;
   if (L) *L = plan->L;
@@ -688,6 +829,7 @@ morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int
 morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* out, int32_t reps,
                                    int32_t* R_out, int32_t* schedule_out, void* stream) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->image2d) return fail(MORLET_ERR_UNSUPPORTED, "autotune does not take image plans");
   if (reps < 1 || reps > 1000) return fail(MORLET_ERR_INVALID_ARG, "reps must be in [1, 1000]");
   if ((int)dtype < 0 || (int)dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
   if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
@@ -768,6 +910,10 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
 morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
   // sized for the longest scan range over every n0 the plan may use (n0 = 0)
+  if (plan->image2d) {
+    *bytes = image_layout(plan).total;
+    return MORLET_OK;
+  }
   *bytes = plan->multiply ? mult_layout(plan).total
                           : mk::workspace_bytes(plan->K, plan->batched ? plan->ntiles_max : tiles_for(plan->N + plan->L, plan->R));
   return MORLET_OK;
@@ -896,6 +1042,8 @@ morlet_status morlet_scalogram_forward(morlet_plan_t plan, const void* x_packed,
 
 void morlet_destroy(morlet_plan_t plan) {
   if (!plan) return;
+  morlet_destroy(plan->axis[0]);
+  morlet_destroy(plan->axis[1]);
   if (plan->d_tab) (void)hipFree(plan->d_tab);
   if (plan->d_rows) (void)hipFree(plan->d_rows);
   if (plan->d_direct) (void)hipFree(plan->d_direct);

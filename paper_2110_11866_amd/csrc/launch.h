@@ -59,4 +59,7 @@ hipError_t launch_mm_demodulate(const void* x, int dtype, float* u, int64_t N, d
 hipError_t launch_mm_remodulate(const float* g, float2* W, int64_t N, double xi, double ce, double cek,
                                 hipStream_t s);
 
+// out[c][r] = in[r][c] for an R x C row-major float32 matrix (separable 2-D filtering).
+hipError_t launch_transpose(const float* in, float* out, int64_t R, int64_t C, hipStream_t s);
+
 }  // namespace mk

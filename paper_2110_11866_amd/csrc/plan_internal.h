@@ -60,6 +60,12 @@ struct morlet_plan_s {
   bool multiply = false;
   int64_t mult_N = 0;                  // signal length
   double mult_ce = 0, mult_kappa = 0;  // C_xi / (pi^(1/4) sqrt(sigma)) / sqrt(gamma / pi), kappa_xi
+  // separable 2-D Gaussian smoothing of an H x W image (Sec. IV: lines filtered independently):
+  // axis[0] is a batched Gaussian plan over the H rows (length W), axis[1] one over the W rows
+  // of the transposed image (length H); this plan owns both
+  bool image2d = false;
+  int64_t img_H = 0, img_W = 0;
+  morlet_plan_s* axis[2] = {nullptr, nullptr};
 };
 
 namespace mk {

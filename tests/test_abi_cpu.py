@@ -317,3 +317,51 @@ def test_multiply_plan_errors_and_workspace():
             assert L.morlet_plan_set_tile(hp, R) == _abi.MORLET_OK
     finally:
         _abi.morlet_destroy(hp)
+
+
+def test_image_plan_axes_match_oracle():
+    # each axis is a Gaussian fit of its own sigma on its own window; defaults as the 1-D plans
+    for H, W, sy, sx, K, Ly, Lx in [(300, 200, 4.0, 9.0, 4, 0, 0), (64, 4096, 20.0, 3.0, 5, 70, 12)]:
+        h = _abi.morlet_plan_gauss2d(H, W, sy, sx, K, Ly, Lx)
+        try:
+            ix, iy = _abi.morlet_image_axis_info(h, 0, K), _abi.morlet_image_axis_info(h, 1, K)
+            _abi.morlet_plan_set(h, _abi.MORLET_SCAN_ASFT, 0, 0)
+            ax, ay = _abi.morlet_image_axis_info(h, 0, K), _abi.morlet_image_axis_info(h, 1, K)
+        finally:
+            _abi.morlet_destroy(h)
+        for info, sigma, L in ((ix, sx, Lx), (iy, sy, Ly)):
+            if L == 0:
+                hg = _abi.morlet_plan_gauss(1000, sigma, K, 0)
+                L = _abi.morlet_plan_info(hg, K)["L"]
+                _abi.morlet_destroy(hg)
+            assert info["L"] == L and info["n0"] == 0
+            assert np.allclose(info["cos_coef"], O.fit_gauss(sigma, K, L), rtol=1e-10, atol=1e-14)
+        assert ax["n0"] == O.default_n0(sx) and ay["n0"] == O.default_n0(sy)
+
+
+def test_image_plan_errors_and_workspace():
+    L = _abi.lib()
+    h = ctypes.c_void_p()
+    for args in [(-1, 10, 2.0, 2.0, 3, 0, 0), (10, 1 << 25, 2.0, 2.0, 3, 0, 0), (10, 10, 2.0, 2.0, 0, 0, 0),
+                 (10, 10, -2.0, 2.0, 3, 0, 0), (10, 10, 2.0, 2.0, 5, 2, 0)]:
+        assert L.morlet_plan_gauss2d(ctypes.byref(h), *args) == _abi.MORLET_ERR_INVALID_ARG, args
+    assert L.morlet_plan_gauss2d(ctypes.byref(h), 120, 90, 3.0, 5.0, 4, 0, 0) == _abi.MORLET_OK
+    hp = h.value
+    try:
+        assert _abi.morlet_workspace_size(hp) >= 2 * 120 * 90 * 4
+        fake = 1 << 20
+        assert L.gauss_smooth(hp, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_forward(hp, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_plan_autotune(hp, fake, 0, fake, 3, None, None, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.gauss_smooth2d(hp, fake, 0, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
+        assert L.morlet_image_axis_info(hp, 2, None, None, None, None) == _abi.MORLET_ERR_INVALID_ARG
+        for R in (4, 8, 16, 32):
+            assert L.morlet_plan_set_tile(hp, R) == _abi.MORLET_OK
+    finally:
+        _abi.morlet_destroy(hp)
+    h1 = _abi.morlet_plan_gauss(100, 3.0, 4, 0)
+    try:
+        assert L.gauss_smooth2d(h1, 1 << 20, 0, 1 << 20, 1 << 20, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+    finally:
+        _abi.morlet_destroy(h1)
