@@ -159,6 +159,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
     const int par = P.serial ? (int)(ti & 1) : 0;
     const int64_t jt = ti * T;
     const int64_t j0 = jt + (int64_t)tid * R;
+    // a wave whose positions all lie at or past jend (only in a row's last tile) feeds no output
+    // and no later state: it skips its loads, chunk sums and outputs (its sums stay zero)
+    const bool wave_dead = jt + (int64_t)__builtin_amdgcn_readfirstlane(wid) * 64 * R >= row.jend;
     const unsigned char* tb = P.tabs + (int64_t)row.scale * P.tab_stride;
     const Tab<WIDE> tab{(cptr<acc_t>)(WIDE ? tb + P.f32_bytes : tb), K};
     const Tab<true> tabd{(cptr<double>)(tb + P.f32_bytes), K};
@@ -203,9 +206,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
         ld4_fast<DT>(xs, j - 2 * row.L, yb[0]);
       }
     };
-    // Positions past jend (the end of the row's last tile) are scanned like the others: they
-    // produce no output and their state is never carried further, so their inputs need no
-    // masking (in the gradient pass the cotangent is zero there).
+    // Positions past jend in a wave that also holds earlier positions are scanned like the
+    // others: they produce no output and their state is never carried further, so their inputs
+    // need no masking (in the gradient pass the cotangent is zero there).
     bool fast_in = (j0 - 2 * row.L >= 0) && (j0 + R <= row.N);
     {
       if constexpr (VAR == kAdj) {
@@ -270,7 +273,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
             *reinterpret_cast<float4*>(stash + 16 * q + 4 * r) = make_float4(ya[0][r], ya[1][r], yb[0][r], yb[1][r]);
         }
       };
-      if (fast_in && NS == 1 && !MOM) {
+      if (wave_dead) {
+        // nothing to load or sum
+      } else if (fast_in && NS == 1 && !MOM) {
         // every position of the run is in range: form all R differences first, then per term
         // a Horner pass four positions at a time, B <- a^4 B + (a^3 dy_0 + a^2 dy_1 + a dy_2 + dy_3)
         double dyd[R];
@@ -611,7 +616,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
 #pragma unroll
         for (int t = 0; t < K; ++t) { sv_re[t] = 0; sv_im[t] = 0; sw_re[t] = 0; sw_im[t] = 0; }
 #pragma unroll 1
-        for (int q = 0; q < R / 4; ++q) {
+        for (int q = 0; q < (wave_dead ? 0 : R / 4); ++q) {
           float ya[NS][4], yb[NS][4], gr[4], gi[4];
           if constexpr (kStash) {
             const float* stg = &s_out[wid][0] + lane * kStride;
@@ -802,6 +807,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
         // path and the wave reconverges before the cooperative store
 #pragma unroll
         for (int u = 0; u < R / kSub; ++u) {
+          if (wave_dead) break;
           if constexpr (kStash) {
 #pragma unroll
             for (int q = u * (kSub / 4); q < (u + 1) * (kSub / 4); ++q) {
