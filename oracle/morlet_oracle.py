@@ -51,7 +51,7 @@ __all__ = [
     "select_PS", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
     "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
     "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
-    "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d",
+    "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d", "sliding_sum", "forward_tree",
 ]
 
 
@@ -681,4 +681,53 @@ def gauss_smooth_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
     rows = np.stack([forward(img[r], plan_x) for r in range(H)]) if H and W else np.zeros((H, W))
     out = np.stack([forward(rows[:, c], plan_y) for c in range(W)], axis=1) if H and W else np.zeros((H, W))
     return out
+
+
+# --------------------------------------------------------------------------
+# The paper's GPU route (Sec. IV): window sums by binary doubling (Algorithm 1)
+# --------------------------------------------------------------------------
+def sliding_sum(f: np.ndarray, Lw: int) -> np.ndarray:
+    """h[n] = sum_{k=0}^{Lw-1} f[n+k] for every n, f zero past its end (Algorithm 1): with
+    g_0 = f and h_0 = 0, for each bit r of Lw from the lowest,
+    h <- g_r[n] + h[n + 2^r] if bit r is set, then g_{r+1}[n] = g_r[n] + g_r[n + 2^r]."""
+    f = np.asarray(f)
+    M = f.shape[0]
+    g = f.copy()
+    h = np.zeros_like(f)
+    r = 0
+    while (Lw >> r) > 0:
+        s = 1 << r
+
+        def shifted(a):
+            out = np.zeros_like(a)
+            if s < M:
+                out[:M - s] = a[s:]
+            return out
+
+        if (Lw >> r) & 1:
+            h = g + shifted(h)
+        g = g + shifted(g)
+        r += 1
+    return h
+
+
+def forward_tree(x: np.ndarray, plan: Plan) -> np.ndarray:
+    """SFT Morlet (or Gaussian) result by the route of Sec. IV: per order p the window sum
+    S_p[n] = sum_{j=n-L}^{n+L} x[j] e^{i beta p j} by sliding_sum() of f_p[m] = x[m-L] e^{i beta p (m-L)},
+    then Z_p[n] = e^{-i beta p n} S_p[n] and the K-term combination of forward()."""
+    if plan.mode != "sft":
+        raise ValueError("the sliding-sum route is the SFT form")
+    x = np.asarray(x, dtype=np.float64)
+    N, L = x.shape[0], plan.L
+    acc = np.zeros(N, dtype=np.complex128)
+    if N == 0:
+        return acc if plan.kind == "morlet" else acc.real
+    m = np.arange(N + 2 * L)
+    j = m - L
+    xm = np.where((j >= 0) & (j < N), np.concatenate([np.zeros(L), x, np.zeros(L)]), 0.0)
+    for i, p in enumerate(plan.orders):
+        h = sliding_sum(xm * phase(int(p), j, L), 2 * L + 1)[:N]
+        Z = np.conj(phase(int(p), np.arange(N), L)) * h
+        acc += plan.cos_coef[i] * Z.real - 1j * plan.sin_coef[i] * Z.imag
+    return acc if plan.kind == "morlet" else acc.real
 

@@ -744,3 +744,24 @@ def test_gauss_2d_separable_cosine_image():
     gy = sum(O.kterm_gauss(py)[k + 11] * math.cos(w1 * k) for k in range(-11, 12))
     y = O.gauss_smooth_2d(img, px, py)
     assert np.allclose(y[11:H - 11, 8:W - 8], gx * gy * img[11:H - 11, 8:W - 8], rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- the paper's GPU route (Sec. IV)
+@pytest.mark.parametrize("Lw", [1, 2, 3, 7, 8, 64, 129, 1000])
+def test_sliding_sum_equals_direct_window_sum(Lw):
+    rng = np.random.default_rng(Lw)
+    f = rng.standard_normal(300) + 1j * rng.standard_normal(300)
+    want = np.array([f[n:n + Lw].sum() for n in range(300)])
+    assert np.allclose(O.sliding_sum(f, Lw), want, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["morlet", "gauss"])
+@pytest.mark.parametrize("N,sigma,K,L", [(1, 3.0, 3, 9), (64, 5.0, 5, 20), (500, 20.0, 6, 80), (300, 8.0, 4, 31)])
+def test_tree_route_equals_kernel_integral(kind, N, sigma, K, L):
+    # two summation orders of the same K-term convolution: binary doubling over the window
+    # (Algorithm 1) and the kernel-integral recurrence
+    rng = np.random.default_rng(N + K)
+    x = rng.standard_normal(N)
+    pl = O.plan_morlet(sigma, 6.0 / sigma, K, L) if kind == "morlet" else O.plan_gauss(sigma, K, L)
+    a, b = O.forward_tree(x, pl), O.forward(x, pl)
+    assert np.allclose(a, b, rtol=1e-10, atol=1e-12 * max(np.abs(b).max(), 1e-300))
