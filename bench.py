@@ -339,6 +339,11 @@ def bench_paper_scale(args, torch, M):
     torch.cuda.synchronize()
     dsteps = max(3, min(args.steps, 10))
     _, direct_ms = _timed(torch, lambda: plan.direct(xt, H, out=dout), dsteps, 1)
+    # the paper's own GPU route (Sec. IV): window sums by binary doubling, SFT
+    tplan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L)
+    tplan.tree(xt, out=dout)
+    torch.cuda.synchronize()
+    _, tree_ms = _timed(torch, lambda: tplan.tree(xt, out=dout), dsteps, 1)
     line = {
         "metric": "Gsamples*scales/s (ASFT-scan Morlet transform)",
         "value": N / (ms_step * 1e-3) / 1e9,
@@ -353,6 +358,9 @@ def bench_paper_scale(args, torch, M):
         "graph_replay_ms": graph_ms,
         "direct_conv": {"half_width": H, "ms": direct_ms, "speedup": direct_ms / kern_ms,
                         "what": "same GPU, exact taps on [-3 sigma, 3 sigma], float32 FMA, HIP events"},
+        "sliding_sum_tree": {"ms": tree_ms, "speedup": tree_ms / kern_ms,
+                             "what": "the paper's GPU route (binary doubling of the window sums, Algorithm 1), "
+                                     "same GPU, SFT, HIP events over its launches"},
     }
     if not args.no_cpu:
         p = O.plan_morlet(sigma, 6.0 / sigma, K, L, mode=args.mode,

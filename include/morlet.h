@@ -302,6 +302,19 @@ morlet_status morlet_scalogram_backward(morlet_plan_t plan, const void* x_packed
 morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W,
                                     int64_t half_width, void* stream);
 
+/* Comparison path: the paper's own GPU route (Sec. IV). Per order p the window sum of
+ * x[j] e^{i beta p j} over [n - L, n + L] by binary doubling (Algorithm 1), then demodulation
+ * and the K-term combination: the same SFT result as morlet_forward / gauss_smooth (SFT
+ * mode only) by another summation order, O(N K log L) work in log2(2L + 1) levels (the first
+ * nine in one LDS pass, one global pass per further level). For single-signal Morlet plans
+ * (out: complex64 [N]) and Gaussian smoothing plans (out: float32 [N]). The workspace
+ * (morlet_tree_workspace_size: 4 K (N + 2L) complex float32, no initialisation needed)
+ * belongs to the caller. Errors: MORLET_ERR_INVALID_ARG (other plan kinds, null pointers),
+ * MORLET_ERR_UNSUPPORTED (ASFT mode, unknown dtype), MORLET_ERR_WORKSPACE, MORLET_ERR_HIP. */
+morlet_status morlet_tree_workspace_size(morlet_plan_t plan, size_t* bytes);
+morlet_status morlet_tree_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* out, void* ws,
+                                  size_t ws_bytes, void* stream);
+
 /* Destroy a plan (NULL is ignored). Not stream-ordered: no call using it may be pending. */
 void morlet_destroy(morlet_plan_t plan);
 

@@ -79,6 +79,20 @@ class _PlanBase:
     def workspace_bytes(self) -> int:
         return _abi.morlet_workspace_size(self.handle)
 
+    def tree(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Comparison path: the same SFT result by the paper's sliding-sum route (Sec. IV,
+        Algorithm 1), single-signal Morlet and Gaussian smoothing plans in SFT mode."""
+        self._check_x(x)
+        if out is None:
+            out = self._out_like(x)
+        need = _abi.morlet_tree_workspace_size(self.handle)
+        tw = getattr(self, "_tree_ws", None)
+        if tw is None or tw.numel() < need or tw.device != x.device:
+            tw = self._tree_ws = torch.empty(max(need, 64), dtype=torch.uint8, device=x.device)
+        _abi.morlet_tree_forward(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(), tw.data_ptr(),
+                                 tw.numel(), _stream())
+        return out
+
     def backward_workspace_bytes(self) -> int:
         return _abi.morlet_backward_workspace_size(self.handle)
 

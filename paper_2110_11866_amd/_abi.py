@@ -30,6 +30,8 @@ SIGNATURES = {
     "morlet_plan_gauss_deriv": (ctypes.c_int, [_P(_vp), _i64, _dbl, _i32, _i64, _i32]),
     "morlet_plan_multiply": (ctypes.c_int, [_P(_vp), _i64, _dbl, _dbl, _i32, _i64]),
     "morlet_plan_gauss2d": (ctypes.c_int, [_P(_vp), _i64, _i64, _dbl, _dbl, _i32, _i64, _i64]),
+    "morlet_tree_workspace_size": (ctypes.c_int, [_vp, _P(_sz)]),
+    "morlet_tree_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "gauss_smooth2d": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "morlet_image_axis_info": (ctypes.c_int, [_vp, _i32, _P(_i64), _P(_i64), _P(_dbl), _P(_dbl)]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
@@ -229,3 +231,15 @@ def morlet_destroy(plan: int) -> None:
 
 def morlet_last_error() -> str:
     return lib().morlet_last_error().decode()
+
+
+def morlet_tree_workspace_size(plan: int) -> int:
+    n = ctypes.c_size_t()
+    check(lib().morlet_tree_workspace_size(plan, ctypes.byref(n)))
+    return n.value
+
+
+def morlet_tree_forward(plan: int, x_ptr: int, dtype: int, out_ptr: int, ws_ptr: int, ws_bytes: int,
+                        stream: int) -> None:
+    check(lib().morlet_tree_forward(plan, x_ptr, dtype, out_ptr, ws_ptr, ws_bytes, stream))
+

@@ -1072,6 +1072,40 @@ morlet_status morlet_scalogram_backward(morlet_plan_t plan, const void* x_packed
   return run_backward(plan, x_packed, (int)dtype, gW_packed, gx_packed, gparams, ws, ws_bytes, stream, 0, true);
 }
 
+static bool tree_plan_ok(morlet_plan_t plan) {
+  return plan && !plan->batched && !plan->multiply && !plan->image2d && plan->deriv == 0 &&
+         (plan->kind == 0 || plan->kind == 1);
+}
+
+morlet_status morlet_tree_workspace_size(morlet_plan_t plan, size_t* bytes) {
+  if (!bytes) return fail(MORLET_ERR_INVALID_ARG, "null output");
+  if (!tree_plan_ok(plan)) return fail(MORLET_ERR_INVALID_ARG, "needs a single-signal Morlet or Gaussian smoothing plan");
+  *bytes = 4 * (size_t)plan->K * (size_t)(plan->N + 2 * plan->L) * sizeof(float2);
+  return MORLET_OK;
+}
+
+morlet_status morlet_tree_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* out, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  if (!tree_plan_ok(plan)) return fail(MORLET_ERR_INVALID_ARG, "needs a single-signal Morlet or Gaussian smoothing plan");
+  if (plan->mode != MORLET_SCAN_SFT) return fail(MORLET_ERR_UNSUPPORTED, "the sliding-sum route is the SFT form");
+  if ((int)dtype < 0 || (int)dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  if (plan->N == 0) return MORLET_OK;
+  if (!x || !out || !ws) return fail(MORLET_ERR_INVALID_ARG, "null x, output or workspace pointer");
+  size_t need = 0;
+  (void)morlet_tree_workspace_size(plan, &need);
+  if (ws_bytes < need) return fail(MORLET_ERR_WORKSPACE, "workspace too small");
+  mk::TreeCoef c{};
+  c.K = plan->K;
+  for (int t = 0; t < plan->K; ++t) {
+    c.cc[t] = plan->cc[t];
+    c.sc[t] = plan->sc[t];
+  }
+  const hipError_t e = mk::launch_tree(x, (int)dtype, plan->N, plan->L, plan->K, plan->P_S, c, plan->kind == 1 ? 1 : 0,
+                                       static_cast<float2*>(ws), out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
+}
+
 morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W,
                                     int64_t half_width, void* stream) {
   if (!plan || plan->batched || plan->kind != 0) return fail(MORLET_ERR_INVALID_ARG, "needs a single-signal Morlet plan");

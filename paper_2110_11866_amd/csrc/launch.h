@@ -62,4 +62,13 @@ hipError_t launch_mm_remodulate(const float* g, float2* W, int64_t N, double xi,
 // out[c][r] = in[r][c] for an R x C row-major float32 matrix (separable 2-D filtering).
 hipError_t launch_transpose(const float* in, float* out, int64_t R, int64_t C, hipStream_t s);
 
+// The paper's sliding-sum route (comparison path): K-term combination weights, and the
+// launches over a buffer of 4 K (N + 2L) complex float32 (g and h, two of each).
+struct TreeCoef {
+  int K;
+  double cc[kMaxTerms], sc[kMaxTerms];
+};
+hipError_t launch_tree(const void* x, int dtype, int64_t N, int64_t L, int K, int P_S, const TreeCoef& coef,
+                       int real_out, float2* buf, void* W, hipStream_t s);
+
 }  // namespace mk

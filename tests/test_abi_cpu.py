@@ -365,3 +365,26 @@ def test_image_plan_errors_and_workspace():
         assert L.gauss_smooth2d(h1, 1 << 20, 0, 1 << 20, 1 << 20, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
     finally:
         _abi.morlet_destroy(h1)
+
+
+def test_tree_path_errors_and_workspace():
+    L = _abi.lib()
+    h = _abi.morlet_plan(5000, 20.0, 0.3, 5, 80)
+    hg = _abi.morlet_plan_gauss(5000, 20.0, 4, 80)
+    hd = _abi.morlet_plan_gauss_deriv(5000, 20.0, 4, 80, 1)
+    hs = _abi.morlet_scalogram_plan([100, 200], [4.0, 8.0], [1.5, 0.75], 4, 0.0)
+    fake = 1 << 20
+    try:
+        assert _abi.morlet_tree_workspace_size(h) == 4 * 5 * (5000 + 160) * 8
+        assert _abi.morlet_tree_workspace_size(hg) == 4 * 4 * (5000 + 160) * 8
+        n = ctypes.c_size_t()
+        for bad in (hd, hs):
+            assert L.morlet_tree_workspace_size(bad, ctypes.byref(n)) == _abi.MORLET_ERR_INVALID_ARG
+            assert L.morlet_tree_forward(bad, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_tree_forward(h, fake, 0, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
+        assert L.morlet_tree_forward(h, fake, 7, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        _abi.morlet_plan_set(h, _abi.MORLET_SCAN_ASFT, 0, 0)
+        assert L.morlet_tree_forward(h, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+    finally:
+        for x in (h, hg, hd, hs):
+            _abi.morlet_destroy(x)
