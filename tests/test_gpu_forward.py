@@ -308,3 +308,40 @@ def test_long_row_crosses_super_groups(mode):
     p = O.plan_morlet(sigma, 6.0 / sigma, K, L, mode=mode, n0=info["n0"] if mode == "asft" else None)
     want = O.forward(x.astype(np.float64), p)
     assert rel_l2(a.cpu().numpy(), want) <= 1e-5, rel_l2(a.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_max_single_row_sampled(mode):
+    # one 2^30-sample row: 262144 tiles, 64 super-groups of the look-back; outputs sampled at the
+    # ends, around tile / group / super-group boundaries and at random, each checked against the
+    # oracle's plain sum over its own window of the same (device-generated) input
+    import paper_2110_11866_amd as M
+    _announce("max-row", mode)
+    N, sigma, K, L = 1 << 30, 64.0, 5, 0
+    gen = torch.Generator(device="cuda").manual_seed(30)
+    xt = torch.randn(N, generator=gen, device="cuda")
+    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode)
+    W = plan.forward(xt)
+    torch.cuda.synchronize()
+    info = plan.info()
+    L, n0 = info["L"], info["n0"]
+    p = O.plan_morlet(sigma, 6.0 / sigma, K, L, mode=mode, n0=n0 if mode == "asft" else None, P_S=info["P_S"])
+    h, shift = (O.asft_kernel(p), n0) if mode == "asft" else (O.kterm_morlet(p), 0)
+    T = 16 * 256
+    ns = {0, 1, L, N - 1, N - 2, N - L - 1}
+    for j in (T, 64 * T, 4096 * T, 5 * 4096 * T, 63 * 4096 * T, 64 * 4096 * T - T):
+        for d in (-1, 0, 1):
+            ns.add(j + d - (L - n0))      # output at scan position j + d
+    ns.update(int(v) for v in np.random.default_rng(31).integers(0, N, 40))
+    ns = sorted(n for n in ns if 0 <= n < N)
+    got = W[torch.tensor(ns, device="cuda")].cpu().numpy()
+    want = np.zeros(len(ns), dtype=np.complex128)
+    for i, n in enumerate(ns):
+        a, b = max(0, n - shift - L), min(N, n - shift + L + 1)
+        seg = xt[a:b].double().cpu().numpy()
+        want[i] = O.conv_same_at(seg, h, L, np.array([n - a]), shift)[0]
+    err = np.abs(got - want) / np.abs(want).max()
+    print(f"[result] {mode}: {len(ns)} sampled outputs, max error {err.max():.2e} of the largest", flush=True)
+    assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
+    del W, xt
+    torch.cuda.empty_cache()
