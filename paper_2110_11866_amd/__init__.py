@@ -68,7 +68,7 @@ class _PlanBase:
 
     def autotune(self, x: torch.Tensor, reps: int = 5) -> dict:
         """Time the forward on x for each tile shape (and schedule, for scalograms) and keep
-        the fastest; returns {"R": 16 | 32, "schedule": "tiles" | "rows"}."""
+        the fastest; returns {"R": 4 | 8 | 16 | 32, "schedule": "tiles" | "rows"}."""
         self._check_x(x)
         out = self._out_like(x)
         R, sched = _abi.morlet_plan_autotune(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(),
