@@ -98,19 +98,22 @@ def _timed(torch, fn, steps, warmup):
     return wall * 1e3 / steps, float(np.mean(kern))
 
 
-def _cpu_oracle_rows(x, offs, lengths, rows, plan_of, budget_s=12.0):
-    """Time the FP64 oracle over (signal, scale) rows until the budget is spent."""
+def _cpu_oracle_rows(x, offs, lengths, rows, plan_of, budget_s=12.0, keep=0):
+    """Time the FP64 oracle over (signal, scale) rows until the budget is spent; the results
+    of the first `keep` rows are returned for the accuracy figure."""
     from oracle import morlet_oracle as O
-    done_samples, t0, used = 0, time.perf_counter(), 0
+    done_samples, t0, used, kept = 0, time.perf_counter(), 0, []
     for (b, s) in rows:
         p = plan_of(s)
-        O.forward(x[offs[b]:offs[b] + lengths[b]].astype(np.float64), p)
+        y = O.forward(x[offs[b]:offs[b] + lengths[b]].astype(np.float64), p)
+        if len(kept) < keep:
+            kept.append(((b, s), y))
         done_samples += int(lengths[b])
         used += 1
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
-    return done_samples / el / 1e9, used, done_samples
+    return done_samples / el / 1e9, used, done_samples, kept
 
 
 def bench_scalogram(args, torch, M):
@@ -158,11 +161,20 @@ def bench_scalogram(args, torch, M):
             return cache[s]
         rng = np.random.default_rng(7)
         rows = [(int(rng.integers(0, len(lengths))), int(rng.integers(0, S))) for _ in range(400)]
-        rate, used, nsamp = _cpu_oracle_rows(x, offs, lengths, rows, plan_of)
+        rate, used, nsamp, kept = _cpu_oracle_rows(x, offs, lengths, rows, plan_of, keep=64)
         line["cpu_baseline"] = {"value": rate, "unit": "Gsamples*scales/s", "cores": 1, "kind": "oracle",
                                 "sample": f"{used} random (signal, scale) rows of the same workload "
                                           f"({nsamp} samples x scales), numpy float64 kernel-integral "
                                           "recurrences, one thread"}
+        # accuracy of the timed launch's output on the oracle rows kept above (rel-L2 per row)
+        errs = []
+        for (b, s), y in kept:
+            o = plan.out_offset(b, s)
+            g = out[o:o + int(lengths[b])].cpu().numpy().astype(np.complex128)
+            if len(y):
+                errs.append(float(np.linalg.norm(g - y) / max(np.linalg.norm(y), 1e-300)))
+        line["rel_l2_vs_fp64"] = {"max": max(errs), "median": float(np.median(errs)), "rows": len(errs),
+                                  "bar": 1e-5}
     return line
 
 

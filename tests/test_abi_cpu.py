@@ -388,3 +388,23 @@ def test_tree_path_errors_and_workspace():
     finally:
         for x in (h, hg, hd, hs):
             _abi.morlet_destroy(x)
+
+
+def test_empty_inputs_of_the_newer_paths():
+    # N = 0 (or an empty image) is a no-op that succeeds before any pointer is looked at
+    L = _abi.lib()
+    hm = _abi.morlet_plan_multiply(0, 10.0, 0.6, 2, 0)
+    hi = _abi.morlet_plan_gauss2d(0, 50, 3.0, 3.0, 4, 0, 0)
+    hj = _abi.morlet_plan_gauss2d(40, 0, 3.0, 3.0, 4, 0, 0)
+    ht = _abi.morlet_plan(0, 10.0, 0.6, 4, 40)
+    hd = _abi.morlet_plan_gauss_deriv(0, 10.0, 4, 40, 1)
+    try:
+        assert L.morlet_forward(hm, None, 0, None, None, 0, None) == _abi.MORLET_OK
+        assert L.gauss_smooth2d(hi, None, 0, None, None, 0, None) == _abi.MORLET_OK
+        assert L.gauss_smooth2d(hj, None, 0, None, None, 0, None) == _abi.MORLET_OK
+        assert L.morlet_tree_forward(ht, None, 0, None, None, 0, None) == _abi.MORLET_OK
+        _abi.morlet_plan_set(hd, _abi.MORLET_SCAN_ASFT, 0, 0)
+        assert L.gauss_smooth(hd, None, 0, None, None, 0, None) == _abi.MORLET_OK
+    finally:
+        for h in (hm, hi, hj, ht, hd):
+            _abi.morlet_destroy(h)
