@@ -686,8 +686,10 @@ morlet_status morlet_plan_gauss2d(morlet_plan_t* out, int64_t H, int64_t W, doub
   p->N = H * W;
   p->axis[0] = ax;
   p->axis[1] = ay;
-  s = init_gauss_rows(ax, (int)H, W, sigma_x, K, L_x);
-  if (s == MORLET_OK) s = init_gauss_rows(ay, (int)W, H, sigma_y, K, L_y);
+  // an empty image has no lines to filter on either axis
+  const bool empty = H == 0 || W == 0;
+  s = init_gauss_rows(ax, empty ? 0 : (int)H, W, sigma_x, K, L_x);
+  if (s == MORLET_OK) s = init_gauss_rows(ay, empty ? 0 : (int)W, H, sigma_y, K, L_y);
   if (s != MORLET_OK) {
     morlet_destroy(p);
     return s;
