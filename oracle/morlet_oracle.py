@@ -52,6 +52,7 @@ __all__ = [
     "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
     "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
     "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d", "sliding_sum", "forward_tree",
+    "forward_edge",
 ]
 
 
@@ -730,4 +731,19 @@ def forward_tree(x: np.ndarray, plan: Plan) -> np.ndarray:
         Z = np.conj(phase(int(p), np.arange(N), L)) * h
         acc += plan.cos_coef[i] * Z.real - 1j * plan.sin_coef[i] * Z.imag
     return acc if plan.kind == "morlet" else acc.real
+
+
+# --------------------------------------------------------------------------
+# Edge extension (Sec. II: x beyond [0, N-1] is zero or the value on the edge)
+# --------------------------------------------------------------------------
+def forward_edge(x: np.ndarray, plan: Plan) -> np.ndarray:
+    """forward() with x extended by its edge values instead of zeros: every output n reads
+    x[n - n0 - k] for |k| <= L, i.e. at most 2L samples outside [0, N-1] on either side, so x is
+    padded by 2L copies of x[0] and of x[N-1] and the central N outputs are kept."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    if N == 0:
+        return forward(x, plan)
+    P = 2 * plan.L
+    return forward(np.pad(x, (P, P), mode="edge"), plan)[P:P + N]
 

@@ -765,3 +765,30 @@ def test_tree_route_equals_kernel_integral(kind, N, sigma, K, L):
     pl = O.plan_morlet(sigma, 6.0 / sigma, K, L) if kind == "morlet" else O.plan_gauss(sigma, K, L)
     a, b = O.forward_tree(x, pl), O.forward(x, pl)
     assert np.allclose(a, b, rtol=1e-10, atol=1e-12 * max(np.abs(b).max(), 1e-300))
+
+
+# ---------------------------------------------------------------- edge extension (Sec. II)
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_edge_extension_constant_signal_everywhere(mode):
+    # a constant signal extended by its edges is constant everywhere, so every output, edges
+    # included, is c times the sum of the taps (zero extension would fall off near the ends)
+    c, N, sigma, K, L = 1.3, 90, 6.0, 5, 24
+    pm = O.plan_morlet(sigma, 6.0 / sigma, K, L, mode=mode, n0=3 if mode == "asft" else None)
+    pg = O.plan_gauss(sigma, K, L, mode=mode, n0=3 if mode == "asft" else None)
+    for pl in (pm, pg):
+        taps = O.asft_kernel(pl) if mode == "asft" else (O.kterm_morlet(pl) if pl.kind == "morlet" else O.kterm_gauss(pl))
+        y = O.forward_edge(np.full(N, c), pl)
+        assert np.allclose(y, c * taps.sum(), rtol=1e-12, atol=1e-12)
+        assert not np.allclose(O.forward(np.full(N, c), pl)[:3], c * taps.sum(), rtol=1e-3)
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+@pytest.mark.parametrize("N", [1, 7, 40])
+def test_edge_extension_brute_force(mode, N):
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal(N)
+    L = 9
+    pl = O.plan_morlet(3.0, 2.0, 4, L, mode=mode, n0=2 if mode == "asft" else None)
+    h, s = (O.asft_kernel(pl), pl.n0) if mode == "asft" else (O.kterm_morlet(pl), 0)
+    want = np.array([sum(h[k + L] * x[min(max(n - s - k, 0), N - 1)] for k in range(-L, L + 1)) for n in range(N)])
+    assert np.allclose(O.forward_edge(x, pl), want, rtol=1e-11, atol=1e-13)
