@@ -181,6 +181,17 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0,
  * tiles (the plan keeps its tile shape). */
 morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R);
 
+/* How a single signal is extended beyond [0, N-1] (Sec. II: zero, or the value on the edge).
+ * MORLET_BOUNDARY_ZERO (default). MORLET_BOUNDARY_EDGE: x[j] = x[0] for j < 0 and x[N-1] for
+ * j >= N; the forward (morlet_forward, gauss_smooth) pads the signal by 2L edge copies per
+ * side in the workspace, scans N + 4L samples and copies the central N outputs (the workspace
+ * grows accordingly: query morlet_workspace_size after setting). Host-only, no device work.
+ * Errors: MORLET_ERR_INVALID_ARG (unknown value), MORLET_ERR_UNSUPPORTED (scalogram,
+ * multiplication-method and image plans). With edge extension the backward calls,
+ * morlet_direct_forward and morlet_tree_forward return MORLET_ERR_UNSUPPORTED. */
+typedef enum { MORLET_BOUNDARY_ZERO = 0, MORLET_BOUNDARY_EDGE = 1 } morlet_boundary;
+morlet_status morlet_plan_set_boundary(morlet_plan_t plan, morlet_boundary boundary);
+
 /* How a batched plan's launch distributes its rows (signal x scale) over the persistent
  * blocks. MORLET_SCHED_TILES: blocks take single tiles in row order and resolve each
  * tile's incoming state with the decoupled look-back. MORLET_SCHED_ROWS: a block takes a

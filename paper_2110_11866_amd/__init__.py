@@ -44,6 +44,15 @@ class _PlanBase:
         _abi.morlet_plan_set(self.handle, _MODE[mode], int(n0), _ACC[accum])
         return self
 
+    def set_boundary(self, boundary: str) -> "_PlanBase":
+        """Extension of a single signal beyond [0, N-1]: "zero" (default) or "edge" (Sec. II)."""
+        code = {"zero": _abi.MORLET_BOUNDARY_ZERO, "edge": _abi.MORLET_BOUNDARY_EDGE}
+        if boundary not in code:
+            raise ValueError("boundary must be zero or edge")
+        _abi.morlet_plan_set_boundary(self.handle, code[boundary])
+        self._ws = None
+        return self
+
     def set_tile(self, R: int) -> "_PlanBase":
         """Samples per thread of the scan kernels (4, 8, 16 or 32)."""
         _abi.morlet_plan_set_tile(self.handle, int(R))

@@ -31,6 +31,7 @@ SIGNATURES = {
     "morlet_plan_multiply": (ctypes.c_int, [_P(_vp), _i64, _dbl, _dbl, _i32, _i64]),
     "morlet_plan_gauss2d": (ctypes.c_int, [_P(_vp), _i64, _i64, _dbl, _dbl, _i32, _i64, _i64]),
     "morlet_tree_workspace_size": (ctypes.c_int, [_vp, _P(_sz)]),
+    "morlet_plan_set_boundary": (ctypes.c_int, [_vp, ctypes.c_int]),
     "morlet_tree_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "gauss_smooth2d": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "morlet_image_axis_info": (ctypes.c_int, [_vp, _i32, _P(_i64), _P(_i64), _P(_dbl), _P(_dbl)]),
@@ -242,4 +243,11 @@ def morlet_tree_workspace_size(plan: int) -> int:
 def morlet_tree_forward(plan: int, x_ptr: int, dtype: int, out_ptr: int, ws_ptr: int, ws_bytes: int,
                         stream: int) -> None:
     check(lib().morlet_tree_forward(plan, x_ptr, dtype, out_ptr, ws_ptr, ws_bytes, stream))
+
+
+MORLET_BOUNDARY_ZERO, MORLET_BOUNDARY_EDGE = 0, 1
+
+
+def morlet_plan_set_boundary(plan: int, boundary: int) -> None:
+    check(lib().morlet_plan_set_boundary(plan, boundary))
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/morlet.h"
+#include "boundary.h"
 #include "launch.h"
 #include "plan_internal.h"
 
@@ -289,6 +290,63 @@ BwdLayout bwd_layout(morlet_plan_t plan) {
   return b;
 }
 
+// Workspace of a single-signal forward with edge extension: the tile states of the padded
+// row, the padded float32 signal (N + 4L) and its outputs (N + 4L), each 256-byte aligned.
+struct EdgeLayout {
+  size_t x_off, out_off, total;
+};
+EdgeLayout edge_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const int64_t Ne = plan->N + 4 * plan->L;
+  const size_t esize = plan->kind == 0 ? 8 : 4;
+  EdgeLayout e;
+  e.x_off = up(mk::workspace_bytes(plan->K, tiles_for(Ne + plan->L, plan->R)));
+  e.out_off = up(e.x_off + (size_t)Ne * sizeof(float));
+  e.total = e.out_off + (size_t)Ne * esize;
+  return e;
+}
+
+// Edge extension (Sec. II): every output reads at most 2L samples outside [0, N-1], so the
+// signal is padded by 2L edge copies on each side, scanned as one zero-extended row of
+// N + 4L samples, and the central N outputs are copied out.
+morlet_status run_edge(morlet_plan_t plan, const void* x, int dtype, void* out, void* ws, size_t ws_bytes,
+                       void* stream) {
+  if (plan->N == 0) return MORLET_OK;
+  if (!x || !out || !ws) return fail(MORLET_ERR_INVALID_ARG, "null x, output or workspace pointer");
+  const EdgeLayout e = edge_layout(plan);
+  if (ws_bytes < e.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  const int64_t P = 2 * plan->L, Ne = plan->N + 2 * P;
+  const int64_t jend = Ne + plan->L - plan->n0;
+  const int64_t ntiles = tiles_for(jend, plan->R);
+  if (ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* xe = reinterpret_cast<float*>(wsb + e.x_off);
+  unsigned char* oe = wsb + e.out_off;
+  hipError_t err = mk::launch_edge_extend(x, dtype, plan->N, P, xe, s);
+  if (err != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(err));
+  mk::ScanLaunch a;
+  const morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0, 0);
+  if (st != MORLET_OK) return st;
+  a.row0.N = Ne;
+  a.row0.jend = jend;
+  a.row0.ntiles = (int32_t)ntiles;
+  a.ntiles = ntiles;
+  const int occ = mk::scan_occupancy(a.K, a.R, mk::kVarForward, a.wide, a.kind, 0, 0);
+  const int64_t cap = (int64_t)(occ > 0 ? occ : 1) * plan->num_cus;
+  a.grid = (int)(ntiles < cap ? ntiles : cap);
+  a.x = xe;
+  a.dtype = 0;
+  a.out = oe;
+  err = mk::launch_scan(a, mk::kVarForward, 0, s);
+  const size_t esize = plan->kind == 0 ? 8 : 4;
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(out, oe + (size_t)P * esize, (size_t)plan->N * esize, hipMemcpyDeviceToDevice, s);
+  if (err != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(err));
+  return MORLET_OK;
+}
+
 morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, void* ws, size_t ws_bytes,
                        void* stream, int want_kind, bool want_batched = false) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
@@ -299,6 +357,7 @@ morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, 
   if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
   if (want_batched != plan->batched)
     return fail(MORLET_ERR_INVALID_ARG, want_batched ? "needs a scalogram plan" : "needs a single-signal plan");
+  if (plan->boundary == 1) return run_edge(plan, x, dtype, out, ws, ws_bytes, stream);
   const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(plan->N + plan->L - plan->n0, plan->R);
   if (plan->N == 0 || ntiles == 0) return MORLET_OK;
   if (!x || !out || !ws) return fail(MORLET_ERR_INVALID_ARG, "null x, output or workspace pointer");
@@ -419,6 +478,7 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (plan->multiply) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for multiplication-method plans");
   if (plan->image2d) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for image plans");
+  if (plan->boundary != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass with edge extension");
   if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
   if (plan->deriv != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for differential smoothing plans");
   if (want_batched != plan->batched)
@@ -752,6 +812,16 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
   return MORLET_OK;
 }
 
+morlet_status morlet_plan_set_boundary(morlet_plan_t plan, morlet_boundary boundary) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (boundary != MORLET_BOUNDARY_ZERO && boundary != MORLET_BOUNDARY_EDGE)
+    return fail(MORLET_ERR_INVALID_ARG, "unknown boundary");
+  if (plan->batched || plan->multiply || plan->image2d)
+    return fail(MORLET_ERR_UNSUPPORTED, "edge extension is built for single-signal plans");
+  plan->boundary = (int)boundary;
+  return MORLET_OK;
+}
+
 morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule schedule) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (plan->image2d) {
@@ -916,6 +986,10 @@ morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes) {
     *bytes = image_layout(plan).total;
     return MORLET_OK;
   }
+  if (plan->boundary == 1) {
+    *bytes = edge_layout(plan).total;
+    return MORLET_OK;
+  }
   *bytes = plan->multiply ? mult_layout(plan).total
                           : mk::workspace_bytes(plan->K, plan->batched ? plan->ntiles_max : tiles_for(plan->N + plan->L, plan->R));
   return MORLET_OK;
@@ -1076,7 +1150,7 @@ morlet_status morlet_scalogram_backward(morlet_plan_t plan, const void* x_packed
 
 static bool tree_plan_ok(morlet_plan_t plan) {
   return plan && !plan->batched && !plan->multiply && !plan->image2d && plan->deriv == 0 &&
-         (plan->kind == 0 || plan->kind == 1);
+         (plan->kind == 0 || plan->kind == 1) && plan->boundary == 0;
 }
 
 morlet_status morlet_tree_workspace_size(morlet_plan_t plan, size_t* bytes) {
@@ -1111,6 +1185,7 @@ morlet_status morlet_tree_forward(morlet_plan_t plan, const void* x, morlet_dtyp
 morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W,
                                     int64_t half_width, void* stream) {
   if (!plan || plan->batched || plan->kind != 0) return fail(MORLET_ERR_INVALID_ARG, "needs a single-signal Morlet plan");
+  if (plan->boundary != 0) return fail(MORLET_ERR_UNSUPPORTED, "the direct-convolution baseline extends by zeros only");
   if ((int)dtype < 0 || (int)dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
   if (half_width < 0 || half_width > ((int64_t)1 << 30)) return fail(MORLET_ERR_INVALID_ARG, "bad half width");
   if (plan->N == 0) return MORLET_OK;

@@ -29,6 +29,7 @@ struct morlet_plan_s {
   int64_t n0 = 0;         // ASFT shift (0 for SFT)
   int64_t n0_asft = 0;    // shift used when ASFT is selected
   int accum = 0;          // 0 float32, 1 compensated (float64)
+  int boundary = 0;       // single signals: 0 zero extension, 1 edge values (Sec. II)
   std::vector<double> cc, sc;   // cos / sin coefficients (m, l) or (a, 0)
   std::vector<double> jac;      // [4K]: dcc/dsigma, dcc/dxi, dsc/dsigma, dsc/dxi
   double relrmse = 0;

@@ -408,3 +408,29 @@ def test_empty_inputs_of_the_newer_paths():
     finally:
         for h in (hm, hi, hj, ht, hd):
             _abi.morlet_destroy(h)
+
+
+def test_edge_boundary_setting():
+    L = _abi.lib()
+    h = _abi.morlet_plan(1000, 20.0, 0.3, 5, 80)
+    hs = _abi.morlet_scalogram_plan([100, 200], [4.0, 8.0], [1.5, 0.75], 4, 0.0)
+    hm = _abi.morlet_plan_multiply(1000, 20.0, 0.3, 2, 0)
+    hd = _abi.morlet_plan_gauss_deriv(1000, 20.0, 4, 80, 2)
+    fake = 1 << 20
+    try:
+        base = _abi.morlet_workspace_size(h)
+        _abi.morlet_plan_set_boundary(h, _abi.MORLET_BOUNDARY_EDGE)
+        assert _abi.morlet_workspace_size(h) >= base + (1000 + 4 * 80) * (4 + 8)
+        assert L.morlet_plan_set_boundary(h, 5) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_backward(h, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_direct_forward(h, fake, 0, fake, 0, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_tree_forward(h, fake, 0, fake, fake, 1 << 30, None) != _abi.MORLET_OK
+        assert L.morlet_forward(h, fake, 0, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
+        for bad in (hs, hm):
+            assert L.morlet_plan_set_boundary(bad, _abi.MORLET_BOUNDARY_EDGE) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_plan_set_boundary(hd, _abi.MORLET_BOUNDARY_EDGE) == _abi.MORLET_OK
+        _abi.morlet_plan_set_boundary(h, _abi.MORLET_BOUNDARY_ZERO)
+        assert _abi.morlet_workspace_size(h) == base
+    finally:
+        for x in (h, hs, hm, hd):
+            _abi.morlet_destroy(x)

@@ -345,3 +345,37 @@ def test_max_single_row_sampled(mode):
     assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
     del W, xt
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind", ["morlet", "gauss", "gd1", "gd2"])
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+@pytest.mark.parametrize("N,sigma,K,L,dtype,accum", [(3, 4.0, 3, 16, torch.float32, "f32"),
+                                                     (37, 8.0, 4, 40, torch.float32, "f32"),
+                                                     (5000, 30.0, 5, 0, torch.bfloat16, "f32"),
+                                                     (50000, 300.0, 6, 1200, torch.float32, "compensated")])
+def test_edge_extension_parity(N, sigma, K, L, dtype, accum, mode, kind):
+    # x extended by its edge values (Sec. II) instead of zeros (N >= 3: a 1-sample signal extends
+    # to a constant, whose odd-kernel and zero-mean-kernel outputs are exactly zero)
+    import paper_2110_11866_amd as M
+    _announce("edge", kind, mode, N, sigma, K, L, dtype, accum)
+    x = (np.random.default_rng(N + K).standard_normal(N) + 2.0).astype(np.float32)   # nonzero mean: edges matter
+    xt = torch.from_numpy(x).cuda().to(dtype)
+    if kind == "morlet":
+        plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode, accum=accum)
+    elif kind == "gauss":
+        plan = M.GaussPlan(N, sigma, K, L, mode=mode, accum=accum)
+    else:
+        plan = M.GaussDerivPlan(N, sigma, K, L, order=1 if kind == "gd1" else 2, mode=mode, accum=accum)
+    plan.set_boundary("edge")
+    got = plan.forward(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    info = plan.info()
+    n0 = info["n0"] if mode == "asft" else None
+    if kind == "morlet":
+        p = O.plan_morlet(sigma, 6.0 / sigma, K, info["L"], mode=mode, n0=n0)
+    elif kind == "gauss":
+        p = O.plan_gauss(sigma, K, info["L"], mode=mode, n0=n0)
+    else:
+        p = O.plan_gauss_deriv(sigma, K, info["L"], 1 if kind == "gd1" else 2, mode=mode, n0=n0)
+    want = O.forward_edge(xt.double().cpu().numpy(), p)
+    assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
