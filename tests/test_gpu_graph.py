@@ -124,3 +124,24 @@ def test_autotune_single_and_scalogram():
             o = sp.out_offset(b, s)
             got = W[o:o + lengths[b]]
             assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-5, (b, s)
+
+
+def test_graph_newer_forward_paths():
+    # the multiplication method (three kernels), the 2-D smoothing (two scans, two transposes)
+    # and the edge-extended forward (extension kernel, scan, device-to-device copy) replay
+    # bitwise like their eager calls
+    import paper_2110_11866_amd as M
+    _announce("graph-newer")
+    N = 40000
+    xt = torch.from_numpy(np.random.default_rng(5).standard_normal(N).astype(np.float32)).cuda()
+    fresh = lambda k: torch.from_numpy(np.random.default_rng(200 + k).standard_normal(N).astype(np.float32)).cuda()
+    pm = M.MultiplyPlan(N, 50.0, 6 / 50.0, 3, mode="asft")
+    wm, om = pm.workspace(xt.device), torch.empty(N, dtype=torch.complex64, device=xt.device)
+    _replays(lambda: (pm.forward(xt, out=om, ws=wm),), xt, fresh)
+    pe = M.GaussDerivPlan(N, 40.0, 5, 0, order=1, mode="asft").set_boundary("edge")
+    we, oe = pe.workspace(xt.device), torch.empty(N, dtype=torch.float32, device=xt.device)
+    _replays(lambda: (pe.forward(xt, out=oe, ws=we),), xt, fresh)
+    H, W = 200, 200
+    pi = M.Gauss2DPlan(H, W, 5.0, 7.0, 4, mode="asft")
+    wi, oi = pi.workspace(xt.device), torch.empty(H, W, dtype=torch.float32, device=xt.device)
+    _replays(lambda: (pi.forward(xt, out=oi, ws=wi),), xt, fresh)
