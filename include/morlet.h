@@ -186,9 +186,13 @@ morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R);
  * j >= N; the forward (morlet_forward, gauss_smooth) pads the signal by 2L edge copies per
  * side in the workspace, scans N + 4L samples and copies the central N outputs (the workspace
  * grows accordingly: query morlet_workspace_size after setting). Host-only, no device work.
+ * The backward calls (morlet_backward, gauss_smooth_backward) take the extension's transpose:
+ * the adjoint of the padded row folded back (the padded ends' gradients summed onto x[0] and
+ * x[N-1]) and the parameter gradients over the padded signal; morlet_backward_workspace_size
+ * covers them (it also serves the forward).
  * Errors: MORLET_ERR_INVALID_ARG (unknown value), MORLET_ERR_UNSUPPORTED (scalogram,
- * multiplication-method and image plans). With edge extension the backward calls,
- * morlet_direct_forward and morlet_tree_forward return MORLET_ERR_UNSUPPORTED. */
+ * multiplication-method and image plans). With edge extension morlet_direct_forward and
+ * morlet_tree_forward return MORLET_ERR_UNSUPPORTED. */
 typedef enum { MORLET_BOUNDARY_ZERO = 0, MORLET_BOUNDARY_EDGE = 1 } morlet_boundary;
 morlet_status morlet_plan_set_boundary(morlet_plan_t plan, morlet_boundary boundary);
 

@@ -473,17 +473,101 @@ morlet_status run_image2d(morlet_plan_t plan, const void* x, int dtype, float* y
   return MORLET_OK;
 }
 
+// Backward workspace of a single signal with edge extension: the states, partials and row
+// partials for the padded row (N + 4L), then the padded signal, the padded cotangent and the
+// padded row's adjoint, each 256-byte aligned.
+struct EdgeBwdLayout {
+  size_t partials_off, rowpart_off, x_off, g_off, gx_off, total;
+};
+EdgeBwdLayout edge_bwd_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const int64_t Ne = plan->N + 4 * plan->L;
+  const int64_t nt = tiles_for(Ne + plan->L, plan->R);
+  const size_t nred = (size_t)mk::pg_partials(plan->K) * sizeof(double);
+  const size_t esize = plan->kind == 0 ? 8 : 4;
+  EdgeBwdLayout b;
+  b.partials_off = up(mk::workspace_bytes(2 * plan->K, nt));
+  b.rowpart_off = up(b.partials_off + (size_t)nt * nred);
+  b.x_off = up(b.rowpart_off + nred);
+  b.g_off = up(b.x_off + (size_t)Ne * sizeof(float));
+  b.gx_off = up(b.g_off + (size_t)Ne * esize);
+  b.total = b.gx_off + (size_t)Ne * sizeof(float);
+  return b;
+}
+
+// The launch of a single-signal plan moved onto its padded row of Ne samples.
+void pad_launch(morlet_plan_t plan, mk::ScanLaunch& a, int64_t Ne, int variant, int mom, int dtype) {
+  const int64_t jend = Ne + plan->L - plan->n0;
+  const int64_t ntiles = tiles_for(jend, plan->R);
+  a.row0.N = Ne;
+  a.row0.jend = jend;
+  a.row0.ntiles = (int32_t)ntiles;
+  a.ntiles = ntiles;
+  const int occ = mk::scan_occupancy(a.K, a.R, variant, a.wide, a.kind, mom, dtype);
+  const int64_t cap = (int64_t)(occ > 0 ? occ : 1) * plan->num_cus;
+  a.grid = (int)(ntiles < cap ? ntiles : cap);
+}
+
+// Backward with edge extension: the forward is W = C A E x (E the extension, A the scan of the
+// padded row, C the central crop), so dLoss/dx = E^T A^T C^T g: the cotangent zero-padded, the
+// adjoint of the padded row, and the fold of the padded ends onto x[0] and x[N-1]; the
+// parameter gradients come from the gradient pass over (E x, C^T g).
+morlet_status run_backward_edge(morlet_plan_t plan, const void* x, int dtype, const void* g, float* gx,
+                                double* gparams, void* ws, size_t ws_bytes, void* stream) {
+  if (plan->N == 0) {
+    if (gparams) return fail(MORLET_ERR_UNSUPPORTED, "parameter gradients of an empty signal are not computed");
+    return MORLET_OK;
+  }
+  if (!g || !gx || !ws || (gparams && !x)) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  const EdgeBwdLayout b = edge_bwd_layout(plan);
+  if (ws_bytes < b.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  const int64_t P = 2 * plan->L, Ne = plan->N + 2 * P;
+  if (tiles_for(Ne + plan->L, plan->R) > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* xe = reinterpret_cast<float*>(wsb + b.x_off);
+  void* ge = wsb + b.g_off;
+  float* gxe = reinterpret_cast<float*>(wsb + b.gx_off);
+  hipError_t e = mk::launch_pad_center(g, plan->kind == 0 ? 8 : 4, plan->N, P, ge, s);
+  mk::ScanLaunch a;
+  morlet_status st = make_launch(plan, a, ws, mk::kVarAdjoint, 0, 0);
+  if (st != MORLET_OK) return st;
+  pad_launch(plan, a, Ne, mk::kVarAdjoint, 0, 0);
+  a.x = ge;
+  a.dtype = 0;
+  a.out = gxe;
+  if (e == hipSuccess) e = mk::launch_scan(a, mk::kVarAdjoint, 0, s);
+  if (e == hipSuccess) e = mk::launch_edge_fold(gxe, plan->N, P, gx, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  if (!gparams) return MORLET_OK;
+  const int mom = plan->mode == 1 ? 1 : 0;
+  e = mk::launch_edge_extend(x, dtype, plan->N, P, xe, s);
+  st = make_launch(plan, a, ws, mk::kVarParamGrad, mom, 0);
+  if (st != MORLET_OK) return st;
+  pad_launch(plan, a, Ne, mk::kVarParamGrad, mom, 0);
+  a.x = xe;
+  a.dtype = 0;
+  a.g = ge;
+  a.partials = reinterpret_cast<double*>(wsb + b.partials_off);
+  if (e == hipSuccess) e = mk::launch_scan(a, mk::kVarParamGrad, mom, s);
+  if (e == hipSuccess)
+    e = mk::launch_pg_finalize(a, 1, reinterpret_cast<double*>(wsb + b.rowpart_off), gparams, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
+}
+
 morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const void* g, float* gx, double* gparams,
                            void* ws, size_t ws_bytes, void* stream, int want_kind, bool want_batched) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
   if (plan->multiply) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for multiplication-method plans");
   if (plan->image2d) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for image plans");
-  if (plan->boundary != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass with edge extension");
   if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
   if (plan->deriv != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for differential smoothing plans");
   if (want_batched != plan->batched)
     return fail(MORLET_ERR_INVALID_ARG, want_batched ? "needs a scalogram plan" : "needs a single-signal plan");
   if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  if (plan->boundary == 1) return run_backward_edge(plan, x, dtype, g, gx, gparams, ws, ws_bytes, stream);
   const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(plan->N + plan->L - plan->n0, plan->R);
   if (plan->N == 0 || ntiles == 0) {
     if (gparams) return fail(MORLET_ERR_UNSUPPORTED, "parameter gradients of an empty signal are not computed");
@@ -1128,7 +1212,7 @@ void morlet_destroy(morlet_plan_t plan) {
 
 morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
-  *bytes = bwd_layout(plan).total;
+  *bytes = plan->boundary == 1 ? std::max(edge_bwd_layout(plan).total, edge_layout(plan).total) : bwd_layout(plan).total;
   return MORLET_OK;
 }
 

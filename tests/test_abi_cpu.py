@@ -422,7 +422,9 @@ def test_edge_boundary_setting():
         _abi.morlet_plan_set_boundary(h, _abi.MORLET_BOUNDARY_EDGE)
         assert _abi.morlet_workspace_size(h) >= base + (1000 + 4 * 80) * (4 + 8)
         assert L.morlet_plan_set_boundary(h, 5) == _abi.MORLET_ERR_INVALID_ARG
-        assert L.morlet_backward(h, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_backward(h, fake, 0, fake, fake, None, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
+        bw = _abi.morlet_backward_workspace_size(h)
+        assert bw >= (1000 + 4 * 80) * (4 + 8 + 4) and bw >= _abi.morlet_workspace_size(h)
         assert L.morlet_direct_forward(h, fake, 0, fake, 0, None) == _abi.MORLET_ERR_UNSUPPORTED
         assert L.morlet_tree_forward(h, fake, 0, fake, fake, 1 << 30, None) != _abi.MORLET_OK
         assert L.morlet_forward(h, fake, 0, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE

@@ -221,3 +221,50 @@ def test_differentiation_workload_sampled(schedule):
         for s in range(S):
             want_gp[s] += O.param_grads(xb, gn[b, s], plans[s])
     assert np.all(np.abs(gpn - want_gp) <= 1e-5 * np.abs(want_gp)), np.abs(gpn - want_gp) / np.abs(want_gp)
+
+
+def _fold(gxe, N, P):
+    # transpose of the edge extension x_ext[m] = x[clamp(m - P, 0, N - 1)]
+    gx = gxe[P:P + N].copy()
+    gx[0] += gxe[:P].sum()
+    gx[N - 1] += gxe[P + N:].sum()
+    return gx
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+@pytest.mark.parametrize("kind", ["morlet", "gauss"])
+@pytest.mark.parametrize("N,sigma,K,L", [(1, 6.0, 3, 20), (37, 8.0, 4, 40), (20000, 100.0, 5, 400)])
+def test_backward_with_edge_extension(N, sigma, K, L, kind, mode):
+    # the extension's transpose: adjoint of the padded row, folded onto the ends; parameter
+    # gradients over the padded signal; and the adjoint identity with both sides on the GPU
+    import paper_2110_11866_amd as M
+    _announce("backward-edge", N, sigma, K, L, kind, mode)
+    rng = np.random.default_rng(N + K)
+    x = (rng.standard_normal(N) + 1.0).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    if kind == "morlet":
+        plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode)
+        g = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+    else:
+        plan = M.GaussPlan(N, sigma, K, L, mode=mode)
+        g = rng.standard_normal(N).astype(np.float32)
+    plan.set_boundary("edge")
+    gt = torch.from_numpy(g).cuda()
+    W = plan.forward(xt).cpu().numpy()
+    gx, gp = plan.backward(xt, gt)
+    torch.cuda.synchronize()
+    info = plan.info()
+    p = _oracle_plan(kind, sigma, K, info, mode)
+    P = 2 * info["L"]
+    gn = g.astype(np.complex128 if kind == "morlet" else np.float64)
+    ge = np.concatenate([np.zeros(P, gn.dtype), gn, np.zeros(P, gn.dtype)])
+    want_gx = _fold(O.adjoint(ge, p), N, P)
+    assert rel(gx.cpu().numpy(), want_gx) <= 1e-5, rel(gx.cpu().numpy(), want_gx)
+    xe = np.pad(x.astype(np.float64), (P, P), mode="edge")
+    want_gp = O.param_grads(xe, ge, p)
+    got_gp = gp.cpu().numpy()
+    idx = [0] if kind == "gauss" else [0, 1]
+    assert np.all(np.abs(got_gp[idx] - want_gp[idx]) <= 1e-5 * np.abs(want_gp[idx])), (got_gp, want_gp)
+    lhs = float(np.sum((np.conj(gn) * W.astype(np.complex128)).real))
+    rhs = float(np.dot(x.astype(np.float64), gx.cpu().numpy().astype(np.float64)))
+    assert abs(lhs - rhs) <= 2e-5 * (abs(lhs) + np.sqrt(N)), (lhs, rhs)
