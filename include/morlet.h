@@ -146,7 +146,8 @@ morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, 
  * launch over the H rows, a transpose, one scan launch over the W rows of the transposed
  * image and a transpose back. morlet_plan_set (SFT/ASFT with one n0 for both axes, 0 = each
  * axis's default; accumulation), _set_tile and _set_schedule apply to both axes; autotune
- * and the backward calls return MORLET_ERR_UNSUPPORTED; morlet_plan_info returns
+ * and the 1-D backward calls return MORLET_ERR_UNSUPPORTED (gauss_smooth2d_backward is the
+ * image's backward); morlet_plan_info returns
  * MORLET_ERR_INVALID_ARG (use morlet_image_axis_info). Errors: MORLET_ERR_INVALID_ARG (H or
  * W < 0 or > 2^24, H W > 2^36, sigma not finite and > 0, K outside [1, MORLET_MAX_TERMS],
  * 0 < L < K - 1), MORLET_ERR_UNSUPPORTED (more than 2^31 tiles on an axis),
@@ -160,6 +161,14 @@ morlet_status morlet_plan_gauss2d(morlet_plan_t* out, int64_t H, int64_t W, doub
  * gauss_smooth; MORLET_ERR_INVALID_ARG for a plan that is not an image plan. */
 morlet_status gauss_smooth2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, float* y, void* ws,
                              size_t ws_bytes, void* stream);
+
+/* Backward of the 2-D smoothing for a real loss: gy = dLoss/dy (device float32, H x W) ->
+ * gx = dLoss/dx (device float32, H x W, overwritten). The smoothing is linear, so gx is its
+ * transpose applied to gy: a transpose, the adjoint scan over the W column lines, a transpose,
+ * the adjoint scan over the H row lines. Workspace: morlet_backward_workspace_size (zero-filled
+ * once; it is not the forward's). Errors as gauss_smooth2d. */
+morlet_status gauss_smooth2d_backward(morlet_plan_t plan, const float* gy, float* gx, void* ws, size_t ws_bytes,
+                                      void* stream);
 
 /* Per-axis parameters of an image plan: axis 0 filters along x (the rows), axis 1 along y.
  * L: window half width; n0: ASFT shift in use (0 for SFT); cos_coef[K]: a_p; kernel_relrmse:

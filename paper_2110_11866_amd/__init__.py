@@ -300,8 +300,14 @@ class Gauss2DPlan(_PlanBase):
     def autotune(self, *args, **kwargs):
         raise NotImplementedError("autotune does not take image plans")
 
-    def backward(self, *args, **kwargs):
-        raise NotImplementedError("no backward pass for image plans")
+    def backward(self, gy: torch.Tensor) -> torch.Tensor:
+        """dLoss/dx (float32, H x W) for gy = dLoss/dy (float32, H x W)."""
+        if not gy.is_cuda or gy.dtype != torch.float32 or gy.numel() != self.N or not gy.is_contiguous():
+            raise ValueError("gy must be a contiguous float32 device tensor of H x W elements")
+        w = self.workspace(gy.device, backward=True)
+        gx = torch.empty((self.H, self.W), dtype=torch.float32, device=gy.device)
+        _abi.gauss_smooth2d_backward(self.handle, gy.data_ptr(), gx.data_ptr(), w.data_ptr(), w.numel(), _stream())
+        return gx
 
 
 class ScalogramPlan(_PlanBase):

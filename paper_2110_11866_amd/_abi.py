@@ -34,6 +34,7 @@ SIGNATURES = {
     "morlet_plan_set_boundary": (ctypes.c_int, [_vp, ctypes.c_int]),
     "morlet_tree_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "gauss_smooth2d": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    "gauss_smooth2d_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "morlet_image_axis_info": (ctypes.c_int, [_vp, _i32, _P(_i64), _P(_i64), _P(_dbl), _P(_dbl)]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
     "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
@@ -250,4 +251,8 @@ MORLET_BOUNDARY_ZERO, MORLET_BOUNDARY_EDGE = 0, 1
 
 def morlet_plan_set_boundary(plan: int, boundary: int) -> None:
     check(lib().morlet_plan_set_boundary(plan, boundary))
+
+
+def gauss_smooth2d_backward(plan: int, gy_ptr: int, gx_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    check(lib().gauss_smooth2d_backward(plan, gy_ptr, gx_ptr, ws_ptr, ws_bytes, stream))
 

@@ -609,6 +609,46 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
   return MORLET_OK;
 }
 
+
+// Backward of an image plan (dLoss/dx for y = T S_y T S_x x, T the transpose, S the line
+// smoothings): gx = S_x^T T S_y^T T gy, the batched adjoint of each axis between transposes.
+// Workspace: the larger of the two axes' backward workspaces first (its header at offset 0, where
+// every launch on this workspace keeps it), then two H x W float32 buffers.
+struct ImageBwdLayout {
+  size_t axis_bytes, a_off, b_off, total;
+};
+ImageBwdLayout image_bwd_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t px = (size_t)plan->img_H * (size_t)plan->img_W * sizeof(float);
+  ImageBwdLayout m;
+  m.axis_bytes = std::max(bwd_layout(plan->axis[0]).total, bwd_layout(plan->axis[1]).total);
+  m.a_off = up(m.axis_bytes);
+  m.b_off = up(m.a_off + px);
+  m.total = m.b_off + px;
+  return m;
+}
+
+morlet_status run_image2d_backward(morlet_plan_t plan, const float* gy, float* gx, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  const int64_t H = plan->img_H, W = plan->img_W;
+  if (H == 0 || W == 0) return MORLET_OK;
+  if (!gy || !gx || !ws) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  const ImageBwdLayout m = image_bwd_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* A = reinterpret_cast<float*>(wsb + m.a_off);
+  float* B = reinterpret_cast<float*>(wsb + m.b_off);
+  void* aw = ws;
+  const size_t aw_bytes = m.axis_bytes;
+  hipError_t e = mk::launch_transpose(gy, A, H, W, s);   // W x H: the column lines' cotangents
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  morlet_status st = run_backward(plan->axis[1], nullptr, 0, A, B, nullptr, aw, aw_bytes, stream, 1, true);
+  if (st != MORLET_OK) return st;
+  e = mk::launch_transpose(B, A, W, H, s);                // H x W: the row lines' cotangents
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return run_backward(plan->axis[0], nullptr, 0, A, gx, nullptr, aw, aw_bytes, stream, 1, true);
+}
 }  // namespace
 
 extern "C" {
@@ -846,6 +886,12 @@ morlet_status gauss_smooth2d(morlet_plan_t plan, const void* x, morlet_dtype dty
                              size_t ws_bytes, void* stream) {
   if (!plan || !plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d needs an image plan");
   return run_image2d(plan, x, (int)dtype, y, ws, ws_bytes, stream);
+}
+
+morlet_status gauss_smooth2d_backward(morlet_plan_t plan, const float* gy, float* gx, void* ws, size_t ws_bytes,
+                                      void* stream) {
+  if (!plan || !plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d_backward needs an image plan");
+  return run_image2d_backward(plan, gy, gx, ws, ws_bytes, stream);
 }
 
 morlet_status morlet_image_axis_info(morlet_plan_t plan, int32_t axis, int64_t* L, int64_t* n0, double* cos_coef,
@@ -1212,6 +1258,10 @@ void morlet_destroy(morlet_plan_t plan) {
 
 morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
+  if (plan->image2d) {
+    *bytes = image_bwd_layout(plan).total;
+    return MORLET_OK;
+  }
   *bytes = plan->boundary == 1 ? std::max(edge_bwd_layout(plan).total, edge_layout(plan).total) : bwd_layout(plan).total;
   return MORLET_OK;
 }

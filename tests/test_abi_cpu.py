@@ -436,3 +436,16 @@ def test_edge_boundary_setting():
     finally:
         for x in (h, hs, hm, hd):
             _abi.morlet_destroy(x)
+
+
+def test_image_backward_workspace_keeps_the_header_first():
+    # forward and backward share a workspace: the backward's own scan workspace (with the header)
+    # comes first, and the backward size also covers the forward
+    h = _abi.morlet_plan_gauss2d(120, 90, 3.0, 5.0, 4, 0, 0)
+    try:
+        fw, bw = _abi.morlet_workspace_size(h), _abi.morlet_backward_workspace_size(h)
+        assert bw >= fw and bw >= 2 * 120 * 90 * 4
+        L = _abi.lib()
+        assert L.gauss_smooth2d_backward(h, 1 << 20, 1 << 20, 1 << 20, 100, None) == _abi.MORLET_ERR_WORKSPACE
+    finally:
+        _abi.morlet_destroy(h)

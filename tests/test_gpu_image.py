@@ -65,3 +65,32 @@ def test_image_repeat_is_bitwise():
     b = plan.forward(xt)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("H,W,sy,sx,K,mode", [(1, 1, 2.0, 2.0, 3, "sft"), (50, 300, 3.0, 10.0, 4, "asft"),
+                                              (257, 129, 8.0, 5.0, 5, "sft"), (300, 200, 6.0, 4.0, 4, "asft")])
+def test_image_backward(H, W, sy, sx, K, mode):
+    # gx = S_x^T T S_y^T T gy against the oracle's adjoint per line, and <gy, S x> = <S^T gy, x> with
+    # both sides from the GPU; a forward after the backward on the same plan (shared workspace)
+    # still matches
+    import paper_2110_11866_amd as M
+    _announce("image-backward", H, W, sy, sx, K, mode)
+    rng = np.random.default_rng(H + W)
+    img = rng.standard_normal((H, W)).astype(np.float32)
+    gy = rng.standard_normal((H, W)).astype(np.float32)
+    xt, gt = torch.from_numpy(img).cuda(), torch.from_numpy(gy).cuda()
+    plan = M.Gauss2DPlan(H, W, sy, sx, K, mode=mode)
+    y0 = plan.forward(xt).cpu().numpy()
+    gx = plan.backward(gt).cpu().numpy()
+    y1 = plan.forward(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    ix, iy = plan.axis_info(0), plan.axis_info(1)
+    px = O.plan_gauss(sx, K, ix["L"], mode=mode, n0=ix["n0"] if mode == "asft" else None)
+    py = O.plan_gauss(sy, K, iy["L"], mode=mode, n0=iy["n0"] if mode == "asft" else None)
+    g64 = gy.astype(np.float64)
+    cols = np.stack([O.adjoint(g64[:, c], py) for c in range(W)], axis=1)
+    want = np.stack([O.adjoint(cols[r], px) for r in range(H)])
+    assert rel_l2(gx, want) <= 1e-5, rel_l2(gx, want)
+    lhs, rhs = float(np.sum(g64 * y0)), float(np.sum(img.astype(np.float64) * gx))
+    assert abs(lhs - rhs) <= 2e-5 * (abs(lhs) + np.sqrt(H * W)), (lhs, rhs)
+    assert np.array_equal(y0, y1)
