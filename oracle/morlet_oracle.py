@@ -596,6 +596,10 @@ def forward_direct(x: np.ndarray, sigma: float, xi: float | None, L: int, deriv:
 def _taps_and_shift(plan: Plan) -> tuple[np.ndarray, int]:
     if plan.mode == "asft":
         return asft_kernel(plan), plan.n0
+    if plan.kind == "mult":
+        return kterm_multiply(plan), 0
+    if plan.kind in ("gd1", "gd2"):
+        return kterm_gauss_deriv(plan), 0
     base = kterm_morlet(plan) if plan.kind == "morlet" else kterm_gauss(plan)
     return base, 0
 

@@ -333,14 +333,20 @@ def test_asft_shift_and_phase_recover_the_wavelet():
 
 
 # ---------------------------------------------------------------- differentiation
-@pytest.mark.parametrize("kind", ["morlet", "gauss"])
+@pytest.mark.parametrize("kind", ["morlet", "gauss", "mult", "gd1"])
 @pytest.mark.parametrize("mode", ["sft", "asft"])
 def test_adjoint_dot_product(kind, mode):
+    # Re <g, A x> = <x, A^T g>: the adjoint (from the taps) against the forward (from the
+    # kernel-integral recurrences)
     rng = np.random.default_rng(4)
     N = 150
-    pl = O.plan_morlet(6.0, 1.0, 4, 24, mode=mode) if kind == "morlet" else O.plan_gauss(6.0, 4, 24, mode=mode)
+    n0 = 2 if mode == "asft" else None
+    pl = {"morlet": lambda: O.plan_morlet(6.0, 1.0, 4, 24, mode=mode, n0=n0),
+          "gauss": lambda: O.plan_gauss(6.0, 4, 24, mode=mode, n0=n0),
+          "mult": lambda: O.plan_multiply(6.0, 1.0, 3, 24, mode=mode, n0=n0),
+          "gd1": lambda: O.plan_gauss_deriv(6.0, 4, 24, 1, mode=mode, n0=n0)}[kind]()
     x = rng.standard_normal(N)
-    g = rng.standard_normal(N) + (1j * rng.standard_normal(N) if kind == "morlet" else 0)
+    g = rng.standard_normal(N) + (1j * rng.standard_normal(N) if kind in ("morlet", "mult") else 0)
     lhs = np.sum((np.conj(g) * O.forward(x, pl)).real)
     rhs = np.dot(x, O.adjoint(g, pl))
     assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
