@@ -132,7 +132,9 @@ morlet_status morlet_plan_gauss_deriv(morlet_plan_t* out, int64_t N, double sigm
  * exactly) and the accumulation precision; morlet_plan_set_tile, _set_schedule and
  * _autotune apply. morlet_plan_info reports a_p as cos_coef (sin_coef zero), P_S = 0 and the
  * error of psi_hat_M against psi on [-L, L] as kernel_relrmse. L = 0 takes the error-optimal
- * window of the Gaussian fit. Forward only (backward calls return MORLET_ERR_UNSUPPORTED).
+ * window of the Gaussian fit. morlet_backward gives dLoss/dx (gparams must be null: parameter
+ * gradients return MORLET_ERR_UNSUPPORTED): the transposes of the remodulation and the
+ * demodulation around the three rows' adjoint scan; workspace: morlet_backward_workspace_size.
  * Errors: MORLET_ERR_INVALID_ARG (N < 0 or N > 2^38, sigma or xi not finite and > 0,
  * P_M < 0 or P_M + 1 > MORLET_MAX_TERMS, 0 < L < P_M), MORLET_ERR_ALLOC, MORLET_ERR_HIP. */
 morlet_status morlet_plan_multiply(morlet_plan_t* out, int64_t N, double sigma, double xi, int32_t P_M,

@@ -190,7 +190,7 @@ class MultiplyPlan(MorletPlan):
     """Morlet transform by the multiplication method (Sec. III-B): the Gaussian envelope
     fitted with the cosines of orders 0..P_M (K = P_M + 1 terms) times the carrier, evaluated
     as three Gaussian smoothings (demodulated real and imaginary parts, and the signal) in one
-    scan launch between a demodulation and a remodulation kernel. Forward only."""
+    scan launch between a demodulation and a remodulation kernel. The backward gives dLoss/dx."""
 
     kind = "morlet"
 
@@ -205,8 +205,14 @@ class MultiplyPlan(MorletPlan):
     def direct(self, *args, **kwargs):
         raise NotImplementedError("the direct-convolution baseline needs a direct-method plan")
 
-    def backward(self, *args, **kwargs):
-        raise NotImplementedError("no backward pass for multiplication-method plans")
+    def backward(self, x: torch.Tensor | None, gW: torch.Tensor, want_params: bool = False):
+        """(dLoss/dx float32 [N], None) for the cotangent gW (complex64 [N]); parameter
+        gradients are not built for the multiplication method."""
+        if want_params:
+            raise NotImplementedError("parameter gradients are not built for the multiplication method")
+        if gW.dtype != torch.complex64 or gW.numel() != self.N:
+            raise ValueError("gW must be complex64 of N elements")
+        return _bwd_common(self, _abi.morlet_backward, None, gW, False, 2)
 
 
 class GaussPlan(_PlanBase):
@@ -261,7 +267,7 @@ class GaussDerivPlan(GaussPlan):
 class Gauss2DPlan(_PlanBase):
     """Separable 2-D Gaussian smoothing of an H x W image (row-major, x along a row): the
     lines are filtered independently (Sec. IV), rows then columns, each axis with K cosine
-    terms on its own window (0: error-optimal). Forward only."""
+    terms on its own window (0: error-optimal). The backward gives dLoss/dx."""
 
     kind = "image"
 

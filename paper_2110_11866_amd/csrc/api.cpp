@@ -12,6 +12,7 @@
 #include "../../include/morlet.h"
 #include "boundary.h"
 #include "launch.h"
+#include "multiply.h"
 #include "plan_internal.h"
 
 namespace {
@@ -557,10 +558,58 @@ morlet_status run_backward_edge(morlet_plan_t plan, const void* x, int dtype, co
   return MORLET_OK;
 }
 
+// Backward workspace of a multiplication-method plan: the three-row plan's backward workspace
+// (header first), then the rows' cotangents and their adjoints (3N float32 each).
+struct MultBwdLayout {
+  size_t g_off, gu_off, total;
+};
+MultBwdLayout mult_bwd_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  MultBwdLayout m;
+  m.g_off = up(bwd_layout(plan).total);
+  m.gu_off = up(m.g_off + 3 * (size_t)plan->mult_N * sizeof(float));
+  m.total = m.gu_off + 3 * (size_t)plan->mult_N * sizeof(float);
+  return m;
+}
+
+// dLoss/dx of the multiplication method: the transpose of the remodulation (three row
+// cotangents), the adjoint scan of the three Gaussian rows (one scale, so each row's adjoint is
+// written straight to its place), the transpose of the demodulation.
+morlet_status run_multiply_backward(morlet_plan_t plan, const void* gW, float* gx, void* ws, size_t ws_bytes,
+                                    void* stream) {
+  const int64_t N = plan->mult_N;
+  if (N == 0) return MORLET_OK;
+  if (!gW || !gx || !ws) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  if (plan->ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  const MultBwdLayout m = mult_bwd_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* g3 = reinterpret_cast<float*>(wsb + m.g_off);
+  float* gu3 = reinterpret_cast<float*>(wsb + m.gu_off);
+  hipError_t e = mk::launch_mm_remodulate_t(static_cast<const float2*>(gW), g3, N, plan->xi, plan->mult_ce,
+                                            plan->mult_ce * plan->mult_kappa, s);
+  mk::ScanLaunch a;
+  const morlet_status st = make_launch(plan, a, ws, mk::kVarAdjoint, 0, 0);
+  if (st != MORLET_OK) return st;
+  a.x = g3;
+  a.dtype = 0;
+  a.out = gu3;
+  if (e == hipSuccess) e = mk::launch_scan(a, mk::kVarAdjoint, 0, s);
+  if (e == hipSuccess) e = mk::launch_mm_demodulate_t(gu3, gx, N, plan->xi, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
+}
+
 morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const void* g, float* gx, double* gparams,
                            void* ws, size_t ws_bytes, void* stream, int want_kind, bool want_batched) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
-  if (plan->multiply) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for multiplication-method plans");
+  if (plan->multiply) {
+    if (want_kind != 0 || want_batched) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
+    if (gparams) return fail(MORLET_ERR_UNSUPPORTED, "parameter gradients are not built for the multiplication method");
+    return run_multiply_backward(plan, g, gx, ws, ws_bytes, stream);
+  }
   if (plan->image2d) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for image plans");
   if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
   if (plan->deriv != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for differential smoothing plans");
@@ -1260,6 +1309,10 @@ morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) 
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
   if (plan->image2d) {
     *bytes = image_bwd_layout(plan).total;
+    return MORLET_OK;
+  }
+  if (plan->multiply) {
+    *bytes = std::max(mult_bwd_layout(plan).total, mult_layout(plan).total);
     return MORLET_OK;
   }
   *bytes = plan->boundary == 1 ? std::max(edge_bwd_layout(plan).total, edge_layout(plan).total) : bwd_layout(plan).total;

@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "launch.h"
+#include "multiply.h"
 #include "scan_common.h"
 
 namespace mk {
@@ -45,6 +46,31 @@ __global__ __launch_bounds__(kMmThreads) void mm_remodulate_kernel(const float* 
   }
 }
 
+// Transposes for the backward (real loss, gW = dLoss/dRe W + i dLoss/dIm W):
+//   g[n] = ce (gWr cos + gWi sin), g[N + n] = ce (gWi cos - gWr sin), g[2N + n] = -ce kappa gWr
+__global__ __launch_bounds__(kMmThreads) void mm_remodulate_t_kernel(const float2* gW, float* g, int64_t N, double xi,
+                                                                       double ce, double cek) {
+  const int64_t stride = (int64_t)gridDim.x * kMmThreads;
+  for (int64_t n = (int64_t)blockIdx.x * kMmThreads + threadIdx.x; n < N; n += stride) {
+    double s, c;
+    sincos(xi * (double)n, &s, &c);
+    const double gr = gW[n].x, gi = gW[n].y;
+    g[n] = (float)(ce * (gr * c + gi * s));
+    g[N + n] = (float)(ce * (gi * c - gr * s));
+    g[2 * N + n] = (float)(-cek * gr);
+  }
+}
+
+//   gx[m] = cos(xi m) gu[m] - sin(xi m) gu[N + m] + gu[2N + m]
+__global__ __launch_bounds__(kMmThreads) void mm_demodulate_t_kernel(const float* gu, float* gx, int64_t N, double xi) {
+  const int64_t stride = (int64_t)gridDim.x * kMmThreads;
+  for (int64_t m = (int64_t)blockIdx.x * kMmThreads + threadIdx.x; m < N; m += stride) {
+    double s, c;
+    sincos(xi * (double)m, &s, &c);
+    gx[m] = (float)(c * (double)gu[m] - s * (double)gu[N + m] + (double)gu[2 * N + m]);
+  }
+}
+
 int mm_grid(int64_t N) {
   const int64_t blocks = (N + kMmThreads - 1) / kMmThreads;
   return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 8192));
@@ -62,6 +88,19 @@ hipError_t launch_mm_remodulate(const float* g, float2* W, int64_t N, double xi,
                                 hipStream_t s) {
   if (N <= 0) return hipSuccess;
   hipLaunchKernelGGL(mm_remodulate_kernel, dim3(mm_grid(N)), dim3(kMmThreads), 0, s, g, W, N, xi, ce, cek);
+  return hipGetLastError();
+}
+
+hipError_t launch_mm_remodulate_t(const float2* gW, float* g, int64_t N, double xi, double ce, double cek,
+                                  hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mm_remodulate_t_kernel, dim3(mm_grid(N)), dim3(kMmThreads), 0, s, gW, g, N, xi, ce, cek);
+  return hipGetLastError();
+}
+
+hipError_t launch_mm_demodulate_t(const float* gu, float* gx, int64_t N, double xi, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mm_demodulate_t_kernel, dim3(mm_grid(N)), dim3(kMmThreads), 0, s, gu, gx, N, xi);
   return hipGetLastError();
 }
 

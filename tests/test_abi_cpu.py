@@ -308,7 +308,10 @@ def test_multiply_plan_errors_and_workspace():
     try:
         assert _abi.morlet_workspace_size(hp) >= 6 * 5000 * 4
         fake = 1 << 20
-        assert L.morlet_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_backward(hp, fake, 0, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_backward(hp, None, 0, fake, fake, None, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
+        assert L.gauss_smooth_backward(hp, None, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert _abi.morlet_backward_workspace_size(hp) >= max(_abi.morlet_workspace_size(hp), 6 * 5000 * 4)
         assert L.gauss_smooth(hp, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
         assert L.morlet_direct_forward(hp, fake, 0, fake, 0, None) == _abi.MORLET_ERR_INVALID_ARG
         assert L.morlet_forward(hp, fake, 0, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE

@@ -95,3 +95,30 @@ def test_multiply_close_to_direct_method_at_xi0_6():
     exact = O.forward_direct(x.astype(np.float64), sigma, xi, 5 * L)
     em, ed = rel_l2(wm, exact), rel_l2(wd, exact)
     assert 0.3 < em / ed < 3.0, (em, ed)
+
+
+@pytest.mark.parametrize("N,sigma,xi0,PM,mode", [(1, 8.0, 6.0, 2, "sft"), (3000, 60.0, 6.0, 3, "asft"),
+                                                 (20000, 100.0, 2.0, 4, "sft"), (50000, 300.0, 6.0, 2, "asft")])
+def test_multiply_backward(N, sigma, xi0, PM, mode):
+    # dLoss/dx against the oracle's adjoint (transpose of the multiplication-method taps) and the
+    # adjoint identity with both sides from the GPU; a forward after the backward still matches
+    import paper_2110_11866_amd as M
+    _announce("multiply-backward", N, sigma, xi0, PM, mode)
+    rng = np.random.default_rng(N + PM)
+    x = rng.standard_normal(N).astype(np.float32)
+    g = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+    xt, gt = torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda()
+    plan = M.MultiplyPlan(N, sigma, xi0 / sigma, PM, mode=mode)
+    W0 = plan.forward(xt).cpu().numpy()
+    gx, gp = plan.backward(None, gt)
+    W1 = plan.forward(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    assert gp is None
+    info = plan.info()
+    p = O.plan_multiply(sigma, xi0 / sigma, PM, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None)
+    want = O.adjoint(g.astype(np.complex128), p)
+    assert rel_l2(gx.cpu().numpy(), want) <= 1e-5, rel_l2(gx.cpu().numpy(), want)
+    lhs = float(np.sum((np.conj(g.astype(np.complex128)) * W0.astype(np.complex128)).real))
+    rhs = float(np.dot(x.astype(np.float64), gx.cpu().numpy().astype(np.float64)))
+    assert abs(lhs - rhs) <= 2e-5 * (abs(lhs) + np.sqrt(N)), (lhs, rhs)
+    assert np.array_equal(W0, W1)
