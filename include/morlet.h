@@ -101,9 +101,11 @@ morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int
  * gamma = 1/(2 sigma^2), b and d by MMSE on [-L, L] (eq. mmse). Run with gauss_smooth
  * (float32 output). Same argument rules as morlet_plan_gauss, with K <= L for order 1;
  * L = 0 takes the window of the Gaussian fit with the same top order (Table 1 uses one
- * beta for G, G_D and G_DD). Forward only (the backward calls return
- * MORLET_ERR_UNSUPPORTED). morlet_plan_info reports b as sin_coef (order 1) or d as
- * cos_coef (order 2); P_S is 1 or 0.
+ * beta for G, G_D and G_DD). gauss_smooth_backward gives dLoss/dx (gparams must be null,
+ * zero extension only, else MORLET_ERR_UNSUPPORTED): the taps are real, so the transpose is
+ * R A R with R the time reversal, i.e. the plan's own forward of the reversed cotangent,
+ * reversed (workspace: morlet_backward_workspace_size). morlet_plan_info reports b as sin_coef
+ * (order 1) or d as cos_coef (order 2); P_S is 1 or 0.
  * After morlet_plan_set(..., MORLET_SCAN_ASFT, n0, ...) the plan is refitted for the
  * attenuated transform (eqs. siftGauss, gddAsft): the K terms become orders 0..K-1 (P_S = 0)
  * with both components, a_p, b_p, d_p the fits of G (orders 0..K-1), G_D (sines 1..K-1) and

@@ -247,7 +247,7 @@ class GaussPlan(_PlanBase):
 
 
 class GaussDerivPlan(GaussPlan):
-    """The Gaussian's differentials applied to the signal (Sec. II), forward only.
+    """The Gaussian's differentials applied to the signal (Sec. II); the backward gives dLoss/dx.
     SFT: order 1 gives x_GD (sine components 1..K), order 2 gives x_GDD (cosine components
     0..K-1). ASFT (eq. gddAsft): orders 0..K-1 with both components, shifted by n0."""
 
@@ -260,8 +260,14 @@ class GaussDerivPlan(GaussPlan):
         if mode != "sft" or n0 or accum != "f32":
             self.set(mode, n0, accum)
 
-    def backward(self, *args, **kwargs):
-        raise NotImplementedError("no backward pass for differential smoothing plans")
+    def backward(self, x: torch.Tensor | None, gy: torch.Tensor, want_params: bool = False):
+        """(dLoss/dx float32 [N], None) for gy = dLoss/dy (float32 [N]): the plan's forward of the
+        reversed cotangent, reversed; parameter gradients are not built for differentials."""
+        if want_params:
+            raise NotImplementedError("parameter gradients are not built for differential plans")
+        if gy.dtype != torch.float32 or gy.numel() != self.N:
+            raise ValueError("gy must be float32 of N elements")
+        return _bwd_common(self, _abi.gauss_smooth_backward, None, gy, False, 2)
 
 
 class Gauss2DPlan(_PlanBase):

@@ -602,6 +602,50 @@ morlet_status run_multiply_backward(morlet_plan_t plan, const void* gW, float* g
   return MORLET_OK;
 }
 
+// Backward of a differential plan (dLoss/dx): its taps are real, so with zero extension the
+// transpose of y[n] = sum_k h[k] x[n - n0 - k] is R A R (R the time reversal):
+// gx = R (forward of the same plan applied to R gy). Workspace: the forward's tile states, then
+// the reversed cotangent and the forward of it (N float32 each).
+int64_t deriv_tiles(morlet_plan_t plan) {
+  return plan->batched ? plan->ntiles : tiles_for(plan->N + plan->L - plan->n0, plan->R);
+}
+struct DerivBwdLayout {
+  size_t g_off, y_off, total;
+};
+DerivBwdLayout deriv_bwd_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  DerivBwdLayout m;
+  m.g_off = up(mk::workspace_bytes(plan->K, deriv_tiles(plan)));
+  m.y_off = up(m.g_off + (size_t)plan->N * sizeof(float));
+  m.total = m.y_off + (size_t)plan->N * sizeof(float);
+  return m;
+}
+
+morlet_status run_deriv_backward(morlet_plan_t plan, const float* gy, float* gx, void* ws, size_t ws_bytes,
+                                 void* stream) {
+  if (plan->N == 0) return MORLET_OK;
+  if (!gy || !gx || !ws) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  const DerivBwdLayout m = deriv_bwd_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  if (deriv_tiles(plan) > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* gr = reinterpret_cast<float*>(wsb + m.g_off);
+  float* yr = reinterpret_cast<float*>(wsb + m.y_off);
+  hipError_t e = mk::launch_reverse(gy, gr, plan->N, s);
+  mk::ScanLaunch a;
+  const morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0, 0);
+  if (st != MORLET_OK) return st;
+  a.x = gr;
+  a.dtype = 0;
+  a.out = yr;
+  if (e == hipSuccess) e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e == hipSuccess) e = mk::launch_reverse(yr, gx, plan->N, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
+}
+
 morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const void* g, float* gx, double* gparams,
                            void* ws, size_t ws_bytes, void* stream, int want_kind, bool want_batched) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
@@ -612,7 +656,11 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
   }
   if (plan->image2d) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for image plans");
   if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
-  if (plan->deriv != 0) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for differential smoothing plans");
+  if (plan->deriv != 0) {
+    if (gparams) return fail(MORLET_ERR_UNSUPPORTED, "parameter gradients are not built for differential plans");
+    if (plan->boundary != 0) return fail(MORLET_ERR_UNSUPPORTED, "differential backward with edge extension is not built");
+    return run_deriv_backward(plan, static_cast<const float*>(g), gx, ws, ws_bytes, stream);
+  }
   if (want_batched != plan->batched)
     return fail(MORLET_ERR_INVALID_ARG, want_batched ? "needs a scalogram plan" : "needs a single-signal plan");
   if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
@@ -1313,6 +1361,10 @@ morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) 
   }
   if (plan->multiply) {
     *bytes = std::max(mult_bwd_layout(plan).total, mult_layout(plan).total);
+    return MORLET_OK;
+  }
+  if (plan->deriv != 0 && plan->boundary == 0) {
+    *bytes = deriv_bwd_layout(plan).total;
     return MORLET_OK;
   }
   *bytes = plan->boundary == 1 ? std::max(edge_bwd_layout(plan).total, edge_layout(plan).total) : bwd_layout(plan).total;

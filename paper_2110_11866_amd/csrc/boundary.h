@@ -17,4 +17,8 @@ hipError_t launch_pad_center(const void* g, int esize, int64_t N, int64_t P, voi
 // gx[N - 1] (the transpose of the edge extension), summed in a fixed order.
 hipError_t launch_edge_fold(const float* gxe, int64_t N, int64_t P, float* gx, hipStream_t s);
 
+// out[n] = in[N - 1 - n] (float32): the time reversal R, for the transpose R A R of a real-tap
+// "same" convolution A.
+hipError_t launch_reverse(const float* in, float* out, int64_t N, hipStream_t s);
+
 }  // namespace mk

@@ -66,7 +66,19 @@ __global__ __launch_bounds__(kEdThreads) void edge_fold_kernel(const float* gxe,
   }
 }
 
+__global__ __launch_bounds__(kEdThreads) void reverse_kernel(const float* in, float* out, int64_t N) {
+  const int64_t stride = (int64_t)gridDim.x * kEdThreads;
+  for (int64_t n = (int64_t)blockIdx.x * kEdThreads + threadIdx.x; n < N; n += stride) out[n] = in[N - 1 - n];
+}
+
 }  // namespace
+
+hipError_t launch_reverse(const float* in, float* out, int64_t N, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((N + kEdThreads - 1) / kEdThreads, 8192));
+  hipLaunchKernelGGL(reverse_kernel, dim3((unsigned)blocks), dim3(kEdThreads), 0, s, in, out, N);
+  return hipGetLastError();
+}
 
 hipError_t launch_pad_center(const void* g, int esize, int64_t N, int64_t P, void* ge, hipStream_t s) {
   const int64_t Ne = N + 2 * P;

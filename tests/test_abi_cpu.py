@@ -92,8 +92,14 @@ def test_differential_plan_errors():
         assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 6, 0) == _abi.MORLET_ERR_INVALID_ARG   # n0 > L
         assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_SFT, 0, 1) == _abi.MORLET_OK
         fake = 1 << 20
-        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        # dLoss/dx only: parameter gradients and edge extension are refused, a short workspace too
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
         assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 0, 0) == _abi.MORLET_OK
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
+        assert _abi.morlet_backward_workspace_size(hp) >= 2 * 100 * 4
+        assert L.morlet_plan_set_boundary(hp, 1) == _abi.MORLET_OK
         assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
     finally:
         _abi.morlet_destroy(hp)

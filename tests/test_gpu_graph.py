@@ -145,3 +145,25 @@ def test_graph_newer_forward_paths():
     pi = M.Gauss2DPlan(H, W, 5.0, 7.0, 4, mode="asft")
     wi, oi = pi.workspace(xt.device), torch.empty(H, W, dtype=torch.float32, device=xt.device)
     _replays(lambda: (pi.forward(xt, out=oi, ws=wi),), xt, fresh)
+
+
+def test_graph_newer_backward_paths():
+    # dLoss/dx of the multiplication method (transposed carriers around the three-row adjoint),
+    # of the 2-D smoothing (two transposes, two adjoint scans) and of a differential (reversal,
+    # forward scan, reversal) replay bitwise like their eager calls, the cotangent changed in place
+    import paper_2110_11866_amd as M
+    _announce("graph-newer-backward")
+    N = 40000
+    rnd = lambda seed, n: torch.from_numpy(np.random.default_rng(seed).standard_normal(n).astype(np.float32)).cuda()
+    pm = M.MultiplyPlan(N, 50.0, 6 / 50.0, 3, mode="asft")
+    gbuf = rnd(8, 2 * N)
+    gW = gbuf.view(torch.complex64)
+    _replays(lambda: (pm.backward(None, gW)[0],), gbuf, lambda k: rnd(400 + k, 2 * N))
+    H, W = 200, 200
+    pi = M.Gauss2DPlan(H, W, 5.0, 7.0, 4, mode="asft")
+    gy = rnd(9, H * W)
+    _replays(lambda: (pi.backward(gy.view(H, W)),), gy, lambda k: rnd(500 + k, H * W))
+    for mode in ("sft", "asft"):
+        pd = M.GaussDerivPlan(N, 40.0, 5, 0, order=2, mode=mode)
+        gd = rnd(10, N)
+        _replays(lambda: (pd.backward(None, gd)[0],), gd, lambda k: rnd(600 + k, N))
