@@ -309,7 +309,8 @@ morlet_status morlet_backward(morlet_plan_t plan, const void* x, morlet_dtype dt
                               double* gparams, void* ws, size_t ws_bytes, void* stream);
 
 /* Gaussian smoothing backward: gy float32 [N] is dLoss/dy; gparams[0] = dLoss/dsigma,
- * gparams[1] = 0. */
+ * gparams[1] = 0. On a differential plan (morlet_plan_gauss_deriv) only dLoss/dx is built:
+ * gparams must be NULL and the extension zero (else MORLET_ERR_UNSUPPORTED); x is unused. */
 morlet_status gauss_smooth_backward(morlet_plan_t plan, const void* x, morlet_dtype dtype, const float* gy,
                                     float* gx, double* gparams, void* ws, size_t ws_bytes, void* stream);
 
