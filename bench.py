@@ -51,7 +51,7 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", type=int, default=16, choices=[4, 8, 16, 32], help="samples per thread")
     ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "rows"],
-                    help="batched launch schedule (scalogram workload)")
+                    help="batched launch schedule (scalogram and image2d workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of this many MB (counter calibration for HBM bytes)")
     return ap.parse_args()
@@ -303,7 +303,7 @@ def bench_image2d(args, torch, M):
     dev = torch.device("cuda:0")
     x = torch.randn(H, W, generator=torch.Generator().manual_seed(17)).to(dev)
     plan = M.Gauss2DPlan(H, W, sigma, sigma, K, mode=args.mode)
-    plan.set_tile(args.tile)
+    plan.set_tile(args.tile).set_schedule(args.schedule)
     out = torch.empty(H, W, dtype=torch.float32, device=dev)
     ws = plan.workspace(dev)
     ms_step, kern_ms = _timed(torch, lambda: plan.forward(x, out=out, ws=ws), args.steps, args.warmup)
@@ -318,7 +318,7 @@ def bench_image2d(args, torch, M):
         "dtype": "f32",
         "config": {"workload": f"image2d: one 4096 x 4096 float32 N(0,1) image, sigma={sigma:g} on both axes, "
                                f"K={K}, windows L={ix['L']} (error-optimal), {args.mode}, float32 out",
-                   "tile_R": args.tile},
+                   "tile_R": args.tile, "schedule": args.schedule},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "scope": "whole path (two scans, two transposes) against 8 B per pixel"},
