@@ -102,9 +102,10 @@ morlet_status morlet_plan_gauss(morlet_plan_t* out, int64_t N, double sigma, int
  * (float32 output). Same argument rules as morlet_plan_gauss, with K <= L for order 1;
  * L = 0 takes the window of the Gaussian fit with the same top order (Table 1 uses one
  * beta for G, G_D and G_DD). gauss_smooth_backward gives dLoss/dx (gparams must be null,
- * zero extension only, else MORLET_ERR_UNSUPPORTED): the taps are real, so the transpose is
- * R A R with R the time reversal, i.e. the plan's own forward of the reversed cotangent,
- * reversed (workspace: morlet_backward_workspace_size). morlet_plan_info reports b as sin_coef
+ * else MORLET_ERR_UNSUPPORTED): the taps are real, so the transpose is R A R with R the time
+ * reversal, i.e. the plan's own forward of the reversed cotangent, reversed; with edge
+ * extension the same over the padded row, folded onto the ends (workspace:
+ * morlet_backward_workspace_size). morlet_plan_info reports b as sin_coef
  * (order 1) or d as cos_coef (order 2); P_S is 1 or 0.
  * After morlet_plan_set(..., MORLET_SCAN_ASFT, n0, ...) the plan is refitted for the
  * attenuated transform (eqs. siftGauss, gddAsft): the K terms become orders 0..K-1 (P_S = 0)
@@ -310,7 +311,7 @@ morlet_status morlet_backward(morlet_plan_t plan, const void* x, morlet_dtype dt
 
 /* Gaussian smoothing backward: gy float32 [N] is dLoss/dy; gparams[0] = dLoss/dsigma,
  * gparams[1] = 0. On a differential plan (morlet_plan_gauss_deriv) only dLoss/dx is built:
- * gparams must be NULL and the extension zero (else MORLET_ERR_UNSUPPORTED); x is unused. */
+ * gparams must be NULL (else MORLET_ERR_UNSUPPORTED); x is unused. */
 morlet_status gauss_smooth_backward(morlet_plan_t plan, const void* x, morlet_dtype dtype, const float* gy,
                                     float* gx, double* gparams, void* ws, size_t ws_bytes, void* stream);
 

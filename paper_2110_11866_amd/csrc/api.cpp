@@ -601,23 +601,26 @@ morlet_status run_multiply_backward(morlet_plan_t plan, const void* gW, float* g
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return MORLET_OK;
 }
-
-// Backward of a differential plan (dLoss/dx): its taps are real, so with zero extension the
-// transpose of y[n] = sum_k h[k] x[n - n0 - k] is R A R (R the time reversal):
-// gx = R (forward of the same plan applied to R gy). Workspace: the forward's tile states, then
-// the reversed cotangent and the forward of it (N float32 each).
-int64_t deriv_tiles(morlet_plan_t plan) {
-  return plan->batched ? plan->ntiles : tiles_for(plan->N + plan->L - plan->n0, plan->R);
-}
+// Backward of a differential plan (dLoss/dx). The taps are real and the map of the zero-extended
+// signal is an N x N Toeplitz matrix A (y[n] = sum_k h[k] x[n - n0 - k]); every square
+// Toeplitz matrix is persymmetric, so A^T = R A R with R the time reversal: gx = R A R gy, the
+// plan's own forward of the reversed cotangent, reversed. With edge extension the forward is
+// C A_e E (E the extension to Ne = N + 4L samples, A_e the Toeplitz map of the padded row, C the
+// central crop), so gx = E^T R A_e R C^T gy: the cotangent zero-padded and reversed, the forward
+// over the padded row, reversed, and the padded ends folded onto x[0] and x[N-1].
+// Workspace: the forward's tile states, then two float32 buffers of the row's length.
 struct DerivBwdLayout {
-  size_t g_off, y_off, total;
+  int64_t Ne, ntiles;
+  size_t a_off, b_off, total;
 };
 DerivBwdLayout deriv_bwd_layout(morlet_plan_t plan) {
   auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
   DerivBwdLayout m;
-  m.g_off = up(mk::workspace_bytes(plan->K, deriv_tiles(plan)));
-  m.y_off = up(m.g_off + (size_t)plan->N * sizeof(float));
-  m.total = m.y_off + (size_t)plan->N * sizeof(float);
+  m.Ne = plan->boundary == 1 ? plan->N + 4 * plan->L : plan->N;
+  m.ntiles = tiles_for(m.Ne + plan->L - plan->n0, plan->R);
+  m.a_off = up(mk::workspace_bytes(plan->K, m.ntiles));
+  m.b_off = up(m.a_off + (size_t)m.Ne * sizeof(float));
+  m.total = m.b_off + (size_t)m.Ne * sizeof(float);
   return m;
 }
 
@@ -628,20 +631,34 @@ morlet_status run_deriv_backward(morlet_plan_t plan, const float* gy, float* gx,
   const DerivBwdLayout m = deriv_bwd_layout(plan);
   if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
   if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
-  if (deriv_tiles(plan) > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  if (m.ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
   hipStream_t s = static_cast<hipStream_t>(stream);
   unsigned char* wsb = static_cast<unsigned char*>(ws);
-  float* gr = reinterpret_cast<float*>(wsb + m.g_off);
-  float* yr = reinterpret_cast<float*>(wsb + m.y_off);
-  hipError_t e = mk::launch_reverse(gy, gr, plan->N, s);
+  float* A = reinterpret_cast<float*>(wsb + m.a_off);
+  float* B = reinterpret_cast<float*>(wsb + m.b_off);
+  const bool edge = plan->boundary == 1;
+  const int64_t P = 2 * plan->L;
+  hipError_t e = hipSuccess;
+  if (edge) {
+    e = mk::launch_pad_center(gy, 4, plan->N, P, A, s);   // C^T gy
+    if (e == hipSuccess) e = mk::launch_reverse(A, B, m.Ne, s);
+  } else {
+    e = mk::launch_reverse(gy, B, m.Ne, s);
+  }
   mk::ScanLaunch a;
   const morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0, 0);
   if (st != MORLET_OK) return st;
-  a.x = gr;
+  if (edge) pad_launch(plan, a, m.Ne, mk::kVarForward, 0, 0);
+  a.x = B;
   a.dtype = 0;
-  a.out = yr;
+  a.out = A;
   if (e == hipSuccess) e = mk::launch_scan(a, mk::kVarForward, 0, s);
-  if (e == hipSuccess) e = mk::launch_reverse(yr, gx, plan->N, s);
+  if (edge) {
+    if (e == hipSuccess) e = mk::launch_reverse(A, B, m.Ne, s);
+    if (e == hipSuccess) e = mk::launch_edge_fold(B, plan->N, P, gx, s);   // E^T
+  } else if (e == hipSuccess) {
+    e = mk::launch_reverse(A, gx, m.Ne, s);
+  }
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return MORLET_OK;
 }
@@ -658,7 +675,6 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
   if (plan->kind != want_kind) return fail(MORLET_ERR_INVALID_ARG, "plan kind does not match the call");
   if (plan->deriv != 0) {
     if (gparams) return fail(MORLET_ERR_UNSUPPORTED, "parameter gradients are not built for differential plans");
-    if (plan->boundary != 0) return fail(MORLET_ERR_UNSUPPORTED, "differential backward with edge extension is not built");
     return run_deriv_backward(plan, static_cast<const float*>(g), gx, ws, ws_bytes, stream);
   }
   if (want_batched != plan->batched)
@@ -1363,7 +1379,7 @@ morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) 
     *bytes = std::max(mult_bwd_layout(plan).total, mult_layout(plan).total);
     return MORLET_OK;
   }
-  if (plan->deriv != 0 && plan->boundary == 0) {
+  if (plan->deriv != 0) {
     *bytes = deriv_bwd_layout(plan).total;
     return MORLET_OK;
   }

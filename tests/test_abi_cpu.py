@@ -92,15 +92,19 @@ def test_differential_plan_errors():
         assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 6, 0) == _abi.MORLET_ERR_INVALID_ARG   # n0 > L
         assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_SFT, 0, 1) == _abi.MORLET_OK
         fake = 1 << 20
-        # dLoss/dx only: parameter gradients and edge extension are refused, a short workspace too
+        # dLoss/dx only: parameter gradients are refused, a short workspace too
         assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
         assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
         assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 0, 0) == _abi.MORLET_OK
         assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
         assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
-        assert _abi.morlet_backward_workspace_size(hp) >= 2 * 100 * 4
+        s0 = _abi.morlet_backward_workspace_size(hp)
+        assert s0 >= 2 * 100 * 4
         assert L.morlet_plan_set_boundary(hp, 1) == _abi.MORLET_OK
-        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        # edge extension: two buffers of the padded row (N + 4L float32 each) on top of the tile states
+        assert _abi.morlet_backward_workspace_size(hp) >= s0 + 4 * 5 * 4
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, None, fake, s0, None) == _abi.MORLET_ERR_WORKSPACE
+        assert L.gauss_smooth_backward(hp, fake, 0, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
     finally:
         _abi.morlet_destroy(hp)
 

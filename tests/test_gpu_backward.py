@@ -308,3 +308,32 @@ def test_differential_backward(N, sigma, K, L, mode, n0, tile, accum, order):
     assert abs(lhs - rhs) <= 2e-5 * (np.linalg.norm(g) * np.linalg.norm(y) + 1e-30), (lhs, rhs)
     with pytest.raises(NotImplementedError):
         plan.backward(None, gt, want_params=True)
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("N,sigma,K,L", [(5, 6.0, 3, 20), (37, 8.0, 4, 40), (20000, 100.0, 5, 400)])
+def test_differential_backward_with_edge_extension(N, sigma, K, L, order, mode):
+    # E^T (R A_e R) C^T: the oracle's adjoint of the padded row folded onto the ends, and the
+    # adjoint identity against the edge-extended forward on the GPU
+    import paper_2110_11866_amd as M
+    _announce("deriv-backward-edge", order, N, sigma, K, L, mode)
+    rng = np.random.default_rng(N + 11 * order)
+    x = (rng.standard_normal(N) + 1.0).astype(np.float32)
+    g = rng.standard_normal(N).astype(np.float32)
+    xt, gt = torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda()
+    plan = M.GaussDerivPlan(N, sigma, K, L, order=order, mode=mode).set_boundary("edge")
+    y = plan.forward(xt).cpu().numpy()
+    gx, gp = plan.backward(None, gt)
+    gx = gx.cpu().numpy()
+    torch.cuda.synchronize()
+    assert gp is None
+    info = plan.info()
+    p = O.plan_gauss_deriv(sigma, K, info["L"], order, mode=mode, n0=info["n0"] if mode == "asft" else None)
+    P = 2 * info["L"]
+    ge = np.concatenate([np.zeros(P), g.astype(np.float64), np.zeros(P)])
+    want = _fold(O.adjoint(ge, p), N, P)
+    assert rel(gx, want) <= 1e-5, rel(gx, want)
+    lhs = float(np.dot(g.astype(np.float64), y.astype(np.float64)))
+    rhs = float(np.dot(x.astype(np.float64), gx.astype(np.float64)))
+    assert abs(lhs - rhs) <= 2e-5 * (np.linalg.norm(g) * np.linalg.norm(y) + np.sqrt(N)), (lhs, rhs)
