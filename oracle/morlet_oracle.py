@@ -51,7 +51,7 @@ __all__ = [
     "select_PS", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
     "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
     "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
-    "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d", "sliding_sum", "forward_tree",
+    "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d", "gabor_2d", "sliding_sum", "forward_tree",
     "forward_edge",
 ]
 
@@ -686,6 +686,19 @@ def gauss_smooth_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
     rows = np.stack([forward(img[r], plan_x) for r in range(H)]) if H and W else np.zeros((H, W))
     out = np.stack([forward(rows[:, c], plan_y) for c in range(W)], axis=1) if H and W else np.zeros((H, W))
     return out
+
+
+def gabor_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
+    """Separable 2-D Gabor filter of a real H x W image: the Morlet transform of every row
+    (plan_x, complex), then the Gaussian smoothing of every column of its real and imaginary
+    parts (plan_y), the lines filtered independently (Sec. IV)."""
+    img = np.asarray(img, dtype=np.float64)
+    H, W = img.shape
+    if H == 0 or W == 0:
+        return np.zeros((H, W), dtype=np.complex128)
+    rows = np.stack([forward(img[r], plan_x) for r in range(H)])
+    cols = [forward(rows[:, c].real, plan_y) + 1j * forward(rows[:, c].imag, plan_y) for c in range(W)]
+    return np.stack(cols, axis=1)
 
 
 # --------------------------------------------------------------------------

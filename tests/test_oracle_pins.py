@@ -752,6 +752,60 @@ def test_gauss_2d_separable_cosine_image():
     assert np.allclose(y[11:H - 11, 8:W - 8], gx * gy * img[11:H - 11, 8:W - 8], rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+@pytest.mark.parametrize("H,W", [(1, 1), (4, 6), (9, 13)])
+def test_gabor_2d_equals_brute_force_outer_product(mode, H, W):
+    """Morlet rows then Gaussian columns equals one 2-D convolution with the outer product of
+    the complex row taps and the real column taps, written as a double loop."""
+    rng = np.random.default_rng(H * 17 + W)
+    img = rng.standard_normal((H, W))
+    px = O.plan_morlet(2.5, 6.0 / 2.5, 4, 7, mode=mode, n0=2 if mode == "asft" else None)
+    py = O.plan_gauss(3.0, 4, 8, mode=mode, n0=2 if mode == "asft" else None)
+    hx, sx = (O.asft_kernel(px), px.n0) if mode == "asft" else (O.kterm_morlet(px), 0)
+    hy, sy = (O.asft_kernel(py).real, py.n0) if mode == "asft" else (O.kterm_gauss(py), 0)
+    want = np.zeros((H, W), dtype=np.complex128)
+    for r in range(H):
+        for c in range(W):
+            acc = 0j
+            for i in range(-py.L, py.L + 1):
+                for j in range(-px.L, px.L + 1):
+                    rr, cc = r - sy - i, c - sx - j
+                    if 0 <= rr < H and 0 <= cc < W:
+                        acc += hy[i + py.L] * hx[j + px.L] * img[rr, cc]
+            want[r, c] = acc
+    assert np.allclose(O.gabor_2d(img, px, py), want, rtol=1e-11, atol=1e-13)
+
+
+def test_gabor_2d_single_row_is_the_row_transform_times_one_tap():
+    # H = 1: each column holds one sample, so the column pass multiplies by the single tap
+    # h_y[-n0] that lands on it (the centre tap for SFT)
+    rng = np.random.default_rng(3)
+    img = rng.standard_normal((1, 50))
+    for mode, n0 in (("sft", None), ("asft", 3)):
+        px = O.plan_morlet(6.0, 1.0, 5, 18, mode=mode, n0=n0)
+        py = O.plan_gauss(4.0, 5, 12, mode=mode, n0=n0)
+        tap = O.asft_kernel(py).real[py.L - py.n0] if mode == "asft" else O.kterm_gauss(py)[py.L]
+        assert np.allclose(O.gabor_2d(img, px, py)[0], tap * O.forward(img[0], px), rtol=1e-12, atol=1e-14)
+
+
+def test_gabor_2d_separable_cosine_image():
+    # img = cos(w1 r) cos(w2 c): in the interior the column pass scales by G_hat_y(w1) and the
+    # row pass maps cos(w2 c) to (Psi(w2) e^{i w2 c} + Psi(-w2) e^{-i w2 c}) / 2, with
+    # Psi(w) = sum_k psi_hat[k] e^{-i w k} and G_hat(w) = sum_k G_hat[k] cos(w k)
+    H, W = 70, 90
+    w1, w2 = 0.41, 0.93
+    r, c = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    img = np.cos(w1 * r) * np.cos(w2 * c)
+    px, py = O.plan_morlet(3.0, 1.1, 5, 10), O.plan_gauss(3.5, 4, 11)
+    k = np.arange(-10, 11)
+    psi = O.kterm_morlet(px)
+    Psi = lambda w: np.sum(psi * np.exp(-1j * w * k))
+    gy = sum(O.kterm_gauss(py)[j + 11] * math.cos(w1 * j) for j in range(-11, 12))
+    want = gy * np.cos(w1 * r) * (Psi(w2) * np.exp(1j * w2 * c) + Psi(-w2) * np.exp(-1j * w2 * c)) / 2
+    y = O.gabor_2d(img, px, py)
+    assert np.allclose(y[11:H - 11, 10:W - 10], want[11:H - 11, 10:W - 10], rtol=0, atol=1e-12)
+
+
 # ---------------------------------------------------------------- the paper's GPU route (Sec. IV)
 @pytest.mark.parametrize("Lw", [1, 2, 3, 7, 8, 64, 129, 1000])
 def test_sliding_sum_equals_direct_window_sum(Lw):
