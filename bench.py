@@ -1,7 +1,7 @@
 """Benchmark of the SFT/ASFT kernel-integral Morlet transform on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W]
-                [--workload scalogram|paper_scale|differentiation|gauss_deriv|multiply|image2d]
+                [--workload scalogram|paper_scale|differentiation|gauss_deriv|multiply|image2d|gabor2d]
 
 Prints one JSON line. A step is one pass of the transform over the workload's whole
 batch, with the inputs resident in HBM. The dominant kernel is timed with HIP events on
@@ -20,6 +20,8 @@ Workloads (seeded, synthetic):
                 sigma = 64, xi = 6/sigma, beside the direct method with P_D = 2 P_M + 1 = 5
   image2d     : separable 2-D Gaussian smoothing of a 4096 x 4096 float32 image, sigma = 8 on both
                 axes, K = 4 (rows, transpose, rows of the transposed image, transpose back)
+  gabor2d     : separable 2-D Gabor filter of a 4096 x 4096 float32 image: Morlet rows (sigma = 8,
+                xi = 6/sigma, K = 5), Gaussian columns of both parts (sigma = 8, K = 4)
 """
 from __future__ import annotations
 
@@ -46,12 +48,12 @@ def _parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scalogram",
                     choices=["scalogram", "paper_scale", "differentiation", "gauss_deriv", "multiply",
-                             "image2d"])
+                             "image2d", "gabor2d"])
     ap.add_argument("--mode", default="asft", choices=["sft", "asft"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", type=int, default=16, choices=[4, 8, 16, 32], help="samples per thread")
     ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "rows"],
-                    help="batched launch schedule (scalogram and image2d workloads)")
+                    help="batched launch schedule (scalogram, image2d and gabor2d workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of this many MB (counter calibration for HBM bytes)")
     return ap.parse_args()
@@ -326,6 +328,40 @@ def bench_image2d(args, torch, M):
     }
 
 
+def bench_gabor2d(args, torch, M):
+    """Separable 2-D Gabor filter of one 4096 x 4096 float32 image: the batched Morlet scan of
+    the rows (complex64 out), a transpose into the real and imaginary planes, one Gaussian
+    scan over their 8192 column lines, a transpose back to complex64."""
+    H = W = 4096
+    sigma, Kx, Ky = 8.0, 5, 4
+    xi = 6.0 / sigma
+    dev = torch.device("cuda:0")
+    x = torch.randn(H, W, generator=torch.Generator().manual_seed(19)).to(dev)
+    plan = M.Gabor2DPlan(H, W, sigma, xi, Kx, sigma, Ky, mode=args.mode)
+    plan.set_tile(args.tile).set_schedule(args.schedule)
+    out = torch.empty(H, W, dtype=torch.complex64, device=dev)
+    ws = plan.workspace(dev)
+    ms_step, kern_ms = _timed(torch, lambda: plan.forward(x, out=out, ws=ws), args.steps, args.warmup)
+    algo_bytes = H * W * (4 + 8)
+    achieved = algo_bytes / (kern_ms * 1e-3) / 1e9
+    ix, iy = plan.axis_info(0), plan.axis_info(1)
+    return {
+        "metric": f"Gpixels/s (separable 2-D Gabor filter, {args.mode.upper()})",
+        "value": H * W / (ms_step * 1e-3) / 1e9,
+        "unit": "Gpixels/s",
+        "ms_per_step": ms_step,
+        "dtype": "f32",
+        "config": {"workload": f"gabor2d: one 4096 x 4096 float32 N(0,1) image, Morlet rows sigma={sigma:g} "
+                               f"xi=6/sigma K={Kx} L={ix['L']}, Gaussian columns sigma={sigma:g} K={Ky} L={iy['L']} "
+                               f"(error-optimal windows), {args.mode}, complex64 out",
+                   "tile_R": args.tile, "schedule": args.schedule},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "scope": "whole path (two scans, two transposes) against 12 B per pixel"},
+        "kernel_ms": kern_ms,
+    }
+
+
 def bench_paper_scale(args, torch, M):
     import workloads
     from oracle import morlet_oracle as O
@@ -412,7 +448,7 @@ def main():
     import paper_2110_11866_amd as M
     fn = {"scalogram": bench_scalogram, "paper_scale": bench_paper_scale,
           "differentiation": bench_differentiation, "gauss_deriv": bench_gauss_deriv,
-          "multiply": bench_multiply, "image2d": bench_image2d}[args.workload]
+          "multiply": bench_multiply, "image2d": bench_image2d, "gabor2d": bench_gabor2d}[args.workload]
     line = fn(args, torch, M)
     full = {"metric": line.pop("metric"), "value": line.pop("value"), "unit": line.pop("unit"),
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": line.pop("ms_per_step"),

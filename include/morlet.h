@@ -175,9 +175,31 @@ morlet_status gauss_smooth2d(morlet_plan_t plan, const void* x, morlet_dtype dty
 morlet_status gauss_smooth2d_backward(morlet_plan_t plan, const float* gy, float* gx, void* ws, size_t ws_bytes,
                                       void* stream);
 
+/* Create a plan for the separable 2-D Gabor filter of a real H x W image (row-major, x along
+ * a row; Sec. IV filters the lines of an image independently): the Morlet transform of every
+ * row (sigma_x, xi in rad/sample, K_x terms, window L_x: the direct method of Sec. III-A, rules
+ * as morlet_plan), then the Gaussian smoothing of every column of its real and imaginary parts
+ * (sigma_y, K_y terms, window L_y: rules as morlet_plan_gauss). L = 0 selects the error-optimal
+ * window per axis. y[r][c] = sum_{i,j} G_y[i] psi_x[j] x[r - i][c - j] (ASFT: each axis's
+ * attenuated taps, read n0 of that axis later). morlet_plan_set, morlet_plan_set_tile and
+ * morlet_plan_set_schedule apply to both axes. H, W in [0, 2^24], H W <= 2^35. Forward only:
+ * gauss_smooth2d_backward returns MORLET_ERR_UNSUPPORTED, as does morlet_backward_workspace_size. */
+morlet_status morlet_plan_gabor2d(morlet_plan_t* out, int64_t H, int64_t W, double sigma_x, double xi, int32_t K_x,
+                                  int64_t L_x, double sigma_y, int32_t K_y, int64_t L_y);
+
+/* 2-D Gabor filter: x (device, H x W elements of dtype, row-major) -> y (device complex64
+ * [re, im] pairs, H x W, row-major). Four launches on the stream: the batched Morlet scan of
+ * the H rows into the workspace, a transpose into the real and imaginary planes, one Gaussian
+ * scan over their 2W column lines, a transpose back into y. Workspace: morlet_workspace_size
+ * (zero-filled once): the tile states and two H W complex64 buffers. Errors: a non-Gabor plan
+ * is MORLET_ERR_INVALID_ARG; otherwise as gauss_smooth2d. */
+morlet_status gabor2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* y, void* ws, size_t ws_bytes,
+                      void* stream);
+
 /* Per-axis parameters of an image plan: axis 0 filters along x (the rows), axis 1 along y.
- * L: window half width; n0: ASFT shift in use (0 for SFT); cos_coef[K]: a_p; kernel_relrmse:
- * error of the fitted Gaussian on [-L, L]. Outputs are nullable. */
+ * L: window half width; n0: ASFT shift in use (0 for SFT); cos_coef[K of that axis]: a_p (the
+ * Gaussian) or m_p (the Morlet rows of a Gabor plan); kernel_relrmse: error of the fitted
+ * kernel on [-L, L]. Outputs are nullable. */
 morlet_status morlet_image_axis_info(morlet_plan_t plan, int32_t axis, int64_t* L, int64_t* n0, double* cos_coef,
                                      double* kernel_relrmse);
 

@@ -13,7 +13,7 @@ from . import _abi
 from ._abi import (MORLET_ACC_COMPENSATED, MORLET_ACC_F32, MORLET_BF16, MORLET_F16, MORLET_F32,
                    MORLET_SCAN_ASFT, MORLET_SCAN_SFT, MorletError)
 
-__all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2DPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
+__all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2DPlan", "Gabor2DPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
            "MorletTransform"]
 
 _DT = {torch.float32: MORLET_F32, torch.float16: MORLET_F16, torch.bfloat16: MORLET_BF16}
@@ -320,6 +320,52 @@ class Gauss2DPlan(_PlanBase):
         gx = torch.empty((self.H, self.W), dtype=torch.float32, device=gy.device)
         _abi.gauss_smooth2d_backward(self.handle, gy.data_ptr(), gx.data_ptr(), w.data_ptr(), w.numel(), _stream())
         return gx
+
+
+class Gabor2DPlan(_PlanBase):
+    """Separable 2-D Gabor filter of a real H x W image (row-major, x along a row): the Morlet
+    transform of every row (sigma_x, xi in rad/sample, K_x terms), then the Gaussian smoothing
+    of every column of its real and imaginary parts (sigma_y, K_y terms); windows 0 are
+    error-optimal. Complex64 output, forward only."""
+
+    kind = "gabor"
+
+    def __init__(self, H: int, W: int, sigma_x: float, xi: float, K_x: int, sigma_y: float, K_y: int,
+                 L_x: int = 0, L_y: int = 0, mode: str = "sft", n0: int = 0, accum: str = "f32"):
+        h = _abi.morlet_plan_gabor2d(int(H), int(W), float(sigma_x), float(xi), int(K_x), int(L_x), float(sigma_y),
+                                     int(K_y), int(L_y))
+        super().__init__(h, int(H) * int(W), max(int(K_x), int(K_y)))
+        self.H, self.W = int(H), int(W)
+        self.K_x, self.K_y = int(K_x), int(K_y)
+        self.sigma_x, self.xi, self.sigma_y = float(sigma_x), float(xi), float(sigma_y)
+        if mode != "sft" or n0 or accum != "f32":
+            self.set(mode, n0, accum)
+
+    def info(self) -> dict:
+        raise TypeError("use axis_info(0) (Morlet rows) or axis_info(1) (Gaussian columns) for an image plan")
+
+    def axis_info(self, axis: int) -> dict:
+        return _abi.morlet_image_axis_info(self.handle, int(axis), self.K_x if int(axis) == 0 else self.K_y)
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+        if not x.is_cuda:
+            raise ValueError("x must be a device tensor")
+        if x.numel() != self.N or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous tensor of {self.H} x {self.W} pixels")
+        if out is None:
+            out = torch.empty((self.H, self.W), dtype=torch.complex64, device=x.device)
+        if out.dtype != torch.complex64 or out.numel() != self.N or not out.is_contiguous():
+            raise ValueError("out must be a contiguous complex64 tensor of H x W elements")
+        w = self.workspace(x.device) if ws is None else ws
+        _abi.gabor2d(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(), w.data_ptr(), w.numel(),
+                     _stream())
+        return out
+
+    def autotune(self, *args, **kwargs):
+        raise NotImplementedError("autotune does not take image plans")
+
+    def backward(self, *args, **kwargs):
+        raise NotImplementedError("the 2-D Gabor filter is built forward only")
 
 
 class ScalogramPlan(_PlanBase):

@@ -11,6 +11,7 @@
 
 #include "../../include/morlet.h"
 #include "boundary.h"
+#include "image2d.h"
 #include "launch.h"
 #include "multiply.h"
 #include "plan_internal.h"
@@ -210,6 +211,49 @@ morlet_status init_gauss_rows(morlet_plan_s* p, int B, int64_t len, double sigma
   return upload_batched(p);
 }
 
+// B Morlet rows of one length at one scale (the row pass of the 2-D Gabor filter): the same
+// fit as morlet_plan, rows laid out back to back.
+morlet_status init_morlet_rows(morlet_plan_s* p, int B, int64_t len, double sigma, double xi, int K, int64_t L) {
+  p->kind = 0;
+  p->sigma = sigma;
+  p->xi = xi;
+  p->K = K;
+  p->L = L ? L : mk::select_L(sigma, xi, K, false);
+  p->P_S = mk::select_ps(sigma, xi, K, p->L, nullptr);
+  std::vector<double> re, im;
+  mk::morlet_taps(sigma, xi, p->L, re, im);
+  const mk::Fit f = mk::fit_orders(re, im, p->L, p->P_S, K);
+  p->cc = f.cc;
+  p->sc = f.sc;
+  p->relrmse = f.relrmse;
+  mk::jacobian(p);
+  p->batched = true;
+  p->B = B;
+  p->S = 1;
+  p->N = (int64_t)B * len;
+  p->R = 16;
+  p->lengths.assign(B, len);
+  p->offsets.resize(B);
+  for (int b = 0; b < B; ++b) p->offsets[b] = (int64_t)b * len;
+  ScaleParams sp;
+  sp.sigma = sigma;
+  sp.xi = xi;
+  sp.L = p->L;
+  sp.P_S = p->P_S;
+  sp.n0_asft = default_n0(sigma, p->L);
+  sp.cc = p->cc;
+  sp.sc = p->sc;
+  sp.jac = p->jac;
+  sp.relrmse = p->relrmse;
+  if (!std::isfinite(sp.relrmse)) return fail(MORLET_ERR_INVALID_ARG, "fit failed");
+  p->scales = {sp};
+  p->n0_asft = sp.n0_asft;
+  build_rows(p);
+  if (p->ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  build_batched_tables(p);
+  return upload_batched(p);
+}
+
 // Fill the launch descriptor for this plan (rows, tables, tiles, workspace, grid).
 morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int variant, int mom, int dtype) {
   const int64_t jend = plan->N + plan->L - plan->n0;
@@ -351,7 +395,7 @@ morlet_status run_edge(morlet_plan_t plan, const void* x, int dtype, void* out, 
 morlet_status run_scan(morlet_plan_t plan, const void* x, int dtype, void* out, void* ws, size_t ws_bytes,
                        void* stream, int want_kind, bool want_batched = false) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
-  if (plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "an image plan runs with gauss_smooth2d");
+  if (plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "an image plan runs with gauss_smooth2d or gabor2d");
   if (plan->kind != want_kind)
     return fail(MORLET_ERR_INVALID_ARG, want_kind == 0 ? "morlet_forward needs a Morlet plan"
                                                        : "gauss_smooth needs a Gaussian plan");
@@ -440,6 +484,57 @@ ImageLayout image_layout(morlet_plan_t plan) {
 // Separable 2-D Gaussian smoothing: rows (x -> A), transpose (A -> B), rows of the transposed
 // image (B -> A), transpose back (A -> y). Both scans share the workspace's tile states: they
 // run in stream order and each launch re-arms the header for the next.
+// Workspace of a 2-D Gabor plan: the larger axis's tile states, then two buffers of H W
+// complex64 (the row pass's output, then the two real planes of its transpose).
+ImageLayout gabor_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t px = (size_t)plan->img_H * (size_t)plan->img_W * 2 * sizeof(float);
+  ImageLayout m;
+  m.a_off = up(std::max(mk::workspace_bytes(plan->axis[0]->K, plan->axis[0]->ntiles_max),
+                        mk::workspace_bytes(plan->axis[1]->K, plan->axis[1]->ntiles_max)));
+  m.b_off = up(m.a_off + px);
+  m.total = m.b_off + px;
+  return m;
+}
+
+// Separable 2-D Gabor filter (Sec. IV: lines filtered independently): the Morlet transform of
+// the H rows (one batched launch, complex64 out), a transpose into the real and imaginary
+// planes (W x H each), one Gaussian launch over their 2W rows, a transpose back to complex64.
+morlet_status run_gabor2d(morlet_plan_t plan, const void* x, int dtype, void* y, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  const int64_t H = plan->img_H, W = plan->img_W;
+  if (H == 0 || W == 0) return MORLET_OK;
+  if (!x || !y || !ws) return fail(MORLET_ERR_INVALID_ARG, "null x, output or workspace pointer");
+  const ImageLayout m = gabor_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small");
+  if (!plan->axis[0]->d_tab || !plan->axis[1]->d_tab)
+    return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float2* Z = reinterpret_cast<float2*>(wsb + m.a_off);
+  float* P = reinterpret_cast<float*>(wsb + m.b_off);
+  mk::ScanLaunch a;
+  morlet_status st = make_launch(plan->axis[0], a, ws, mk::kVarForward, 0, dtype);
+  if (st != MORLET_OK) return st;
+  a.x = x;
+  a.dtype = dtype;
+  a.out = Z;
+  hipError_t e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e == hipSuccess) e = mk::launch_transpose_c2p(Z, P, H, W, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  st = make_launch(plan->axis[1], a, ws, mk::kVarForward, 0, 0);
+  if (st != MORLET_OK) return st;
+  float* G = reinterpret_cast<float*>(Z);   // the 2W smoothed column lines, planar
+  a.x = P;
+  a.dtype = 0;
+  a.out = G;
+  e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e == hipSuccess) e = mk::launch_transpose_p2c(G, static_cast<float2*>(y), H, W, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
+}
+
 morlet_status run_image2d(morlet_plan_t plan, const void* x, int dtype, float* y, void* ws, size_t ws_bytes,
                           void* stream) {
   if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
@@ -997,14 +1092,62 @@ morlet_status morlet_plan_gauss2d(morlet_plan_t* out, int64_t H, int64_t W, doub
 
 morlet_status gauss_smooth2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, float* y, void* ws,
                              size_t ws_bytes, void* stream) {
-  if (!plan || !plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d needs an image plan");
+  if (!plan || !plan->image2d || plan->gabor)
+    return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d needs a Gaussian image plan");
   return run_image2d(plan, x, (int)dtype, y, ws, ws_bytes, stream);
 }
 
 morlet_status gauss_smooth2d_backward(morlet_plan_t plan, const float* gy, float* gx, void* ws, size_t ws_bytes,
                                       void* stream) {
   if (!plan || !plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d_backward needs an image plan");
+  if (plan->gabor) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for Gabor image plans");
   return run_image2d_backward(plan, gy, gx, ws, ws_bytes, stream);
+}
+
+morlet_status morlet_plan_gabor2d(morlet_plan_t* out, int64_t H, int64_t W, double sigma_x, double xi, int32_t K_x,
+                                  int64_t L_x, double sigma_y, int32_t K_y, int64_t L_y) {
+  if (!out) return fail(MORLET_ERR_INVALID_ARG, "null output handle");
+  if (H < 0 || W < 0 || H > ((int64_t)1 << 24) || W > ((int64_t)1 << 24) || H * W > ((int64_t)1 << 35))
+    return fail(MORLET_ERR_INVALID_ARG, "H, W must be in [0, 2^24] with H W <= 2^35");
+  morlet_status s = check_common(W, sigma_x, K_x, L_x);
+  if (s == MORLET_OK) s = check_common(H, sigma_y, K_y, L_y);
+  if (s != MORLET_OK) return s;
+  if (!finite_pos(xi)) return fail(MORLET_ERR_INVALID_ARG, "xi must be finite and > 0");
+  if (L_x != 0 && L_x < K_x) return fail(MORLET_ERR_INVALID_ARG, "L_x must be >= K_x");
+  if (L_y != 0 && L_y + 1 < K_y) return fail(MORLET_ERR_INVALID_ARG, "L_y must be >= K_y - 1");
+  auto* p = new (std::nothrow) morlet_plan_s;
+  auto* ax = new (std::nothrow) morlet_plan_s;
+  auto* ay = new (std::nothrow) morlet_plan_s;
+  if (!p || !ax || !ay) {
+    delete p;
+    delete ax;
+    delete ay;
+    return fail(MORLET_ERR_ALLOC, "out of host memory");
+  }
+  p->kind = 0;
+  p->image2d = true;
+  p->gabor = true;
+  p->img_H = H;
+  p->img_W = W;
+  p->K = std::max(K_x, K_y);
+  p->N = H * W;
+  p->axis[0] = ax;
+  p->axis[1] = ay;
+  const bool empty = H == 0 || W == 0;
+  s = init_morlet_rows(ax, empty ? 0 : (int)H, W, sigma_x, xi, K_x, L_x);
+  if (s == MORLET_OK) s = init_gauss_rows(ay, empty ? 0 : (int)(2 * W), H, sigma_y, K_y, L_y);
+  if (s != MORLET_OK) {
+    morlet_destroy(p);
+    return s;
+  }
+  *out = p;
+  return MORLET_OK;
+}
+
+morlet_status gabor2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* y, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (!plan || !plan->image2d || !plan->gabor) return fail(MORLET_ERR_INVALID_ARG, "gabor2d needs a Gabor image plan");
+  return run_gabor2d(plan, x, (int)dtype, y, ws, ws_bytes, stream);
 }
 
 morlet_status morlet_image_axis_info(morlet_plan_t plan, int32_t axis, int64_t* L, int64_t* n0, double* cos_coef,
@@ -1226,7 +1369,7 @@ morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
   // sized for the longest scan range over every n0 the plan may use (n0 = 0)
   if (plan->image2d) {
-    *bytes = image_layout(plan).total;
+    *bytes = plan->gabor ? gabor_layout(plan).total : image_layout(plan).total;
     return MORLET_OK;
   }
   if (plan->boundary == 1) {
@@ -1372,6 +1515,7 @@ void morlet_destroy(morlet_plan_t plan) {
 morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
   if (plan->image2d) {
+    if (plan->gabor) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for Gabor image plans");
     *bytes = image_bwd_layout(plan).total;
     return MORLET_OK;
   }

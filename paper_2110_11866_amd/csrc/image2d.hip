@@ -1,10 +1,11 @@
-// Transpose for separable 2-D filtering of images: the lines of an image are filtered
+// Transposes for separable 2-D filtering of images: the lines of an image are filtered
 // independently (Sec. IV), rows by one batched scan launch over the H rows, columns by a
 // second over the W rows of the transposed image. out[c][r] = in[r][c] for an R x C row-major
 // float32 matrix, through 64 x 64 LDS tiles (row pitch 65, so the transposed reads hit 64
 // different banks); both the loads and the stores are row-contiguous across a wave.
 #include <hip/hip_runtime.h>
 
+#include "image2d.h"
 #include "launch.h"
 
 namespace mk {
@@ -30,7 +31,72 @@ __global__ __launch_bounds__(kTpThreads) void transpose_kernel(const float* in, 
   }
 }
 
+// Complex image to two planes: the same 64 x 64 tiles, one LDS tile per component. Loads are
+// 8-byte words contiguous along a row of Z, stores contiguous along a row of each plane.
+__global__ __launch_bounds__(kTpThreads) void transpose_c2p_kernel(const float2* in, float* out, int64_t R, int64_t C,
+                                                                     int64_t nbc) {
+  __shared__ float tr[kTpTile][kTpTile + 1], ti[kTpTile][kTpTile + 1];
+  const int64_t b = blockIdx.x;
+  const int64_t r0 = (b / nbc) * kTpTile, c0 = (b % nbc) * kTpTile;
+  const int tx = threadIdx.x & (kTpTile - 1), ty = threadIdx.x / kTpTile;
+  for (int i = ty; i < kTpTile; i += kTpThreads / kTpTile) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    if (r < R && c < C) {
+      const float2 v = in[r * C + c];
+      tr[i][tx] = v.x;
+      ti[i][tx] = v.y;
+    }
+  }
+  __syncthreads();
+  const int64_t plane = R * C;
+  for (int i = ty; i < kTpTile; i += kTpThreads / kTpTile) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < C && r < R) {
+      out[c * R + r] = tr[tx][i];
+      out[plane + c * R + r] = ti[tx][i];
+    }
+  }
+}
+
+// Two planes back to the complex image: tile element [i][tx] holds plane[c0 + i][r0 + tx].
+__global__ __launch_bounds__(kTpThreads) void transpose_p2c_kernel(const float* in, float2* out, int64_t R, int64_t C,
+                                                                     int64_t nbc) {
+  __shared__ float tr[kTpTile][kTpTile + 1], ti[kTpTile][kTpTile + 1];
+  const int64_t b = blockIdx.x;
+  const int64_t r0 = (b / nbc) * kTpTile, c0 = (b % nbc) * kTpTile;
+  const int tx = threadIdx.x & (kTpTile - 1), ty = threadIdx.x / kTpTile;
+  const int64_t plane = R * C;
+  for (int i = ty; i < kTpTile; i += kTpThreads / kTpTile) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < C && r < R) {
+      tr[i][tx] = in[c * R + r];
+      ti[i][tx] = in[plane + c * R + r];
+    }
+  }
+  __syncthreads();
+  for (int i = ty; i < kTpTile; i += kTpThreads / kTpTile) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    if (r < R && c < C) out[r * C + c] = make_float2(tr[tx][i], ti[tx][i]);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_transpose_c2p(const float2* Z, float* P, int64_t R, int64_t C, hipStream_t s) {
+  if (R <= 0 || C <= 0) return hipSuccess;
+  const int64_t nbr = (R + kTpTile - 1) / kTpTile, nbc = (C + kTpTile - 1) / kTpTile;
+  if (nbr * nbc > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose_c2p_kernel, dim3((unsigned)(nbr * nbc)), dim3(kTpThreads), 0, s, Z, P, R, C, nbc);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_p2c(const float* P, float2* Z, int64_t R, int64_t C, hipStream_t s) {
+  if (R <= 0 || C <= 0) return hipSuccess;
+  const int64_t nbr = (R + kTpTile - 1) / kTpTile, nbc = (C + kTpTile - 1) / kTpTile;
+  if (nbr * nbc > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(transpose_p2c_kernel, dim3((unsigned)(nbr * nbc)), dim3(kTpThreads), 0, s, P, Z, R, C, nbc);
+  return hipGetLastError();
+}
 
 hipError_t launch_transpose(const float* in, float* out, int64_t R, int64_t C, hipStream_t s) {
   if (R <= 0 || C <= 0) return hipSuccess;

@@ -65,6 +65,7 @@ struct morlet_plan_s {
   // axis[0] is a batched Gaussian plan over the H rows (length W), axis[1] one over the W rows
   // of the transposed image (length H); this plan owns both
   bool image2d = false;
+  bool gabor = false;   // image plan: Morlet rows (axis 0) then Gaussian columns of both parts
   int64_t img_H = 0, img_W = 0;
   morlet_plan_s* axis[2] = {nullptr, nullptr};
 };

@@ -380,6 +380,46 @@ def test_image_plan_errors_and_workspace():
         _abi.morlet_destroy(h1)
 
 
+def test_gabor_plan_errors_and_workspace():
+    L = _abi.lib()
+    h = ctypes.c_void_p()
+    for args in [(-1, 10, 2.0, 1.0, 3, 0, 2.0, 3, 0), (10, 1 << 25, 2.0, 1.0, 3, 0, 2.0, 3, 0),
+                 (10, 10, 2.0, 0.0, 3, 0, 2.0, 3, 0), (10, 10, 2.0, 1.0, 5, 4, 2.0, 3, 0),
+                 (10, 10, 2.0, 1.0, 3, 0, -2.0, 3, 0), (10, 10, 2.0, 1.0, 3, 0, 2.0, 5, 2)]:
+        assert L.morlet_plan_gabor2d(ctypes.byref(h), *args) == _abi.MORLET_ERR_INVALID_ARG, args
+    hp = _abi.morlet_plan_gabor2d(120, 90, 3.0, 2.0, 5, 0, 4.0, 4, 0)
+    hg = _abi.morlet_plan_gauss2d(120, 90, 3.0, 5.0, 4, 0, 0)
+    fake = 1 << 20
+    try:
+        # two complex64 buffers of the image on top of the tile states
+        assert _abi.morlet_workspace_size(hp) >= 2 * 120 * 90 * 8
+        assert L.gabor2d(hp, fake, 0, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
+        assert L.gabor2d(hp, fake, 3, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.gabor2d(hg, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.gauss_smooth2d(hp, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_forward(hp, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.gauss_smooth2d_backward(hp, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        n = ctypes.c_size_t()
+        assert L.morlet_backward_workspace_size(hp, ctypes.byref(n)) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.morlet_plan_set_boundary(hp, 1) == _abi.MORLET_ERR_UNSUPPORTED
+        # axis 0 carries the Morlet fit (K_x = 5 coefficients), axis 1 the Gaussian (K_y = 4)
+        ix = _abi.morlet_image_axis_info(hp, 0, 5)
+        iy = _abi.morlet_image_axis_info(hp, 1, 4)
+        assert ix["L"] >= 5 and iy["L"] >= 3 and ix["kernel_relrmse"] < 0.5 and iy["kernel_relrmse"] < 0.1
+        for R in (4, 8, 32, 16):
+            assert L.morlet_plan_set_tile(hp, R) == _abi.MORLET_OK
+        assert L.morlet_plan_set(hp, _abi.MORLET_SCAN_ASFT, 0, 0) == _abi.MORLET_OK
+        assert _abi.morlet_image_axis_info(hp, 0, 5)["n0"] >= 1
+        h0 = _abi.morlet_plan_gabor2d(0, 90, 3.0, 2.0, 5, 0, 4.0, 4, 0)
+        try:
+            assert L.gabor2d(h0, None, 0, None, None, 0, None) == _abi.MORLET_OK   # empty: nothing to do
+        finally:
+            _abi.morlet_destroy(h0)
+    finally:
+        _abi.morlet_destroy(hp)
+        _abi.morlet_destroy(hg)
+
+
 def test_tree_path_errors_and_workspace():
     L = _abi.lib()
     h = _abi.morlet_plan(5000, 20.0, 0.3, 5, 80)

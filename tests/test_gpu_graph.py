@@ -127,8 +127,8 @@ def test_autotune_single_and_scalogram():
 
 
 def test_graph_newer_forward_paths():
-    # the multiplication method (three kernels), the 2-D smoothing (two scans, two transposes)
-    # and the edge-extended forward (extension kernel, scan, device-to-device copy) replay
+    # the multiplication method (three kernels), the 2-D smoothing and the 2-D Gabor filter
+    # (two scans, two transposes each) and the edge-extended forward (extension kernel, scan, device-to-device copy) replay
     # bitwise like their eager calls
     import paper_2110_11866_amd as M
     _announce("graph-newer")
@@ -145,6 +145,9 @@ def test_graph_newer_forward_paths():
     pi = M.Gauss2DPlan(H, W, 5.0, 7.0, 4, mode="asft")
     wi, oi = pi.workspace(xt.device), torch.empty(H, W, dtype=torch.float32, device=xt.device)
     _replays(lambda: (pi.forward(xt, out=oi, ws=wi),), xt, fresh)
+    pg = M.Gabor2DPlan(H, W, 4.0, 1.5, 5, 6.0, 4, mode="asft")
+    wg, og = pg.workspace(xt.device), torch.empty(H, W, dtype=torch.complex64, device=xt.device)
+    _replays(lambda: (pg.forward(xt, out=og, ws=wg),), xt, fresh)
 
 
 def test_graph_newer_backward_paths():
