@@ -51,7 +51,7 @@ __all__ = [
     "select_PS", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
     "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
     "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
-    "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d", "gabor_2d", "sliding_sum", "forward_tree",
+    "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d", "gabor_2d", "gabor_2d_adjoint", "sliding_sum", "forward_tree",
     "forward_edge",
 ]
 
@@ -699,6 +699,19 @@ def gabor_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
     rows = np.stack([forward(img[r], plan_x) for r in range(H)])
     cols = [forward(rows[:, c].real, plan_y) + 1j * forward(rows[:, c].imag, plan_y) for c in range(W)]
     return np.stack(cols, axis=1)
+
+
+def gabor_2d_adjoint(g: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
+    """Transpose of gabor_2d for a real loss, g = dLoss/dRe y + i dLoss/dIm y (H x W): the
+    column pass's adjoint on the real and imaginary parts of every column, then the row pass's
+    adjoint (adjoint()) of every row's complex cotangent."""
+    g = np.asarray(g, dtype=np.complex128)
+    H, W = g.shape
+    if H == 0 or W == 0:
+        return np.zeros((H, W))
+    cols = [adjoint(g[:, c].real, plan_y) + 1j * adjoint(g[:, c].imag, plan_y) for c in range(W)]
+    g1 = np.stack(cols, axis=1)
+    return np.stack([adjoint(g1[r], plan_x) for r in range(H)])
 
 
 # --------------------------------------------------------------------------

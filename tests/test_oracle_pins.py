@@ -776,6 +776,27 @@ def test_gabor_2d_equals_brute_force_outer_product(mode, H, W):
     assert np.allclose(O.gabor_2d(img, px, py), want, rtol=1e-11, atol=1e-13)
 
 
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_gabor_2d_adjoint_identity(mode):
+    # Re <g, y(x)> = <gabor_2d_adjoint(g), x> for every real x and complex g, checked on a random
+    # pair and on every basis image of a tiny case (the adjoint's full matrix against the forward's)
+    px = O.plan_morlet(2.5, 2.0, 4, 7, mode=mode, n0=2 if mode == "asft" else None)
+    py = O.plan_gauss(3.0, 4, 8, mode=mode, n0=3 if mode == "asft" else None)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((11, 17))
+    g = rng.standard_normal((11, 17)) + 1j * rng.standard_normal((11, 17))
+    lhs = np.sum((np.conj(g) * O.gabor_2d(x, px, py)).real)
+    assert abs(lhs - np.sum(O.gabor_2d_adjoint(g, px, py) * x)) <= 1e-12 * (1 + abs(lhs))
+    H, W = 3, 4
+    g = rng.standard_normal((H, W)) + 1j * rng.standard_normal((H, W))
+    gx = O.gabor_2d_adjoint(g, px, py)
+    for r in range(H):
+        for c in range(W):
+            e = np.zeros((H, W))
+            e[r, c] = 1.0
+            assert abs(np.sum((np.conj(g) * O.gabor_2d(e, px, py)).real) - gx[r, c]) <= 1e-13
+
+
 def test_gabor_2d_single_row_is_the_row_transform_times_one_tap():
     # H = 1: each column holds one sample, so the column pass multiplies by the single tap
     # h_y[-n0] that lands on it (the centre tap for SFT)
