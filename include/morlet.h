@@ -182,8 +182,8 @@ morlet_status gauss_smooth2d_backward(morlet_plan_t plan, const float* gy, float
  * (sigma_y, K_y terms, window L_y: rules as morlet_plan_gauss). L = 0 selects the error-optimal
  * window per axis. y[r][c] = sum_{i,j} G_y[i] psi_x[j] x[r - i][c - j] (ASFT: each axis's
  * attenuated taps, read n0 of that axis later). morlet_plan_set, morlet_plan_set_tile and
- * morlet_plan_set_schedule apply to both axes. H, W in [0, 2^24], H W <= 2^35. Forward only:
- * gauss_smooth2d_backward returns MORLET_ERR_UNSUPPORTED, as does morlet_backward_workspace_size. */
+ * morlet_plan_set_schedule apply to both axes. H, W in [0, 2^24], H W <= 2^35. The backward
+ * (dLoss/dx) is gabor2d_backward; gauss_smooth2d_backward refuses a Gabor plan. */
 morlet_status morlet_plan_gabor2d(morlet_plan_t* out, int64_t H, int64_t W, double sigma_x, double xi, int32_t K_x,
                                   int64_t L_x, double sigma_y, int32_t K_y, int64_t L_y);
 
@@ -195,6 +195,16 @@ morlet_status morlet_plan_gabor2d(morlet_plan_t* out, int64_t H, int64_t W, doub
  * is MORLET_ERR_INVALID_ARG; otherwise as gauss_smooth2d. */
 morlet_status gabor2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* y, void* ws, size_t ws_bytes,
                       void* stream);
+
+/* Backward of the 2-D Gabor filter for a real loss: gW = dLoss/dRe y + i dLoss/dIm y (device
+ * complex64, H x W) -> gx = dLoss/dx (device float32, H x W, overwritten). The transposes of
+ * the two passes in reverse order: gW into its real and imaginary planes, the Gaussian adjoint
+ * over the 2W column lines, back to complex64, the batched Morlet adjoint over the H rows
+ * (per-line adjoints as morlet_backward). No parameter gradients. Workspace:
+ * morlet_backward_workspace_size (zero-filled once; not the forward's). Errors: a non-Gabor
+ * plan is MORLET_ERR_INVALID_ARG; a short workspace MORLET_ERR_WORKSPACE. */
+morlet_status gabor2d_backward(morlet_plan_t plan, const void* gW, float* gx, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* Per-axis parameters of an image plan: axis 0 filters along x (the rows), axis 1 along y.
  * L: window half width; n0: ASFT shift in use (0 for SFT); cos_coef[K of that axis]: a_p (the

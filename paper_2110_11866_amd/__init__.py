@@ -326,7 +326,7 @@ class Gabor2DPlan(_PlanBase):
     """Separable 2-D Gabor filter of a real H x W image (row-major, x along a row): the Morlet
     transform of every row (sigma_x, xi in rad/sample, K_x terms), then the Gaussian smoothing
     of every column of its real and imaginary parts (sigma_y, K_y terms); windows 0 are
-    error-optimal. Complex64 output, forward only."""
+    error-optimal. Complex64 output; the backward gives dLoss/dx."""
 
     kind = "gabor"
 
@@ -364,8 +364,14 @@ class Gabor2DPlan(_PlanBase):
     def autotune(self, *args, **kwargs):
         raise NotImplementedError("autotune does not take image plans")
 
-    def backward(self, *args, **kwargs):
-        raise NotImplementedError("the 2-D Gabor filter is built forward only")
+    def backward(self, gW: torch.Tensor) -> torch.Tensor:
+        """dLoss/dx (float32, H x W) for gW = dLoss/dRe y + i dLoss/dIm y (complex64, H x W)."""
+        if not gW.is_cuda or gW.dtype != torch.complex64 or gW.numel() != self.N or not gW.is_contiguous():
+            raise ValueError("gW must be a contiguous complex64 device tensor of H x W elements")
+        w = self.workspace(gW.device, backward=True)
+        gx = torch.empty((self.H, self.W), dtype=torch.float32, device=gW.device)
+        _abi.gabor2d_backward(self.handle, gW.data_ptr(), gx.data_ptr(), w.data_ptr(), w.numel(), _stream())
+        return gx
 
 
 class ScalogramPlan(_PlanBase):

@@ -857,6 +857,42 @@ morlet_status run_image2d_backward(morlet_plan_t plan, const float* gy, float* g
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return run_backward(plan->axis[0], nullptr, 0, A, gx, nullptr, aw, aw_bytes, stream, 1, true);
 }
+
+// Backward of the 2-D Gabor filter for a real loss (gW = dLoss/dRe y + i dLoss/dIm y, H x W
+// complex64): the column pass's transpose on both planes, then the row pass's. gW to planes
+// (W x H each), the Gaussian adjoint over the 2W column lines, back to complex64 (H x W), the
+// Morlet adjoint over the H rows. Workspace: the larger axis's backward workspace, then two
+// buffers of H W complex64.
+ImageBwdLayout gabor_bwd_layout(morlet_plan_t plan) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t px = (size_t)plan->img_H * (size_t)plan->img_W * 2 * sizeof(float);
+  ImageBwdLayout m;
+  m.axis_bytes = std::max(bwd_layout(plan->axis[0]).total, bwd_layout(plan->axis[1]).total);
+  m.a_off = up(m.axis_bytes);
+  m.b_off = up(m.a_off + px);
+  m.total = m.b_off + px;
+  return m;
+}
+
+morlet_status run_gabor2d_backward(morlet_plan_t plan, const void* gW, float* gx, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  const int64_t H = plan->img_H, W = plan->img_W;
+  if (H == 0 || W == 0) return MORLET_OK;
+  if (!gW || !gx || !ws) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  const ImageBwdLayout m = gabor_bwd_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* A = reinterpret_cast<float*>(wsb + m.a_off);
+  float* B = reinterpret_cast<float*>(wsb + m.b_off);
+  hipError_t e = mk::launch_transpose_c2p(static_cast<const float2*>(gW), B, H, W, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  morlet_status st = run_backward(plan->axis[1], nullptr, 0, B, A, nullptr, ws, m.axis_bytes, stream, 1, true);
+  if (st != MORLET_OK) return st;
+  e = mk::launch_transpose_p2c(A, reinterpret_cast<float2*>(B), H, W, s);   // the rows' complex cotangent
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return run_backward(plan->axis[0], nullptr, 0, B, gx, nullptr, ws, m.axis_bytes, stream, 0, true);
+}
 }  // namespace
 
 extern "C" {
@@ -1100,7 +1136,7 @@ morlet_status gauss_smooth2d(morlet_plan_t plan, const void* x, morlet_dtype dty
 morlet_status gauss_smooth2d_backward(morlet_plan_t plan, const float* gy, float* gx, void* ws, size_t ws_bytes,
                                       void* stream) {
   if (!plan || !plan->image2d) return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d_backward needs an image plan");
-  if (plan->gabor) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for Gabor image plans");
+  if (plan->gabor) return fail(MORLET_ERR_INVALID_ARG, "a Gabor image plan runs with gabor2d_backward");
   return run_image2d_backward(plan, gy, gx, ws, ws_bytes, stream);
 }
 
@@ -1148,6 +1184,12 @@ morlet_status gabor2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, voi
                       void* stream) {
   if (!plan || !plan->image2d || !plan->gabor) return fail(MORLET_ERR_INVALID_ARG, "gabor2d needs a Gabor image plan");
   return run_gabor2d(plan, x, (int)dtype, y, ws, ws_bytes, stream);
+}
+
+morlet_status gabor2d_backward(morlet_plan_t plan, const void* gW, float* gx, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !plan->image2d || !plan->gabor)
+    return fail(MORLET_ERR_INVALID_ARG, "gabor2d_backward needs a Gabor image plan");
+  return run_gabor2d_backward(plan, gW, gx, ws, ws_bytes, stream);
 }
 
 morlet_status morlet_image_axis_info(morlet_plan_t plan, int32_t axis, int64_t* L, int64_t* n0, double* cos_coef,
@@ -1515,8 +1557,7 @@ void morlet_destroy(morlet_plan_t plan) {
 morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) {
   if (!plan || !bytes) return fail(MORLET_ERR_INVALID_ARG, "null plan or output");
   if (plan->image2d) {
-    if (plan->gabor) return fail(MORLET_ERR_UNSUPPORTED, "no backward pass for Gabor image plans");
-    *bytes = image_bwd_layout(plan).total;
+    *bytes = plan->gabor ? gabor_bwd_layout(plan).total : image_bwd_layout(plan).total;
     return MORLET_OK;
   }
   if (plan->multiply) {

@@ -398,9 +398,10 @@ def test_gabor_plan_errors_and_workspace():
         assert L.gabor2d(hg, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
         assert L.gauss_smooth2d(hp, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
         assert L.morlet_forward(hp, fake, 0, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
-        assert L.gauss_smooth2d_backward(hp, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
-        n = ctypes.c_size_t()
-        assert L.morlet_backward_workspace_size(hp, ctypes.byref(n)) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.gauss_smooth2d_backward(hp, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.gabor2d_backward(hg, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert _abi.morlet_backward_workspace_size(hp) >= 2 * 120 * 90 * 8
+        assert L.gabor2d_backward(hp, fake, fake, fake, 2 * 120 * 90 * 8, None) == _abi.MORLET_ERR_WORKSPACE
         assert L.morlet_plan_set_boundary(hp, 1) == _abi.MORLET_ERR_UNSUPPORTED
         # axis 0 carries the Morlet fit (K_x = 5 coefficients), axis 1 the Gaussian (K_y = 4)
         ix = _abi.morlet_image_axis_info(hp, 0, 5)

@@ -85,3 +85,31 @@ def test_gabor_empty_and_repeat():
     torch.cuda.synchronize()
     assert torch.equal(a, c)
     assert rel_l2(b.cpu().numpy(), a.cpu().numpy()) <= 1e-6
+
+
+@pytest.mark.parametrize("H,W,sx,xi0,Kx,sy,Ky,mode,tile", [
+    (1, 1, 2.0, 6.0, 3, 2.0, 3, "sft", 16),
+    (37, 300, 10.0, 6.0, 5, 3.0, 4, "asft", 16),
+    (257, 129, 5.0, 6.0, 5, 8.0, 4, "sft", 8),
+    (300, 200, 6.0, 4.0, 4, 4.0, 4, "asft", 32),
+])
+def test_gabor_backward(H, W, sx, xi0, Kx, sy, Ky, mode, tile):
+    # dLoss/dx against the oracle's adjoint, and the adjoint identity with both sides on the GPU
+    import paper_2110_11866_amd as M
+    _announce("gabor-backward", H, W, sx, xi0, Kx, sy, Ky, mode, tile)
+    rng = np.random.default_rng(H + 3 * W)
+    img = rng.standard_normal((H, W)).astype(np.float32)
+    g = (rng.standard_normal((H, W)) + 1j * rng.standard_normal((H, W))).astype(np.complex64)
+    xt, gt = torch.from_numpy(img).cuda(), torch.from_numpy(g).cuda()
+    plan = M.Gabor2DPlan(H, W, sx, xi0 / sx, Kx, sy, Ky, mode=mode)
+    plan.set_tile(tile)
+    y = plan.forward(xt).cpu().numpy()
+    gx = plan.backward(gt).cpu().numpy()
+    torch.cuda.synchronize()
+    px, py = _oracle_plans(plan, W, mode)
+    want = O.gabor_2d_adjoint(g.astype(np.complex128), px, py)
+    assert gx.shape == (H, W)
+    assert rel_l2(gx, want) <= 1e-5, rel_l2(gx, want)
+    lhs = float(np.sum((np.conj(g.astype(np.complex128)) * y.astype(np.complex128)).real))
+    rhs = float(np.sum(img.astype(np.float64) * gx.astype(np.float64)))
+    assert abs(lhs - rhs) <= 2e-5 * (np.linalg.norm(g) * np.linalg.norm(y) + 1.0), (lhs, rhs)

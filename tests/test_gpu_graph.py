@@ -166,6 +166,9 @@ def test_graph_newer_backward_paths():
     pi = M.Gauss2DPlan(H, W, 5.0, 7.0, 4, mode="asft")
     gy = rnd(9, H * W)
     _replays(lambda: (pi.backward(gy.view(H, W)),), gy, lambda k: rnd(500 + k, H * W))
+    pg = M.Gabor2DPlan(H, W, 4.0, 1.5, 5, 6.0, 4, mode="asft")
+    gc = rnd(11, 2 * H * W)
+    _replays(lambda: (pg.backward(gc.view(torch.complex64).view(H, W)),), gc, lambda k: rnd(700 + k, 2 * H * W))
     for mode in ("sft", "asft"):
         pd = M.GaussDerivPlan(N, 40.0, 5, 0, order=2, mode=mode)
         gd = rnd(10, N)
