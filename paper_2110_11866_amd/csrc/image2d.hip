@@ -31,15 +31,19 @@ __global__ __launch_bounds__(kTpThreads) void transpose_kernel(const float* in, 
   }
 }
 
-// Complex image to two planes: the same 64 x 64 tiles, one LDS tile per component. Loads are
-// 8-byte words contiguous along a row of Z, stores contiguous along a row of each plane.
+// Complex image to two planes, in tiles of 32 rows x 64 columns (16.6 KB of LDS, so up to eight
+// blocks per CU keep loads in flight). Loads: each wave reads 64 consecutive 8-byte words of a
+// row of Z. Stores: each half wave writes 32 consecutive floats (one 128-byte line) of a row of
+// a plane. The LDS row pitch 65 puts the transposed reads of a half wave in 32 banks.
+constexpr int kCpRows = 32;
+
 __global__ __launch_bounds__(kTpThreads) void transpose_c2p_kernel(const float2* in, float* out, int64_t R, int64_t C,
                                                                      int64_t nbc) {
-  __shared__ float tr[kTpTile][kTpTile + 1], ti[kTpTile][kTpTile + 1];
+  __shared__ float tr[kCpRows][kTpTile + 1], ti[kCpRows][kTpTile + 1];
   const int64_t b = blockIdx.x;
-  const int64_t r0 = (b / nbc) * kTpTile, c0 = (b % nbc) * kTpTile;
+  const int64_t r0 = (b / nbc) * kCpRows, c0 = (b % nbc) * kTpTile;
   const int tx = threadIdx.x & (kTpTile - 1), ty = threadIdx.x / kTpTile;
-  for (int i = ty; i < kTpTile; i += kTpThreads / kTpTile) {
+  for (int i = ty; i < kCpRows; i += kTpThreads / kTpTile) {
     const int64_t r = r0 + i, c = c0 + tx;
     if (r < R && c < C) {
       const float2 v = in[r * C + c];
@@ -49,32 +53,36 @@ __global__ __launch_bounds__(kTpThreads) void transpose_c2p_kernel(const float2*
   }
   __syncthreads();
   const int64_t plane = R * C;
-  for (int i = ty; i < kTpTile; i += kTpThreads / kTpTile) {
-    const int64_t c = c0 + i, r = r0 + tx;
+  const int lane = threadIdx.x & (kCpRows - 1), row = threadIdx.x / kCpRows;   // row: 0..7
+  for (int k = row; k < kTpTile; k += kTpThreads / kCpRows) {
+    const int64_t c = c0 + k, r = r0 + lane;
     if (c < C && r < R) {
-      out[c * R + r] = tr[tx][i];
-      out[plane + c * R + r] = ti[tx][i];
+      out[c * R + r] = tr[lane][k];
+      out[plane + c * R + r] = ti[lane][k];
     }
   }
 }
 
-// Two planes back to the complex image: tile element [i][tx] holds plane[c0 + i][r0 + tx].
+// Two planes back to the complex image, tiles of 32 rows x 64 columns of Z: each half wave
+// reads 32 consecutive floats of a plane row, each wave writes 64 consecutive 8-byte words of
+// a row of Z. LDS [column][row] with pitch 33.
 __global__ __launch_bounds__(kTpThreads) void transpose_p2c_kernel(const float* in, float2* out, int64_t R, int64_t C,
                                                                      int64_t nbc) {
-  __shared__ float tr[kTpTile][kTpTile + 1], ti[kTpTile][kTpTile + 1];
+  __shared__ float tr[kTpTile][kCpRows + 1], ti[kTpTile][kCpRows + 1];
   const int64_t b = blockIdx.x;
-  const int64_t r0 = (b / nbc) * kTpTile, c0 = (b % nbc) * kTpTile;
-  const int tx = threadIdx.x & (kTpTile - 1), ty = threadIdx.x / kTpTile;
+  const int64_t r0 = (b / nbc) * kCpRows, c0 = (b % nbc) * kTpTile;
   const int64_t plane = R * C;
-  for (int i = ty; i < kTpTile; i += kTpThreads / kTpTile) {
-    const int64_t c = c0 + i, r = r0 + tx;
+  const int lane = threadIdx.x & (kCpRows - 1), row = threadIdx.x / kCpRows;
+  for (int k = row; k < kTpTile; k += kTpThreads / kCpRows) {
+    const int64_t c = c0 + k, r = r0 + lane;
     if (c < C && r < R) {
-      tr[i][tx] = in[c * R + r];
-      ti[i][tx] = in[plane + c * R + r];
+      tr[k][lane] = in[c * R + r];
+      ti[k][lane] = in[plane + c * R + r];
     }
   }
   __syncthreads();
-  for (int i = ty; i < kTpTile; i += kTpThreads / kTpTile) {
+  const int tx = threadIdx.x & (kTpTile - 1), ty = threadIdx.x / kTpTile;
+  for (int i = ty; i < kCpRows; i += kTpThreads / kTpTile) {
     const int64_t r = r0 + i, c = c0 + tx;
     if (r < R && c < C) out[r * C + c] = make_float2(tr[tx][i], ti[tx][i]);
   }
@@ -84,7 +92,7 @@ __global__ __launch_bounds__(kTpThreads) void transpose_p2c_kernel(const float* 
 
 hipError_t launch_transpose_c2p(const float2* Z, float* P, int64_t R, int64_t C, hipStream_t s) {
   if (R <= 0 || C <= 0) return hipSuccess;
-  const int64_t nbr = (R + kTpTile - 1) / kTpTile, nbc = (C + kTpTile - 1) / kTpTile;
+  const int64_t nbr = (R + kCpRows - 1) / kCpRows, nbc = (C + kTpTile - 1) / kTpTile;
   if (nbr * nbc > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(transpose_c2p_kernel, dim3((unsigned)(nbr * nbc)), dim3(kTpThreads), 0, s, Z, P, R, C, nbc);
   return hipGetLastError();
@@ -92,7 +100,7 @@ hipError_t launch_transpose_c2p(const float2* Z, float* P, int64_t R, int64_t C,
 
 hipError_t launch_transpose_p2c(const float* P, float2* Z, int64_t R, int64_t C, hipStream_t s) {
   if (R <= 0 || C <= 0) return hipSuccess;
-  const int64_t nbr = (R + kTpTile - 1) / kTpTile, nbc = (C + kTpTile - 1) / kTpTile;
+  const int64_t nbr = (R + kCpRows - 1) / kCpRows, nbc = (C + kTpTile - 1) / kTpTile;
   if (nbr * nbc > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(transpose_p2c_kernel, dim3((unsigned)(nbr * nbc)), dim3(kTpThreads), 0, s, P, Z, R, C, nbc);
   return hipGetLastError();
