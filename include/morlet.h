@@ -175,6 +175,17 @@ morlet_status gauss_smooth2d(morlet_plan_t plan, const void* x, morlet_dtype dty
 morlet_status gauss_smooth2d_backward(morlet_plan_t plan, const float* gy, float* gx, void* ws, size_t ws_bytes,
                                       void* stream);
 
+/* The same backward with the width gradients: gx = dLoss/dx as gauss_smooth2d_backward, and
+ * gparams (device, 2 doubles) = {dLoss/dsigma_y, dLoss/dsigma_x}, each axis's fitted
+ * coefficients differentiated with its window, terms and shift frozen (as for the 1-D plans).
+ * x is the forward's input (device, H x W of dtype). It recomputes the row pass and runs each
+ * axis's adjoint and gradient pass: the columns of S_x x against the transposed cotangent, then
+ * x against the rows' cotangent. Workspace: morlet_backward_workspace_size (zero-filled once).
+ * Errors: a Gabor or non-image plan MORLET_ERR_INVALID_ARG; an empty image or unknown dtype
+ * MORLET_ERR_UNSUPPORTED; otherwise as gauss_smooth2d_backward. */
+morlet_status gauss_smooth2d_grad(morlet_plan_t plan, const void* x, morlet_dtype dtype, const float* gy, float* gx,
+                                  double* gparams, void* ws, size_t ws_bytes, void* stream);
+
 /* Create a plan for the separable 2-D Gabor filter of a real H x W image (row-major, x along
  * a row; Sec. IV filters the lines of an image independently): the Morlet transform of every
  * row (sigma_x, xi in rad/sample, K_x terms, window L_x: the direct method of Sec. III-A, rules

@@ -321,6 +321,20 @@ class Gauss2DPlan(_PlanBase):
         _abi.gauss_smooth2d_backward(self.handle, gy.data_ptr(), gx.data_ptr(), w.data_ptr(), w.numel(), _stream())
         return gx
 
+    def grad(self, x: torch.Tensor, gy: torch.Tensor):
+        """(dLoss/dx float32 H x W, float64 [dLoss/dsigma_y, dLoss/dsigma_x]) for the forward
+        input x and gy = dLoss/dy (float32, H x W); the fitted coefficients are differentiated
+        with each axis's window, terms and shift frozen."""
+        self._check_x(x)
+        if not gy.is_cuda or gy.dtype != torch.float32 or gy.numel() != self.N or not gy.is_contiguous():
+            raise ValueError("gy must be a contiguous float32 device tensor of H x W elements")
+        w = self.workspace(gy.device, backward=True)
+        gx = torch.empty((self.H, self.W), dtype=torch.float32, device=gy.device)
+        gp = torch.empty(2, dtype=torch.float64, device=gy.device)
+        _abi.gauss_smooth2d_grad(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), gy.data_ptr(), gx.data_ptr(),
+                                 gp.data_ptr(), w.data_ptr(), w.numel(), _stream())
+        return gx, gp
+
 
 class Gabor2DPlan(_PlanBase):
     """Separable 2-D Gabor filter of a real H x W image (row-major, x along a row): the Morlet

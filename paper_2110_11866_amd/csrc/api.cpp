@@ -183,8 +183,8 @@ morlet_status init_gauss_rows(morlet_plan_s* p, int B, int64_t len, double sigma
   const mk::Fit f = mk::fit_orders(g, none, p->L, 0, K);
   p->cc = f.cc;
   p->sc.assign(K, 0.0);
-  p->jac.assign(4 * (size_t)K, 0.0);
   p->relrmse = f.relrmse;
+  mk::jacobian(p);   // d a / d sigma, for the parameter gradients of image plans
   p->batched = true;
   p->B = B;
   p->S = 1;
@@ -201,7 +201,7 @@ morlet_status init_gauss_rows(morlet_plan_s* p, int B, int64_t len, double sigma
   sp.n0_asft = default_n0(sigma, p->L);
   sp.cc = f.cc;
   sp.sc.assign(K, 0.0);
-  sp.jac.assign(4 * (size_t)K, 0.0);
+  sp.jac = p->jac;
   sp.relrmse = f.relrmse;
   p->scales = {sp};
   p->n0_asft = sp.n0_asft;
@@ -823,7 +823,7 @@ morlet_status run_backward(morlet_plan_t plan, const void* x, int dtype, const v
 // Workspace: the larger of the two axes' backward workspaces first (its header at offset 0, where
 // every launch on this workspace keeps it), then two H x W float32 buffers.
 struct ImageBwdLayout {
-  size_t axis_bytes, a_off, b_off, total;
+  size_t axis_bytes, a_off, b_off, c_off = 0, gp_off = 0, total;
 };
 ImageBwdLayout image_bwd_layout(morlet_plan_t plan) {
   auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -832,7 +832,9 @@ ImageBwdLayout image_bwd_layout(morlet_plan_t plan) {
   m.axis_bytes = std::max(bwd_layout(plan->axis[0]).total, bwd_layout(plan->axis[1]).total);
   m.a_off = up(m.axis_bytes);
   m.b_off = up(m.a_off + px);
-  m.total = m.b_off + px;
+  m.c_off = up(m.b_off + px);              // third buffer and the per-axis gradients: the
+  m.gp_off = up(m.c_off + px);             // parameter-gradient path only
+  m.total = m.gp_off + 4 * sizeof(double);
   return m;
 }
 
@@ -856,6 +858,48 @@ morlet_status run_image2d_backward(morlet_plan_t plan, const float* gy, float* g
   e = mk::launch_transpose(B, A, W, H, s);                // H x W: the row lines' cotangents
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return run_backward(plan->axis[0], nullptr, 0, A, gx, nullptr, aw, aw_bytes, stream, 1, true);
+}
+
+// dLoss/dx and the width gradients of the 2-D smoothing y = T S_y T S_x x. The column pass sees
+// the columns of y1 = S_x x with cotangent T gy; the row pass sees x with cotangent
+// g1 = T S_y^T T gy. Each axis's batched backward gives its adjoint and its dLoss/dsigma in one
+// call (the plan's coefficients frozen, as for the 1-D plans).
+morlet_status run_image2d_grad(morlet_plan_t plan, const void* x, int dtype, const float* gy, float* gx,
+                               double* gparams, void* ws, size_t ws_bytes, void* stream) {
+  if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  const int64_t H = plan->img_H, W = plan->img_W;
+  if (H == 0 || W == 0) return fail(MORLET_ERR_UNSUPPORTED, "parameter gradients of an empty image are not computed");
+  if (!x || !gy || !gx || !gparams || !ws) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  const ImageBwdLayout m = image_bwd_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
+  if (!plan->axis[0]->d_tab || !plan->axis[1]->d_tab)
+    return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* A = reinterpret_cast<float*>(wsb + m.a_off);
+  float* B = reinterpret_cast<float*>(wsb + m.b_off);
+  float* C = reinterpret_cast<float*>(wsb + m.c_off);
+  double* gp = reinterpret_cast<double*>(wsb + m.gp_off);
+  mk::ScanLaunch a;
+  morlet_status st = make_launch(plan->axis[0], a, ws, mk::kVarForward, 0, dtype);
+  if (st != MORLET_OK) return st;
+  a.x = x;
+  a.dtype = dtype;
+  a.out = A;                                                   // y1 = S_x x (H x W)
+  hipError_t e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e == hipSuccess) e = mk::launch_transpose(A, B, H, W, s);  // its columns (W x H)
+  if (e == hipSuccess) e = mk::launch_transpose(gy, C, H, W, s); // their cotangents (W x H)
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  st = run_backward(plan->axis[1], B, 0, C, A, gp, ws, m.axis_bytes, stream, 1, true);
+  if (st != MORLET_OK) return st;
+  e = mk::launch_transpose(A, B, W, H, s);                       // g1 (H x W)
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  st = run_backward(plan->axis[0], x, dtype, B, gx, gp + 2, ws, m.axis_bytes, stream, 1, true);
+  if (st != MORLET_OK) return st;
+  e = hipMemcpyAsync(gparams, gp, sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(gparams + 1, gp + 2, sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("copy failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
 }
 
 // Backward of the 2-D Gabor filter for a real loss (gW = dLoss/dRe y + i dLoss/dIm y, H x W
@@ -1184,6 +1228,13 @@ morlet_status gabor2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, voi
                       void* stream) {
   if (!plan || !plan->image2d || !plan->gabor) return fail(MORLET_ERR_INVALID_ARG, "gabor2d needs a Gabor image plan");
   return run_gabor2d(plan, x, (int)dtype, y, ws, ws_bytes, stream);
+}
+
+morlet_status gauss_smooth2d_grad(morlet_plan_t plan, const void* x, morlet_dtype dtype, const float* gy, float* gx,
+                                  double* gparams, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !plan->image2d || plan->gabor)
+    return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d_grad needs a Gaussian image plan");
+  return run_image2d_grad(plan, x, (int)dtype, gy, gx, gparams, ws, ws_bytes, stream);
 }
 
 morlet_status gabor2d_backward(morlet_plan_t plan, const void* gW, float* gx, void* ws, size_t ws_bytes, void* stream) {

@@ -94,3 +94,33 @@ def test_image_backward(H, W, sy, sx, K, mode):
     lhs, rhs = float(np.sum(g64 * y0)), float(np.sum(img.astype(np.float64) * gx))
     assert abs(lhs - rhs) <= 2e-5 * (abs(lhs) + np.sqrt(H * W)), (lhs, rhs)
     assert np.array_equal(y0, y1)
+
+
+@pytest.mark.parametrize("H,W,sy,sx,K,mode", [(1, 1, 2.0, 2.0, 3, "sft"), (50, 300, 3.0, 10.0, 4, "asft"),
+                                              (257, 129, 8.0, 5.0, 5, "sft"), (300, 200, 6.0, 4.0, 4, "asft")])
+def test_image_width_gradients(H, W, sy, sx, K, mode):
+    # dLoss/dsigma_y: the column lines of y1 = S_x x against the columns of gy; dLoss/dsigma_x:
+    # the rows of x against the rows of g1 = T S_y^T T gy; each a sum over lines of the oracle's
+    # frozen-plan gradient. gx as the plain backward, bitwise
+    import paper_2110_11866_amd as M
+    _announce("image-grad", H, W, sy, sx, K, mode)
+    rng = np.random.default_rng(3 * H + W)
+    img = rng.standard_normal((H, W)).astype(np.float32)
+    gy = rng.standard_normal((H, W)).astype(np.float32)
+    xt, gt = torch.from_numpy(img).cuda(), torch.from_numpy(gy).cuda()
+    plan = M.Gauss2DPlan(H, W, sy, sx, K, mode=mode)
+    gx, gp = plan.grad(xt, gt)
+    gx0 = plan.backward(gt)
+    gx, gp, gx0 = gx.cpu().numpy(), gp.cpu().numpy(), gx0.cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(gx, gx0)
+    ix, iy = plan.axis_info(0), plan.axis_info(1)
+    px = O.plan_gauss(sx, K, ix["L"], mode=mode, n0=ix["n0"] if mode == "asft" else None)
+    py = O.plan_gauss(sy, K, iy["L"], mode=mode, n0=iy["n0"] if mode == "asft" else None)
+    x64, g64 = img.astype(np.float64), gy.astype(np.float64)
+    y1 = np.stack([O.forward(x64[r], px) for r in range(H)])
+    want_y = sum(O.param_grads(y1[:, c], g64[:, c], py)[0] for c in range(W))
+    g1 = np.stack([O.adjoint(g64[:, c], py) for c in range(W)], axis=1)
+    want_x = sum(O.param_grads(x64[r], g1[r], px)[0] for r in range(H))
+    for got, want in ((gp[0], want_y), (gp[1], want_x)):
+        assert abs(got - want) <= 1e-5 * abs(want) + 1e-9, (gp, want_y, want_x)
