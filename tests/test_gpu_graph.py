@@ -166,6 +166,8 @@ def test_graph_newer_backward_paths():
     pi = M.Gauss2DPlan(H, W, 5.0, 7.0, 4, mode="asft")
     gy = rnd(9, H * W)
     _replays(lambda: (pi.backward(gy.view(H, W)),), gy, lambda k: rnd(500 + k, H * W))
+    xi_ = rnd(12, H * W)
+    _replays(lambda: pi.grad(xi_.view(H, W), gy.view(H, W)), gy, lambda k: rnd(800 + k, H * W))
     pg = M.Gabor2DPlan(H, W, 4.0, 1.5, 5, 6.0, 4, mode="asft")
     gc = rnd(11, 2 * H * W)
     _replays(lambda: (pg.backward(gc.view(torch.complex64).view(H, W)),), gc, lambda k: rnd(700 + k, 2 * H * W))
