@@ -211,11 +211,22 @@ morlet_status gabor2d(morlet_plan_t plan, const void* x, morlet_dtype dtype, voi
  * complex64, H x W) -> gx = dLoss/dx (device float32, H x W, overwritten). The transposes of
  * the two passes in reverse order: gW into its real and imaginary planes, the Gaussian adjoint
  * over the 2W column lines, back to complex64, the batched Morlet adjoint over the H rows
- * (per-line adjoints as morlet_backward). No parameter gradients. Workspace:
+ * (per-line adjoints as morlet_backward); gabor2d_grad adds the parameter gradients. Workspace:
  * morlet_backward_workspace_size (zero-filled once; not the forward's). Errors: a non-Gabor
  * plan is MORLET_ERR_INVALID_ARG; a short workspace MORLET_ERR_WORKSPACE. */
 morlet_status gabor2d_backward(morlet_plan_t plan, const void* gW, float* gx, void* ws, size_t ws_bytes,
                                void* stream);
+
+/* The same backward with the parameter gradients: gx as gabor2d_backward, and gparams (device,
+ * 3 doubles) = {dLoss/dsigma_y, dLoss/dsigma_x, dLoss/dxi}, each axis's fitted coefficients
+ * differentiated with its window, terms and shift frozen (as for the 1-D plans). x is the
+ * forward's input (device, H x W of dtype). It recomputes the row pass, runs the column pass's
+ * adjoint and gradient over the 2W planar column lines, then the row pass's over the H rows.
+ * Workspace: morlet_backward_workspace_size (zero-filled once). Errors: a non-Gabor plan
+ * MORLET_ERR_INVALID_ARG; an empty image or unknown dtype MORLET_ERR_UNSUPPORTED; otherwise as
+ * gabor2d_backward. */
+morlet_status gabor2d_grad(morlet_plan_t plan, const void* x, morlet_dtype dtype, const void* gW, float* gx,
+                           double* gparams, void* ws, size_t ws_bytes, void* stream);
 
 /* Per-axis parameters of an image plan: axis 0 filters along x (the rows), axis 1 along y.
  * L: window half width; n0: ASFT shift in use (0 for SFT); cos_coef[K of that axis]: a_p (the

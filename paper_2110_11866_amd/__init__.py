@@ -387,6 +387,20 @@ class Gabor2DPlan(_PlanBase):
         _abi.gabor2d_backward(self.handle, gW.data_ptr(), gx.data_ptr(), w.data_ptr(), w.numel(), _stream())
         return gx
 
+    def grad(self, x: torch.Tensor, gW: torch.Tensor):
+        """(dLoss/dx float32 H x W, float64 [dLoss/dsigma_y, dLoss/dsigma_x, dLoss/dxi]) for the
+        forward input x and gW (complex64, H x W), each axis's plan frozen."""
+        if not x.is_cuda or x.numel() != self.N or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous device tensor of {self.H} x {self.W} pixels")
+        if not gW.is_cuda or gW.dtype != torch.complex64 or gW.numel() != self.N or not gW.is_contiguous():
+            raise ValueError("gW must be a contiguous complex64 device tensor of H x W elements")
+        w = self.workspace(gW.device, backward=True)
+        gx = torch.empty((self.H, self.W), dtype=torch.float32, device=gW.device)
+        gp = torch.empty(3, dtype=torch.float64, device=gW.device)
+        _abi.gabor2d_grad(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), gW.data_ptr(), gx.data_ptr(),
+                          gp.data_ptr(), w.data_ptr(), w.numel(), _stream())
+        return gx, gp
+
 
 class ScalogramPlan(_PlanBase):
     """Batched ragged scalogram: B packed signals x S scales, one persistent launch.

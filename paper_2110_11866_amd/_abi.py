@@ -38,6 +38,7 @@ SIGNATURES = {
     "gabor2d": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _sz, _vp]),
     "gabor2d_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "gauss_smooth2d_grad": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "gabor2d_grad": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "gauss_smooth2d_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "morlet_image_axis_info": (ctypes.c_int, [_vp, _i32, _P(_i64), _P(_i64), _P(_dbl), _P(_dbl)]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
@@ -141,6 +142,11 @@ def gabor2d(plan: int, x_ptr: int, dtype: int, y_ptr: int, ws_ptr: int, ws_bytes
 def gauss_smooth2d_grad(plan: int, x_ptr: int, dtype: int, gy_ptr: int, gx_ptr: int, gp_ptr: int, ws_ptr: int,
                         ws_bytes: int, stream: int) -> None:
     check(lib().gauss_smooth2d_grad(plan, x_ptr, dtype, gy_ptr, gx_ptr, gp_ptr, ws_ptr, ws_bytes, stream))
+
+
+def gabor2d_grad(plan: int, x_ptr: int, dtype: int, gW_ptr: int, gx_ptr: int, gp_ptr: int, ws_ptr: int,
+                 ws_bytes: int, stream: int) -> None:
+    check(lib().gabor2d_grad(plan, x_ptr, dtype, gW_ptr, gx_ptr, gp_ptr, ws_ptr, ws_bytes, stream))
 
 
 def gabor2d_backward(plan: int, gW_ptr: int, gx_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:

@@ -914,7 +914,9 @@ ImageBwdLayout gabor_bwd_layout(morlet_plan_t plan) {
   m.axis_bytes = std::max(bwd_layout(plan->axis[0]).total, bwd_layout(plan->axis[1]).total);
   m.a_off = up(m.axis_bytes);
   m.b_off = up(m.a_off + px);
-  m.total = m.b_off + px;
+  m.c_off = up(m.b_off + px);              // third buffer and the per-axis gradients: the
+  m.gp_off = up(m.c_off + px);             // parameter-gradient path only
+  m.total = m.gp_off + 4 * sizeof(double);
   return m;
 }
 
@@ -936,6 +938,48 @@ morlet_status run_gabor2d_backward(morlet_plan_t plan, const void* gW, float* gx
   e = mk::launch_transpose_p2c(A, reinterpret_cast<float2*>(B), H, W, s);   // the rows' complex cotangent
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return run_backward(plan->axis[0], nullptr, 0, B, gx, nullptr, ws, m.axis_bytes, stream, 0, true);
+}
+
+// dLoss/dx with the parameter gradients of the 2-D Gabor filter: the row pass recomputed, its
+// planes against the cotangent's planes for the column pass (dLoss/dsigma_y over the 2W
+// column lines of one scale), then x against the rows' complex cotangent for the row pass
+// (dLoss/dsigma_x, dLoss/dxi). gparams = {dsigma_y, dsigma_x, dxi}.
+morlet_status run_gabor2d_grad(morlet_plan_t plan, const void* x, int dtype, const void* gW, float* gx,
+                               double* gparams, void* ws, size_t ws_bytes, void* stream) {
+  if (dtype < 0 || dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  const int64_t H = plan->img_H, W = plan->img_W;
+  if (H == 0 || W == 0) return fail(MORLET_ERR_UNSUPPORTED, "parameter gradients of an empty image are not computed");
+  if (!x || !gW || !gx || !gparams || !ws) return fail(MORLET_ERR_INVALID_ARG, "null pointer");
+  const ImageBwdLayout m = gabor_bwd_layout(plan);
+  if (ws_bytes < m.total) return fail(MORLET_ERR_WORKSPACE, "workspace too small for the backward pass");
+  if (!plan->axis[0]->d_tab || !plan->axis[1]->d_tab)
+    return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  unsigned char* wsb = static_cast<unsigned char*>(ws);
+  float* A = reinterpret_cast<float*>(wsb + m.a_off);
+  float* B = reinterpret_cast<float*>(wsb + m.b_off);
+  float* C = reinterpret_cast<float*>(wsb + m.c_off);
+  double* gp = reinterpret_cast<double*>(wsb + m.gp_off);
+  mk::ScanLaunch a;
+  morlet_status st = make_launch(plan->axis[0], a, ws, mk::kVarForward, 0, dtype);
+  if (st != MORLET_OK) return st;
+  a.x = x;
+  a.dtype = dtype;
+  a.out = A;                                                            // y1 = rows' transform
+  hipError_t e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e == hipSuccess) e = mk::launch_transpose_c2p(reinterpret_cast<const float2*>(A), B, H, W, s);
+  if (e == hipSuccess) e = mk::launch_transpose_c2p(static_cast<const float2*>(gW), C, H, W, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  st = run_backward(plan->axis[1], B, 0, C, A, gp, ws, m.axis_bytes, stream, 1, true);
+  if (st != MORLET_OK) return st;
+  e = mk::launch_transpose_p2c(A, reinterpret_cast<float2*>(B), H, W, s);   // the rows' cotangent
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  st = run_backward(plan->axis[0], x, dtype, B, gx, gp + 2, ws, m.axis_bytes, stream, 0, true);
+  if (st != MORLET_OK) return st;
+  e = hipMemcpyAsync(gparams, gp, sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(gparams + 1, gp + 2, 2 * sizeof(double), hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("copy failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
 }
 }  // namespace
 
@@ -1235,6 +1279,13 @@ morlet_status gauss_smooth2d_grad(morlet_plan_t plan, const void* x, morlet_dtyp
   if (!plan || !plan->image2d || plan->gabor)
     return fail(MORLET_ERR_INVALID_ARG, "gauss_smooth2d_grad needs a Gaussian image plan");
   return run_image2d_grad(plan, x, (int)dtype, gy, gx, gparams, ws, ws_bytes, stream);
+}
+
+morlet_status gabor2d_grad(morlet_plan_t plan, const void* x, morlet_dtype dtype, const void* gW, float* gx,
+                           double* gparams, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !plan->image2d || !plan->gabor)
+    return fail(MORLET_ERR_INVALID_ARG, "gabor2d_grad needs a Gabor image plan");
+  return run_gabor2d_grad(plan, x, (int)dtype, gW, gx, gparams, ws, ws_bytes, stream);
 }
 
 morlet_status gabor2d_backward(morlet_plan_t plan, const void* gW, float* gx, void* ws, size_t ws_bytes, void* stream) {

@@ -401,6 +401,9 @@ def test_gabor_plan_errors_and_workspace():
         assert L.gauss_smooth2d_backward(hp, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
         assert L.gabor2d_backward(hg, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
         assert L.gauss_smooth2d_grad(hp, fake, 0, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.gabor2d_grad(hg, fake, 0, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.gabor2d_grad(hp, fake, 3, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
+        assert L.gabor2d_grad(hp, fake, 0, fake, fake, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE
         assert L.gauss_smooth2d_grad(hg, fake, 3, fake, fake, fake, fake, 1 << 30, None) == _abi.MORLET_ERR_UNSUPPORTED
         assert L.gauss_smooth2d_grad(hg, fake, 0, fake, fake, None, fake, 1 << 30, None) == _abi.MORLET_ERR_INVALID_ARG
         assert L.gauss_smooth2d_grad(hg, fake, 0, fake, fake, fake, fake, 100, None) == _abi.MORLET_ERR_WORKSPACE

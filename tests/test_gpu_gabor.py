@@ -113,3 +113,36 @@ def test_gabor_backward(H, W, sx, xi0, Kx, sy, Ky, mode, tile):
     lhs = float(np.sum((np.conj(g.astype(np.complex128)) * y.astype(np.complex128)).real))
     rhs = float(np.sum(img.astype(np.float64) * gx.astype(np.float64)))
     assert abs(lhs - rhs) <= 2e-5 * (np.linalg.norm(g) * np.linalg.norm(y) + 1.0), (lhs, rhs)
+
+
+@pytest.mark.parametrize("H,W,sx,xi0,Kx,sy,Ky,mode", [
+    (1, 1, 2.0, 6.0, 3, 2.0, 3, "sft"),
+    (37, 300, 10.0, 6.0, 5, 3.0, 4, "asft"),
+    (257, 129, 5.0, 6.0, 5, 8.0, 4, "sft"),
+    (300, 200, 6.0, 4.0, 4, 4.0, 4, "asft"),
+])
+def test_gabor_parameter_gradients(H, W, sx, xi0, Kx, sy, Ky, mode):
+    # dsigma_y: the column lines of both parts of the row transform against the cotangent's;
+    # dsigma_x, dxi: the rows of x against the rows' complex cotangent; each a sum over lines of
+    # the oracle's frozen-plan gradient. gx as the plain backward, bitwise
+    import paper_2110_11866_amd as M
+    _announce("gabor-grad", H, W, sx, xi0, Kx, sy, Ky, mode)
+    rng = np.random.default_rng(7 * H + W)
+    img = rng.standard_normal((H, W)).astype(np.float32)
+    g = (rng.standard_normal((H, W)) + 1j * rng.standard_normal((H, W))).astype(np.complex64)
+    xt, gt = torch.from_numpy(img).cuda(), torch.from_numpy(g).cuda()
+    plan = M.Gabor2DPlan(H, W, sx, xi0 / sx, Kx, sy, Ky, mode=mode)
+    gx, gp = plan.grad(xt, gt)
+    gx0 = plan.backward(gt)
+    gx, gp, gx0 = gx.cpu().numpy(), gp.cpu().numpy(), gx0.cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(gx, gx0)
+    px, py = _oracle_plans(plan, W, mode)
+    x64, g64 = img.astype(np.float64), g.astype(np.complex128)
+    y1 = np.stack([O.forward(x64[r], px) for r in range(H)])
+    want_y = sum(O.param_grads(y1[:, c].real, g64[:, c].real, py)[0] + O.param_grads(y1[:, c].imag, g64[:, c].imag, py)[0]
+                 for c in range(W))
+    g1 = np.stack([O.adjoint(g64[:, c].real, py) + 1j * O.adjoint(g64[:, c].imag, py) for c in range(W)], axis=1)
+    want_x = sum(O.param_grads(x64[r], g1[r], px) for r in range(H))
+    want = np.array([want_y, want_x[0], want_x[1]])
+    assert np.all(np.abs(gp - want) <= 1e-5 * np.abs(want) + 1e-9), (gp, want)
