@@ -171,6 +171,8 @@ def test_graph_newer_backward_paths():
     pg = M.Gabor2DPlan(H, W, 4.0, 1.5, 5, 6.0, 4, mode="asft")
     gc = rnd(11, 2 * H * W)
     _replays(lambda: (pg.backward(gc.view(torch.complex64).view(H, W)),), gc, lambda k: rnd(700 + k, 2 * H * W))
+    _replays(lambda: pg.grad(xi_.view(H, W), gc.view(torch.complex64).view(H, W)), gc,
+             lambda k: rnd(900 + k, 2 * H * W))
     for mode in ("sft", "asft"):
         pd = M.GaussDerivPlan(N, 40.0, 5, 0, order=2, mode=mode)
         gd = rnd(10, N)
