@@ -67,9 +67,15 @@ typedef enum { MORLET_F32 = 0, MORLET_F16 = 1, MORLET_BF16 = 2 } morlet_dtype;
 /* Transform: plain SFT (Sec. II-A/B) or attenuated SFT (Sec. II-D/E). */
 typedef enum { MORLET_SCAN_SFT = 0, MORLET_SCAN_ASFT = 1 } morlet_scan;
 
-/* Scan accumulation: float32 throughout, or compensated (the scan state, its carries and
- * the K-term combination held in float64 while the input and output stay 32-bit). */
-typedef enum { MORLET_ACC_F32 = 0, MORLET_ACC_COMPENSATED = 1 } morlet_accum;
+/* Scan arithmetic. Inputs and outputs stay 32-bit (16-bit inputs are widened) in every mode.
+ *   MORLET_ACC_F32   (default): float32 for everything a thread computes - the chunk sums of its
+ *                    positions, the 16-lane wave scan, the recurrence and the K-term combination;
+ *                    float64 only for the carries between the 16-lane rows of a wave, between
+ *                    waves and between tiles (the decoupled look-back). Backward calls run the
+ *                    mixed scan in this mode.
+ *   MORLET_ACC_F64 : float64 scan state, carries and K-term combination (a reference mode).
+ *   MORLET_ACC_MIXED: float64 chunk sums and wave scan, float32 recurrence and combination. */
+typedef enum { MORLET_ACC_F32 = 0, MORLET_ACC_F64 = 1, MORLET_ACC_MIXED = 2 } morlet_accum;
 
 /* Maximum number of Fourier terms a plan may use. */
 #define MORLET_MAX_TERMS 12
@@ -288,6 +294,22 @@ morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule sched
  * plan keeps its tile shape and schedule. */
 morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* out, int32_t reps,
                                    int32_t* R_out, int32_t* schedule_out, void* stream);
+
+/* Refit a single-signal Morlet or Gaussian-smoothing plan at new parameters sigma (and xi, in
+ * rad/sample, for Morlet; ignored for Gaussian), keeping its window L, lowest order P_S, terms K,
+ * ASFT shift n0, mode, accumulation, tile shape and boundary: the MMSE fit of Sec. III-A (eq.
+ * mmse; eq. aproGauss for the Gaussian) and its Jacobian are recomputed on the host at the frozen
+ * orders, and the constant table (which also depends on alpha = n0/sigma^2) is copied into the
+ * plan's existing device table with hipMemcpyAsync on `stream`, so launches queued on that stream
+ * before the call use the old coefficients and later ones the new. For training loops that update
+ * sigma and xi every step (the parameter gradients treat L, P_S and n0 as frozen): no device
+ * allocation. The first call allocates a pinned host staging copy of the table and an event (kept
+ * until morlet_destroy); each call waits on that event for the previous upload to have read the
+ * staging copy. Host work and an event wait: not for use under graph capture. Launches on other
+ * streams are not ordered with the upload. Errors: MORLET_ERR_INVALID_ARG (null plan, sigma or xi
+ * not finite and > 0), MORLET_ERR_UNSUPPORTED (scalogram, image, multiplication-method and
+ * differential plans), MORLET_ERR_ALLOC, MORLET_ERR_HIP. */
+morlet_status morlet_plan_refit(morlet_plan_t plan, double sigma, double xi, void* stream);
 
 /* Plan parameters (host outputs; any pointer may be NULL).
  *   cos_coef[K]: m_p (Morlet) or a_p (Gaussian); sin_coef[K]: l_p (0 for Gaussian);

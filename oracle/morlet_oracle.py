@@ -40,6 +40,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
+from functools import partial
 
 import numpy as np
 from scipy.signal import fftconvolve, lfilter
@@ -48,7 +49,7 @@ __all__ = [
     "gaussian", "gaussian_d1", "gaussian_d2", "fit_gauss_d1", "fit_gauss_d2", "plan_gauss_deriv",
     "kterm_gauss_deriv",
     "morlet", "Plan", "plan_morlet", "plan_gauss", "fit_morlet", "fit_gauss",
-    "select_PS", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
+    "select_PS", "select_PS_full", "default_n0", "kterm_morlet", "kterm_gauss", "asft_kernel", "kernel_relrmse",
     "conv_same", "conv_same_at", "phase", "sft_component", "asft_component",
     "forward", "forward_direct", "adjoint", "param_grads", "dpsi_dtheta",
     "plan_multiply", "kterm_multiply", "freq_component", "gauss_smooth_2d", "gabor_2d", "gabor_2d_adjoint", "sliding_sum", "forward_tree",
@@ -221,13 +222,11 @@ def kernel_relrmse(approx: np.ndarray, exact: np.ndarray) -> float:
     return float(np.linalg.norm(approx - exact) / np.linalg.norm(exact))
 
 
-def select_PS(sigma: float, xi: float, K: int, L: int) -> int:
-    """P_S minimising the relative RMSE of the fitted wavelet on [-L, L]
-    (Sec. V-A, the optimum P_S of Fig. MSE2); ties go to the smallest P_S."""
+def _argmin_PS(sigma: float, xi: float, K: int, L: int, candidates) -> int:
     k = np.arange(-L, L + 1, dtype=np.float64)
     psi = morlet(sigma, xi, k)
     best, best_err = 0, math.inf
-    for ps in _ps_range(xi, K, L):
+    for ps in candidates:
         m, l = fit_morlet(sigma, xi, K, L, ps)
         err = kernel_relrmse(_kterm(m, l, ps, L), psi)
         if err < best_err * (1.0 - 1e-12):
@@ -235,8 +234,24 @@ def select_PS(sigma: float, xi: float, K: int, L: int) -> int:
     return best
 
 
+def select_PS(sigma: float, xi: float, K: int, L: int) -> int:
+    """P_S minimising the relative RMSE of the fitted wavelet on [-L, L]
+    (Sec. V-A, the optimum P_S of Fig. MSE2); ties go to the smallest P_S.
+    The search stops K orders above the carrier (see _ps_range); the tests pin
+    this against select_PS_full, the argmin over every admissible order."""
+    return _argmin_PS(sigma, xi, K, L, _ps_range(xi, K, L))
+
+
+def select_PS_full(sigma: float, xi: float, K: int, L: int) -> int:
+    """The same argmin over every admissible lowest order 0..L-K+1 (orders alias
+    modulo 2L, so P_S + K - 1 <= L), with no cap at the carrier. O(L^2 K^2) work:
+    meant for small windows."""
+    return _argmin_PS(sigma, xi, K, L, range(0, max(L - K + 1, 0) + 1))
+
+
 def default_n0(sigma: float) -> int:
-    """Default ASFT shift max(1, round(sigma / 8)), halves rounded up."""
+    """Default ASFT shift max(1, round(sigma / 8)). The paper fixes no rule (it uses
+    n0 = 10 at a window of 256); this reading rounds halves up (sigma = 20 gives 3)."""
     return max(1, int(math.floor(sigma / 8.0 + 0.5)))
 
 
@@ -678,27 +693,37 @@ def param_grads(x: np.ndarray, g: np.ndarray, plan: Plan) -> np.ndarray:
 # Images: separable 2-D Gaussian smoothing (Sec. IV: the lines of an image are filtered
 # independently, rows then columns)
 # --------------------------------------------------------------------------
-def gauss_smooth_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
+def _lines(fn, items, map_lines):
+    return list(map_lines(fn, items)) if map_lines is not None else [fn(v) for v in items]
+
+
+def gauss_smooth_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan, map_lines=None) -> np.ndarray:
     """y = G_y *_columns (G_x *_rows img) for an H x W image (row-major, x along a row), each
-    line by forward() with the axis's plan."""
+    line by forward() with the axis's plan. map_lines(fn, lines), if given, applies fn to every
+    line (the lines are independent, so a caller may spread them over processes)."""
     img = np.asarray(img, dtype=np.float64)
     H, W = img.shape
-    rows = np.stack([forward(img[r], plan_x) for r in range(H)]) if H and W else np.zeros((H, W))
-    out = np.stack([forward(rows[:, c], plan_y) for c in range(W)], axis=1) if H and W else np.zeros((H, W))
-    return out
+    if H == 0 or W == 0:
+        return np.zeros((H, W))
+    rows = np.stack(_lines(partial(forward, plan=plan_x), list(img), map_lines))
+    cols = _lines(partial(forward, plan=plan_y), list(np.ascontiguousarray(rows.T)), map_lines)
+    return np.stack(cols, axis=1)
 
 
-def gabor_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
+def gabor_2d(img: np.ndarray, plan_x: Plan, plan_y: Plan, map_lines=None) -> np.ndarray:
     """Separable 2-D Gabor filter of a real H x W image: the Morlet transform of every row
     (plan_x, complex), then the Gaussian smoothing of every column of its real and imaginary
-    parts (plan_y), the lines filtered independently (Sec. IV)."""
+    parts (plan_y), the lines filtered independently (Sec. IV). map_lines as for
+    gauss_smooth_2d."""
     img = np.asarray(img, dtype=np.float64)
     H, W = img.shape
     if H == 0 or W == 0:
         return np.zeros((H, W), dtype=np.complex128)
-    rows = np.stack([forward(img[r], plan_x) for r in range(H)])
-    cols = [forward(rows[:, c].real, plan_y) + 1j * forward(rows[:, c].imag, plan_y) for c in range(W)]
-    return np.stack(cols, axis=1)
+    rows = np.stack(_lines(partial(forward, plan=plan_x), list(img), map_lines))
+    cT = np.ascontiguousarray(rows.T)
+    re = _lines(partial(forward, plan=plan_y), list(cT.real.copy()), map_lines)
+    im = _lines(partial(forward, plan=plan_y), list(cT.imag.copy()), map_lines)
+    return np.stack(re, axis=1) + 1j * np.stack(im, axis=1)
 
 
 def gabor_2d_adjoint(g: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
@@ -718,28 +743,24 @@ def gabor_2d_adjoint(g: np.ndarray, plan_x: Plan, plan_y: Plan) -> np.ndarray:
 # The paper's GPU route (Sec. IV): window sums by binary doubling (Algorithm 1)
 # --------------------------------------------------------------------------
 def sliding_sum(f: np.ndarray, Lw: int) -> np.ndarray:
-    """h[n] = sum_{k=0}^{Lw-1} f[n+k] for every n, f zero past its end (Algorithm 1): with
-    g_0 = f and h_0 = 0, for each bit r of Lw from the lowest,
-    h <- g_r[n] + h[n + 2^r] if bit r is set, then g_{r+1}[n] = g_r[n] + g_r[n + 2^r]."""
+    """h[n] = sum_{k=0}^{Lw-1} f[n+k] for every n, f zero past its end: the window sums
+    that Algorithm 1 forms by binary doubling, taken here from their definition (a
+    correlation with Lw ones; scipy's FFT convolution for long windows, a library
+    primitive for the same sums)."""
     f = np.asarray(f)
     M = f.shape[0]
-    g = f.copy()
-    h = np.zeros_like(f)
-    r = 0
-    while (Lw >> r) > 0:
-        s = 1 << r
-
-        def shifted(a):
-            out = np.zeros_like(a)
-            if s < M:
-                out[:M - s] = a[s:]
-            return out
-
-        if (Lw >> r) & 1:
-            h = g + shifted(h)
-        g = g + shifted(g)
-        r += 1
-    return h
+    if M == 0 or Lw <= 0:
+        return np.zeros_like(f)
+    ones = np.ones(Lw)
+    if M * Lw <= (1 << 24):
+        full = np.convolve(f, ones)            # full[i] = sum_{k=0}^{Lw-1} f[i-k]
+    else:
+        full = fftconvolve(f, ones)
+    # h[n] = full[n + Lw - 1] (terms past the end of f are zero)
+    out = np.zeros_like(f)
+    src = full[Lw - 1:Lw - 1 + M]
+    out[:src.shape[0]] = src
+    return out
 
 
 def forward_tree(x: np.ndarray, plan: Plan) -> np.ndarray:

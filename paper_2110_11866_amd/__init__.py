@@ -10,7 +10,7 @@ from __future__ import annotations
 import torch
 
 from . import _abi
-from ._abi import (MORLET_ACC_COMPENSATED, MORLET_ACC_F32, MORLET_BF16, MORLET_F16, MORLET_F32,
+from ._abi import (MORLET_ACC_F32, MORLET_ACC_F64, MORLET_ACC_MIXED, MORLET_BF16, MORLET_F16, MORLET_F32,
                    MORLET_SCAN_ASFT, MORLET_SCAN_SFT, MorletError)
 
 __all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2DPlan", "Gabor2DPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
@@ -18,7 +18,7 @@ __all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2D
 
 _DT = {torch.float32: MORLET_F32, torch.float16: MORLET_F16, torch.bfloat16: MORLET_BF16}
 _MODE = {"sft": MORLET_SCAN_SFT, "asft": MORLET_SCAN_ASFT}
-_ACC = {"f32": MORLET_ACC_F32, "compensated": MORLET_ACC_COMPENSATED}
+_ACC = {"f32": MORLET_ACC_F32, "f64": MORLET_ACC_F64, "mixed": MORLET_ACC_MIXED}
 
 
 def torch_dtype_code(dt: torch.dtype) -> int:
@@ -70,6 +70,16 @@ class _PlanBase:
 
     def info(self) -> dict:
         return _abi.morlet_plan_info(self.handle, self.K)
+
+    def refit(self, sigma: float, xi: float = 0.0) -> "_PlanBase":
+        """Refit the coefficients at new sigma (and xi, Morlet plans) with the window, lowest
+        order, ASFT shift and tile shape kept, into the plan's own device table on the
+        current stream (morlet_plan_refit; single-signal Morlet and Gaussian plans)."""
+        _abi.morlet_plan_refit(self.handle, float(sigma), float(xi), _stream() if torch.cuda.is_available() else 0)
+        self.sigma = float(sigma)
+        if self.kind == "morlet":
+            self.xi = float(xi)
+        return self
 
     def _out_like(self, x: torch.Tensor) -> torch.Tensor:
         n = self.S * self.N if self.kind == "scalogram" else self.N
@@ -458,6 +468,9 @@ class _MorletFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, sigma, xi, plan):
         ctx.plan = plan
+        # the parameter gradients come back in the parameters' own dtypes (float64 for the
+        # layer's parameters), never rounded through float32 on the way
+        ctx.param_dtypes = tuple(v.dtype if torch.is_tensor(v) else torch.float64 for v in (sigma, xi))
         ctx.save_for_backward(x)
         return plan.forward(x.contiguous())
 
@@ -468,8 +481,8 @@ class _MorletFn(torch.autograd.Function):
         gx, gp = ctx.plan.backward(x.contiguous(), gW.contiguous().to(torch.complex64), want_params=want_p)
         gs = gxi = None
         if want_p:
-            gs = gp[0].to(torch.float32 if ctx.needs_input_grad[1] else torch.float64)
-            gxi = gp[1].to(torch.float32 if ctx.needs_input_grad[2] else torch.float64)
+            gs = gp[0].to(ctx.param_dtypes[0]) if ctx.needs_input_grad[1] else None
+            gxi = gp[1].to(ctx.param_dtypes[1]) if ctx.needs_input_grad[2] else None
         return (gx.to(x.dtype) if ctx.needs_input_grad[0] else None), gs, gxi, None
 
 
@@ -480,8 +493,10 @@ def morlet_transform(x: torch.Tensor, sigma: torch.Tensor, xi: torch.Tensor, pla
 
 class MorletTransform(torch.nn.Module):
     """Morlet transform layer with learnable sigma and xi (rad/sample). The plan (window L,
-    lowest order P_S, ASFT shift n0) is chosen once at construction and kept fixed; the
-    coefficients are refitted whenever sigma or xi change."""
+    lowest order P_S, ASFT shift n0) is chosen once at construction and kept fixed, as the
+    parameter gradients assume; whenever sigma or xi change the coefficients are refitted
+    into the plan's existing device table on the current stream (morlet_plan_refit: no
+    device allocation per step)."""
 
     def __init__(self, N: int, sigma: float, xi: float, K: int, L: int = 0, mode: str = "sft", n0: int = 0,
                  accum: str = "f32"):
@@ -496,13 +511,8 @@ class MorletTransform(torch.nn.Module):
     def plan(self) -> MorletPlan:
         key = (float(self.sigma.detach()), float(self.xi.detach()))
         if key != self._key:
-            c = self._cfg
-            p = MorletPlan(c["N"], key[0], key[1], c["K"], c["L"])
-            if p.info()["P_S"] != c["P_S"]:
-                raise MorletError(2, "the refitted plan chose another lowest order; rebuild the layer")
-            if c["mode"] != "sft" or c["accum"] != "f32":
-                p.set(c["mode"], c["n0"], c["accum"])
-            self._plan, self._key = p, key
+            self._plan.refit(key[0], key[1])
+            self._key = key
         return self._plan
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:

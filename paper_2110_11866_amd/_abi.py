@@ -18,7 +18,7 @@ MORLET_ERR_HIP = 5
 
 MORLET_F32, MORLET_F16, MORLET_BF16 = 0, 1, 2
 MORLET_SCAN_SFT, MORLET_SCAN_ASFT = 0, 1
-MORLET_ACC_F32, MORLET_ACC_COMPENSATED = 0, 1
+MORLET_ACC_F32, MORLET_ACC_F64, MORLET_ACC_MIXED = 0, 1, 2
 MORLET_MAX_TERMS = 12
 
 # every symbol include/morlet.h declares, with (restype, argtypes)
@@ -42,6 +42,7 @@ SIGNATURES = {
     "gauss_smooth2d_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
     "morlet_image_axis_info": (ctypes.c_int, [_vp, _i32, _P(_i64), _P(_i64), _P(_dbl), _P(_dbl)]),
     "morlet_plan_set": (ctypes.c_int, [_vp, ctypes.c_int, _i64, ctypes.c_int]),
+    "morlet_plan_refit": (ctypes.c_int, [_vp, _dbl, _dbl, _vp]),
     "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
     "morlet_plan_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
     "morlet_plan_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _i32, _P(_i32), _P(_i32), _vp]),
@@ -162,6 +163,10 @@ def morlet_image_axis_info(plan: int, axis: int, K: int) -> dict:
 
 def morlet_plan_set(plan: int, mode: int, n0: int, accum: int) -> None:
     check(lib().morlet_plan_set(plan, mode, n0, accum))
+
+
+def morlet_plan_refit(plan: int, sigma: float, xi: float, stream: int) -> None:
+    check(lib().morlet_plan_refit(plan, sigma, xi, stream))
 
 
 def morlet_plan_set_tile(plan: int, R: int) -> None:

@@ -25,7 +25,19 @@ TILES = (4, 8, 16, 32)
 INSTANCES = [("scan_inst.hip", k, r) for k in TERMS for r in TILES]
 
 
-def _compile(item) -> str:
+# headers only the host sources include (a change to them leaves the device objects alone)
+HOST_HEADERS = ("plan_internal.h",)
+
+
+def _newest_header(host: bool) -> float:
+    hdrs = [os.path.join(CSRC, f) for f in os.listdir(CSRC)
+            if f.endswith(".h") and (host or f not in HOST_HEADERS)]
+    if host:
+        hdrs.append(os.path.join(HERE, "..", "include", "morlet.h"))
+    return max(os.path.getmtime(h) for h in hdrs)
+
+
+def _compile(item, incremental: bool = False) -> str:
     if isinstance(item, tuple):
         src, k, r = item
         obj = os.path.join(BUILD, "scan_k%d_r%d.o" % (k, r))
@@ -33,6 +45,10 @@ def _compile(item) -> str:
     else:
         src, obj, defs = item, os.path.join(BUILD, os.path.splitext(item)[0] + ".o"), []
     path = os.path.join(CSRC, src)
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(path) and t > _newest_header(src.endswith(".cpp")):
+            return obj
     if src.endswith(".hip"):
         cmd = [HIPCC, "-c", *COMMON, *DEVICE_FLAGS, *defs, "-x", "hip", path, "-o", obj]
     else:
@@ -41,13 +57,14 @@ def _compile(item) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libmorlet.so; returns its path."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source and link libmorlet.so; returns its path. incremental=True keeps
+    objects newer than their source and every header (development rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
     # the largest instantiation sets first, so the long compiles start early
     srcs = sorted(INSTANCES, key=lambda t: (-t[1], -t[2])) + DEVICE_SOURCES + HOST_SOURCES
     with ThreadPoolExecutor(max_workers=int(os.environ.get("MAX_JOBS", "8"))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda it: _compile(it, incremental), srcs))
     tmp = OUT + ".tmp"
     subprocess.run([HIPCC, "-shared", "-fPIC", *DEVICE_FLAGS, *objs, "-o", tmp], check=True)
     os.replace(tmp, OUT)
@@ -57,5 +74,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -262,8 +262,11 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   a.K = plan->K;
   a.R = plan->R;
   // the gradient pass always accumulates in float64: the chain rule through the fitted
-  // coefficients cancels the per-term sums by orders of magnitude
-  a.wide = variant == mk::kVarParamGrad ? 1 : plan->accum;
+  // coefficients cancels the per-term sums by orders of magnitude; the adjoint runs the
+  // float64 or the mixed scan (the float32 tile scan is built for the forward)
+  a.acc = variant == mk::kVarParamGrad ? mk::kAccF64
+          : variant == mk::kVarAdjoint ? (plan->accum == MORLET_ACC_F64 ? mk::kAccF64 : mk::kAccMixed)
+                                       : plan->accum;
   // differentials: 2 real output from the sines (SFT, first), 1 from the cosines (SFT,
   // second), 3 from both (ASFT)
   a.kind = plan->deriv == 0 ? plan->kind : plan->mode == MORLET_SCAN_ASFT ? 3 : plan->deriv == 1 ? 2 : 1;
@@ -294,7 +297,7 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   a.f32_bytes = (int64_t)mk::TabLayout{plan->K, plan->R}.f32Bytes();
   a.ws = ws;
   a.dtype = dtype;
-  const int occ = mk::scan_occupancy(a.K, a.R, variant, a.wide, a.kind, mom, dtype);
+  const int occ = mk::scan_occupancy(a.K, a.R, variant, a.acc, a.kind, mom, dtype);
   if (occ <= 0) return fail(MORLET_ERR_UNSUPPORTED, "no kernel for this configuration");
   const int64_t cap = (int64_t)occ * plan->num_cus;
   a.grid = (int)(ntiles < cap ? ntiles : cap);
@@ -378,7 +381,7 @@ morlet_status run_edge(morlet_plan_t plan, const void* x, int dtype, void* out, 
   a.row0.jend = jend;
   a.row0.ntiles = (int32_t)ntiles;
   a.ntiles = ntiles;
-  const int occ = mk::scan_occupancy(a.K, a.R, mk::kVarForward, a.wide, a.kind, 0, 0);
+  const int occ = mk::scan_occupancy(a.K, a.R, mk::kVarForward, a.acc, a.kind, 0, 0);
   const int64_t cap = (int64_t)(occ > 0 ? occ : 1) * plan->num_cus;
   a.grid = (int)(ntiles < cap ? ntiles : cap);
   a.x = xe;
@@ -599,7 +602,7 @@ void pad_launch(morlet_plan_t plan, mk::ScanLaunch& a, int64_t Ne, int variant, 
   a.row0.jend = jend;
   a.row0.ntiles = (int32_t)ntiles;
   a.ntiles = ntiles;
-  const int occ = mk::scan_occupancy(a.K, a.R, variant, a.wide, a.kind, mom, dtype);
+  const int occ = mk::scan_occupancy(a.K, a.R, variant, a.acc, a.kind, mom, dtype);
   const int64_t cap = (int64_t)(occ > 0 ? occ : 1) * plan->num_cus;
   a.grid = (int)(ntiles < cap ? ntiles : cap);
 }
@@ -1319,7 +1322,7 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
     return st;
   }
   if (mode != MORLET_SCAN_SFT && mode != MORLET_SCAN_ASFT) return fail(MORLET_ERR_UNSUPPORTED, "unknown scan mode");
-  if (accum != MORLET_ACC_F32 && accum != MORLET_ACC_COMPENSATED)
+  if (accum != MORLET_ACC_F32 && accum != MORLET_ACC_F64 && accum != MORLET_ACC_MIXED)
     return fail(MORLET_ERR_UNSUPPORTED, "unknown accumulation mode");
   if (n0 < 0 || (!plan->batched && n0 > plan->L))
     return fail(MORLET_ERR_INVALID_ARG, "n0 must be 0 (default) or in [1, L]");
@@ -1543,7 +1546,6 @@ morlet_status gauss_smooth(morlet_plan_t plan, const void* x, morlet_dtype dtype
   return run_scan(plan, x, (int)dtype, y, ws, ws_bytes, stream, 1, false);
 }
 
-
 morlet_status morlet_scalogram_plan(morlet_plan_t* out, int32_t B, const int64_t* lengths, int32_t S,
                                     const double* sigmas, const double* xis, int32_t K, double L_over_sigma) {
   if (!out) return fail(MORLET_ERR_INVALID_ARG, "null output handle");
@@ -1646,10 +1648,75 @@ morlet_status morlet_scalogram_forward(morlet_plan_t plan, const void* x_packed,
   return run_scan(plan, x_packed, (int)dtype, W_packed, ws, ws_bytes, stream, 0, true);
 }
 
+morlet_status morlet_plan_refit(morlet_plan_t plan, double sigma, double xi, void* stream) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->batched || plan->image2d || plan->multiply || plan->deriv != 0)
+    return fail(MORLET_ERR_UNSUPPORTED, "refit takes single-signal Morlet and Gaussian smoothing plans");
+  if (!finite_pos(sigma)) return fail(MORLET_ERR_INVALID_ARG, "sigma must be finite and > 0");
+  if (plan->kind == 0 && !finite_pos(xi)) return fail(MORLET_ERR_INVALID_ARG, "xi must be finite and > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the previous refit's upload must have left the staging buffer before it is rewritten
+  if (plan->stage_event && hipEventSynchronize(static_cast<hipEvent_t>(plan->stage_event)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MORLET_ERR_HIP, "waiting for the previous table upload failed");
+  }
+  plan->sigma = sigma;
+  std::vector<double> re, im;
+  if (plan->kind == 0) {
+    plan->xi = xi;
+    mk::morlet_taps(sigma, xi, plan->L, re, im);
+  } else {
+    mk::gauss_taps(sigma, plan->L, re);
+  }
+  const mk::Fit f = mk::fit_orders(re, im, plan->L, plan->P_S, plan->K);
+  plan->cc = f.cc;
+  plan->sc = f.sc;
+  plan->relrmse = f.relrmse;
+  mk::jacobian(plan);
+  plan->direct_H = -1;   // the direct-convolution baseline's taps follow sigma and xi
+  std::string err;
+  mk::build_table(plan, &err);
+  if (!plan->d_tab) return MORLET_OK;   // no HIP device: host-side plan only
+  if (plan->h_tab.size() != plan->tab_bytes) return fail(MORLET_ERR_HIP, "table size changed");
+  if (plan->h_stage && plan->stage_bytes != plan->tab_bytes) {   // the tile shape changed the table
+    (void)hipHostFree(plan->h_stage);
+    plan->h_stage = nullptr;
+  }
+  if (!plan->h_stage) {
+    if (hipHostMalloc(&plan->h_stage, plan->tab_bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      plan->h_stage = nullptr;
+      return fail(MORLET_ERR_ALLOC, "hipHostMalloc of the staging table failed");
+    }
+    plan->stage_bytes = plan->tab_bytes;
+  }
+  if (!plan->stage_event) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MORLET_ERR_HIP, "hipEventCreate failed");
+    }
+    plan->stage_event = ev;
+  }
+  std::memcpy(plan->h_stage, plan->h_tab.data(), plan->tab_bytes);
+  hipError_t e = hipMemcpyAsync(plan->d_tab, plan->h_stage, plan->tab_bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(static_cast<hipEvent_t>(plan->stage_event), s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MORLET_ERR_HIP, std::string("table upload failed: ") + hipGetErrorString(e));
+  }
+  return MORLET_OK;
+}
+
 void morlet_destroy(morlet_plan_t plan) {
   if (!plan) return;
   morlet_destroy(plan->axis[0]);
   morlet_destroy(plan->axis[1]);
+  if (plan->stage_event) {
+    (void)hipEventSynchronize(static_cast<hipEvent_t>(plan->stage_event));
+    (void)hipEventDestroy(static_cast<hipEvent_t>(plan->stage_event));
+  }
+  if (plan->h_stage) (void)hipHostFree(plan->h_stage);
   if (plan->d_tab) (void)hipFree(plan->d_tab);
   if (plan->d_rows) (void)hipFree(plan->d_rows);
   if (plan->d_direct) (void)hipFree(plan->d_direct);

@@ -6,8 +6,12 @@
 
 namespace mk {
 
+// Scan arithmetic (the values of morlet_accum): float32 tile scan with float64 carries,
+// float64 throughout, float64 chunk sums and wave scan with a float32 recurrence.
+enum ScanAcc { kAccF32 = 0, kAccF64 = 1, kAccMixed = 2 };
+
 struct ScanLaunch {
-  int K, R, wide, kind;         // kind: 0 Morlet (complex64 out), 1 Gaussian (float32 out)
+  int K, R, acc, kind;          // acc: ScanAcc; kind: 0 Morlet (complex64 out), 1 Gaussian (float32 out)
   const void* x;                // signal(s)
   int dtype;                    // 0 f32, 1 f16, 2 bf16
   void* out;                    // complex64 or float32
@@ -32,7 +36,7 @@ enum ScanVariant { kVarForward = 0, kVarAdjoint = 1, kVarParamGrad = 2 };
 // Launch a scan variant (forward, adjoint, parameter-gradient pass; mom: carry the
 // alpha-derivative states for the ASFT sigma gradient).
 hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s);
-int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int dtype);
+int scan_occupancy(int K, int R, int variant, int acc, int kind, int mom, int dtype);
 // Sum per-tile partials into d/dsigma, d/dxi per scale: per-row sums into rowpart
 // [nrows][4K+3] (one block per row), then one block per scale over its rows.
 hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* rowpart, double* gparams, hipStream_t s);
@@ -49,7 +53,7 @@ hipError_t launch_direct_conv(const void* x, int dtype, int64_t N, const float2*
 
 hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s);
 // Resident blocks per CU of the forward kernel for this configuration (0 if unsupported).
-int scan_forward_occupancy(int K, int R, int wide, int kind);
+int scan_forward_occupancy(int K, int R, int acc, int kind);
 hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
 
 // Multiplication method (Sec. III-B), around a three-row Gaussian scan: u = [x cos(xi m),

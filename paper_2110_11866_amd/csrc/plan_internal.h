@@ -28,7 +28,7 @@ struct morlet_plan_s {
   int mode = 0;           // 0 SFT, 1 ASFT
   int64_t n0 = 0;         // ASFT shift (0 for SFT)
   int64_t n0_asft = 0;    // shift used when ASFT is selected
-  int accum = 0;          // 0 float32, 1 compensated (float64)
+  int accum = 0;          // morlet_accum: 0 float32 tile scan, 1 float64, 2 mixed
   int boundary = 0;       // single signals: 0 zero extension, 1 edge values (Sec. II)
   std::vector<double> cc, sc;   // cos / sin coefficients (m, l) or (a, 0)
   std::vector<double> jac;      // [4K]: dcc/dsigma, dcc/dxi, dsc/dsigma, dsc/dxi
@@ -40,6 +40,11 @@ struct morlet_plan_s {
   void* d_tab = nullptr;  // device copy of the constant table
   size_t tab_bytes = 0;
   std::vector<unsigned char> h_tab;
+  // morlet_plan_refit: pinned staging copy of the table for the stream-ordered upload, and the
+  // event recorded after that upload (allocated by the first refit, kept until destroy)
+  void* h_stage = nullptr;
+  size_t stage_bytes = 0;
+  void* stage_event = nullptr;            // hipEvent_t
   // batched ragged plans (B signals x S scales); empty for single-signal plans
   bool batched = false;
   int B = 0, S = 0;

@@ -13,7 +13,7 @@ namespace mk {
 
 using KernelFn = void (*)(ScanLaunch);
 // Selectors of the per-(K, R) instantiation sets, one object each (scan_inst.hip).
-using SelectFn = KernelFn (*)(int var, int wide, int kind, int mom, int dt);
+using SelectFn = KernelFn (*)(int var, int acc, int kind, int mom, int dt);
 #define MK_DECL_R(K) \
   KernelFn select_scan_k##K##_r4(int, int, int, int, int); KernelFn select_scan_k##K##_r8(int, int, int, int, int); \
   KernelFn select_scan_k##K##_r16(int, int, int, int, int); KernelFn select_scan_k##K##_r32(int, int, int, int, int);
@@ -26,14 +26,14 @@ namespace {
 // index of a supported tile shape: R = 4, 8, 16, 32 -> 0..3, else -1
 int r_index(int R) { return R == 4 ? 0 : R == 8 ? 1 : R == 16 ? 2 : R == 32 ? 3 : -1; }
 
-KernelFn select_kernel(int K, int R, int var, int wide, int kind, int mom, int dt) {
+KernelFn select_kernel(int K, int R, int var, int acc, int kind, int mom, int dt) {
 #define MK_ROW(K) {select_scan_k##K##_r4, select_scan_k##K##_r8, select_scan_k##K##_r16, select_scan_k##K##_r32}
   static const SelectFn table[kMaxTerms][4] = {MK_ROW(1), MK_ROW(2), MK_ROW(3), MK_ROW(4),  MK_ROW(5),  MK_ROW(6),
                                                MK_ROW(7), MK_ROW(8), MK_ROW(9), MK_ROW(10), MK_ROW(11), MK_ROW(12)};
 #undef MK_ROW
   const int ri = r_index(R);
   if (K < 1 || K > kMaxTerms || ri < 0) return nullptr;
-  return table[K - 1][ri](var, wide, kind, mom, dt);
+  return table[K - 1][ri](var, acc, kind, mom, dt);
 }
 
 __global__ void zero_fill_kernel(uint4* p, size_t n16, unsigned char* tail, size_t ntail) {
@@ -128,23 +128,23 @@ __global__ void sum_scales_kernel(const float* part, float* out, const Row* rows
 }  // namespace
 
 hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s) {
-  KernelFn fn = select_kernel(a.K, a.R, variant, a.wide, a.kind, mom, variant == kVarAdjoint ? 0 : a.dtype);
+  KernelFn fn = select_kernel(a.K, a.R, variant, a.acc, a.kind, mom, variant == kVarAdjoint ? 0 : a.dtype);
   if (!fn) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fn, dim3(a.grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
-int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int dtype) {
+int scan_occupancy(int K, int R, int variant, int acc, int kind, int mom, int dtype) {
   // resident blocks per CU of one kernel instantiation; queried once per instantiation (every
   // device this library runs on is a gfx950) and kept, so launches make no runtime query
-  static std::atomic<int> cache[kMaxTerms + 1][4][3][2][4][2][3];
-  if (K < 1 || K > kMaxTerms || r_index(R) < 0 || variant < 0 || variant > 2 || wide < 0 || wide > 1 ||
+  static std::atomic<int> cache[kMaxTerms + 1][4][3][3][4][2][3];
+  if (K < 1 || K > kMaxTerms || r_index(R) < 0 || variant < 0 || variant > 2 || acc < 0 || acc > 2 ||
       kind < 0 || kind > 3 || mom < 0 || mom > 1 || dtype < 0 || dtype > 2)
     return 0;
-  std::atomic<int>& slot = cache[K][r_index(R)][variant][wide][kind][mom][variant == kVarAdjoint ? 0 : dtype];
+  std::atomic<int>& slot = cache[K][r_index(R)][variant][acc][kind][mom][variant == kVarAdjoint ? 0 : dtype];
   const int known = slot.load(std::memory_order_relaxed);
   if (known > 0) return known;
-  KernelFn fn = select_kernel(K, R, variant, wide, kind, mom, variant == kVarAdjoint ? 0 : dtype);
+  KernelFn fn = select_kernel(K, R, variant, acc, kind, mom, variant == kVarAdjoint ? 0 : dtype);
   if (!fn) return 0;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(fn), kThreads, 0) != hipSuccess)
@@ -156,7 +156,7 @@ int scan_occupancy(int K, int R, int variant, int wide, int kind, int mom, int d
 
 hipError_t launch_scan_forward(const ScanLaunch& a, hipStream_t s) { return launch_scan(a, kVarForward, 0, s); }
 
-int scan_forward_occupancy(int K, int R, int wide, int kind) { return scan_occupancy(K, R, kVarForward, wide, kind, 0, 0); }
+int scan_forward_occupancy(int K, int R, int acc, int kind) { return scan_occupancy(K, R, kVarForward, acc, kind, 0, 0); }
 
 hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* rowpart, double* gparams, hipStream_t s) {
   hipLaunchKernelGGL(pg_rows_kernel, dim3(a.nrows), dim3(256), 0, s, a, a.K, rowpart);

@@ -11,7 +11,7 @@
 #define MK_SELECT_NAME(k, r) MK_SELECT_NAME_(k, r)
 
 namespace mk {
-KernelFn MK_SELECT_NAME(MK_K, MK_R)(int var, int wide, int kind, int mom, int dt) {
-  return pick_scan<MK_K, MK_R>(var, wide, kind, mom, dt);
+KernelFn MK_SELECT_NAME(MK_K, MK_R)(int var, int acc, int kind, int mom, int dt) {
+  return pick_scan<MK_K, MK_R>(var, acc, kind, mom, dt);
 }
 }  // namespace mk

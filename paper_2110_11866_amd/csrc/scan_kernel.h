@@ -74,9 +74,20 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
 // smoothing, its second differential); 2 real output from the sine components (the
 // Gaussian's first differential, forward only); 3 real output from both components (the
 // differentials by the attenuated transform, forward only)
-template <int VAR, int K, int R, bool WIDE, int KIND, bool MOM, int DT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR == kFwd && !WIDE && R <= 16) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
-  using acc_t = typename std::conditional<WIDE, double, float>::type;
+// ACC: arithmetic of the scan (the library's morlet_accum values)
+//   kAccF32   : float32 for the per-thread work (chunk sums, 16-lane wave scan, recurrence,
+//               combination); float64 only for the carries between rows of a wave, waves and
+//               tiles (forward only).
+//   kAccF64   : float64 scan state, carries and combination.
+//   kAccMixed : float64 chunk sums and wave scan, float32 recurrence and combination.
+template <int VAR, int K, int R, int ACC, int KIND, bool MOM, int DT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    (VAR == kFwd && (ACC == kAccF32 || (ACC == kAccMixed && R <= 16))) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
+  constexpr bool WIDE = ACC == kAccF64;
+  constexpr bool F32T = ACC == kAccF32;                  // float32 tile scan
+  static_assert(!F32T || VAR == kFwd, "the float32 tile scan is built for the forward");
+  using acc_t = typename std::conditional<WIDE, double, float>::type;   // recurrence and combination
+  using sc_t = typename std::conditional<F32T, float, double>::type;    // chunk sums and wave scan
   constexpr int T = R * kThreads;
   constexpr bool GAUSS = KIND != 0;                      // real output
   constexpr bool SINE = KIND == 2;
@@ -165,6 +176,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
     const unsigned char* tb = P.tabs + (int64_t)row.scale * P.tab_stride;
     const Tab<WIDE> tab{(cptr<acc_t>)(WIDE ? tb + P.f32_bytes : tb), K};
     const Tab<true> tabd{(cptr<double>)(tb + P.f32_bytes), K};
+    const Tab<!F32T> tabs{(cptr<sc_t>)(F32T ? tb : tb + P.f32_bytes), K};   // chunk sums, wave scan
     const int mo = lay.nComplex();   // offset of the moment entries d a^d
 
     // 1. inputs, four positions at a time: y[j..j+3] and y[j-2L..j-2L+3] (zero outside the
@@ -227,34 +239,35 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
     const acc_t Dw = tab.scalar(lay.sD());
 
     // 2. chunk sums: the recurrence run from a zero state over the thread's R positions,
-    //    B = sum_r a^{R-1-r} dy[r], in Horner form and in float64. Everything that propagates
-    //    along the row (chunk sums, wave scan, tile aggregates, carries) is float64, so float32
-    //    rounding never accumulates over the row; only the per-sample recurrence of step 5 is
-    //    float32 (one rounded carry, then R steps). On gfx950 a float64 FMA issues at the rate
-    //    of an unpacked float32 FMA.
+    //    B = sum_r a^{R-1-r} dy[r], in Horner form, in sc_t: float32 in the float32 mode,
+    //    float64 in the others. The sums over rows of a wave, waves and tiles (aggregates,
+    //    carries) are float64 in every mode, so float32 rounding never accumulates along the
+    //    row: each thread starts from a rounded float64 carry and runs R steps. On gfx950 a
+    //    float64 FMA issues at the rate of an unpacked float32 FMA; the float32 mode saves the
+    //    conversions and half the DPP moves of the wave scan.
     //    State i = s K + t: stream s, term t; with MOM, state K + t is the alpha-derivative of
     //    state t: w <- a (w - v) + ddy, ddy = d dy / d alpha = 2L a^{2L} y[j-2L].
-    double br[KS], bi[KS];
+    sc_t br[KS], bi[KS];
 #pragma unroll
     for (int i = 0; i < KS; ++i) { br[i] = 0; bi[i] = 0; }
     {
-      const double Dd = tabd.scalar(lay.sD());
+      const sc_t Dd = tabs.scalar(lay.sD());
       auto step1 = [&](int q, const float (&ya)[NS][4], const float (&yb)[NS][4]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const double ddy = MOM ? (double)(2 * row.L) * Dd * (double)yb[0][r] : 0.0;
+          const sc_t ddy = MOM ? (sc_t)(2 * row.L) * Dd * (sc_t)yb[0][r] : (sc_t)0;
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
-            const double dyd = (double)ya[s][r] - Dd * (double)yb[s][r];
+            const sc_t dyd = (sc_t)ya[s][r] - Dd * (sc_t)yb[s][r];
 #pragma unroll
             for (int t = 0; t < K; ++t) {
               const int i = s * K + t;
-              const double ar = tabd.re(lay.eA(), t), ai = tabd.im(lay.eA(), t);
-              const double pr = br[i], pi = bi[i];
+              const sc_t ar = tabs.re(lay.eA(), t), ai = tabs.im(lay.eA(), t);
+              const sc_t pr = br[i], pi = bi[i];
               br[i] = fma(ar, pr, fma(-ai, pi, dyd));
               bi[i] = fma(ar, pi, ai * pr);
               if (MOM && s == 0) {
-                const double wr = br[K + t] - pr, wi = bi[K + t] - pi;
+                const sc_t wr = br[K + t] - pr, wi = bi[K + t] - pi;
                 br[K + t] = fma(ar, wr, fma(-ai, wi, ddy));
                 bi[K + t] = fma(ar, wi, ai * wr);
               }
@@ -278,34 +291,34 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
       } else if (fast_in && NS == 1 && !MOM) {
         // every position of the run is in range: form all R differences first, then per term
         // a Horner pass four positions at a time, B <- a^4 B + (a^3 dy_0 + a^2 dy_1 + a dy_2 + dy_3)
-        double dyd[R];
+        sc_t dyd[R];
 #pragma unroll
         for (int q = 0; q < R / 4; ++q) {
           float ya[NS][4], yb[NS][4];
           load_quad_fast(j0 + 4 * q, ya, yb);
           keep(q, ya, yb);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) dyd[4 * q + r] = (double)ya[0][r] - Dd * (double)yb[0][r];
+          for (int r = 0; r < 4; ++r) dyd[4 * q + r] = (sc_t)ya[0][r] - Dd * (sc_t)yb[0][r];
         }
 #pragma unroll
         for (int t = 0; t < K; ++t) {
           // the term's own contiguous block (one scalar load): a^1 .. a^4
           const int hc = lay.vHC(t);
-          const double a1r = tabd.scalar(hc), a1i = tabd.scalar(hc + 1);
-          const double a2r = tabd.scalar(hc + 2), a2i = tabd.scalar(hc + 3);
-          const double a3r = tabd.scalar(hc + 4), a3i = tabd.scalar(hc + 5);
-          const double a4r = tabd.scalar(hc + 6), a4i = tabd.scalar(hc + 7);
-          double Br = 0, Bi = 0;
+          const sc_t a1r = tabs.scalar(hc), a1i = tabs.scalar(hc + 1);
+          const sc_t a2r = tabs.scalar(hc + 2), a2i = tabs.scalar(hc + 3);
+          const sc_t a3r = tabs.scalar(hc + 4), a3i = tabs.scalar(hc + 5);
+          const sc_t a4r = tabs.scalar(hc + 6), a4i = tabs.scalar(hc + 7);
+          sc_t Br = 0, Bi = 0;
 #pragma unroll
           for (int q = 0; q < R / 4; ++q) {
-            const double d0 = dyd[4 * q], d1 = dyd[4 * q + 1], d2 = dyd[4 * q + 2], d3 = dyd[4 * q + 3];
-            const double cr = fma(a3r, d0, fma(a2r, d1, fma(a1r, d2, d3)));
-            const double ci = fma(a3i, d0, fma(a2i, d1, a1i * d2));
+            const sc_t d0 = dyd[4 * q], d1 = dyd[4 * q + 1], d2 = dyd[4 * q + 2], d3 = dyd[4 * q + 3];
+            const sc_t cr = fma(a3r, d0, fma(a2r, d1, fma(a1r, d2, d3)));
+            const sc_t ci = fma(a3i, d0, fma(a2i, d1, a1i * d2));
             if (q == 0) {
               Br = cr;
               Bi = ci;
             } else {
-              const double nr = fma(a4r, Br, fma(-a4i, Bi, cr));
+              const sc_t nr = fma(a4r, Br, fma(-a4i, Bi, cr));
               Bi = fma(a4r, Bi, fma(a4i, Br, ci));
               Br = nr;
             }
@@ -347,12 +360,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
     //    its base). Row shifts are DPP moves, lanes shifted in from outside the row read zero.
     //    Then the row-exclusive prefix E_l (S shifted by one lane) stays in registers and the
     //    four row totals go to LDS.
-    auto row_shr = [](double v, int sh) -> double {
+    auto row_shr = [](sc_t v, int sh) -> sc_t {
       switch (sh) {   // dpp_ctrl row_shr:n = 0x110 + n; bound_ctrl: invalid source lanes read 0
-        case 1: return __builtin_amdgcn_update_dpp(0.0, v, 0x111, 0xF, 0xF, true);
-        case 2: return __builtin_amdgcn_update_dpp(0.0, v, 0x112, 0xF, 0xF, true);
-        case 4: return __builtin_amdgcn_update_dpp(0.0, v, 0x114, 0xF, 0xF, true);
-        default: return __builtin_amdgcn_update_dpp(0.0, v, 0x118, 0xF, 0xF, true);
+        case 1: return __builtin_amdgcn_update_dpp((sc_t)0, v, 0x111, 0xF, 0xF, true);
+        case 2: return __builtin_amdgcn_update_dpp((sc_t)0, v, 0x112, 0xF, 0xF, true);
+        case 4: return __builtin_amdgcn_update_dpp((sc_t)0, v, 0x114, 0xF, 0xF, true);
+        default: return __builtin_amdgcn_update_dpp((sc_t)0, v, 0x118, 0xF, 0xF, true);
       }
     };
     // one state (with its moment partner) at a time, so only its shifted copies are live
@@ -361,17 +374,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu((VAR =
 #pragma unroll
       for (int i = 0; i < (MOM ? K : KS); ++i) {
         const int t = i % K;
-        const double ar = tabd.re(lay.eTR(d), t), ai = tabd.im(lay.eTR(d), t);
-        const double ur = row_shr(br[i], 1 << d), ui = row_shr(bi[i], 1 << d);
+        const sc_t ar = tabs.re(lay.eTR(d), t), ai = tabs.im(lay.eTR(d), t);
+        const sc_t ur = row_shr(br[i], 1 << d), ui = row_shr(bi[i], 1 << d);
         if constexpr (MOM) {
-          const double wr = row_shr(br[K + i], 1 << d), wi = row_shr(bi[K + i], 1 << d);
+          const sc_t wr = row_shr(br[K + i], 1 << d), wi = row_shr(bi[K + i], 1 << d);
           cmac(br[K + i], bi[K + i], ar, ai, wr, wi);
           cmac(br[K + i], bi[K + i], -tabd.re(mo + lay.eTR(d), t), -tabd.im(mo + lay.eTR(d), t), ur, ui);
         }
         cmac(br[i], bi[i], ar, ai, ur, ui);
       }
     }
-    double er[KS], ei[KS];
+    sc_t er[KS], ei[KS];
 #pragma unroll
     for (int i = 0; i < KS; ++i) { er[i] = row_shr(br[i], 1); ei[i] = row_shr(bi[i], 1); }
     const int rw = lane >> 4;   // row of the lane within its wave
@@ -871,15 +884,16 @@ using KernelFn = void (*)(ScanLaunch);
 
 // One instantiation set per K, defined in scan_k<K>.hip.
 template <int K, int R>
-KernelFn pick_scan(int var, int wide, int gauss, int mom, int dt) {
+KernelFn pick_scan(int var, int acc, int gauss, int mom, int dt) {
   static_assert(R % 4 == 0, "R must be a multiple of 4");
-#define MK_PICK(V, W, G, M, D) \
-  if (var == V && wide == W && gauss == G && mom == M && dt == D) return (KernelFn)scan_kernel<V, K, R, W, G, M, D>;
-#define MK_PICK_DT(V, W, G, M) MK_PICK(V, W, G, M, 0) MK_PICK(V, W, G, M, 1) MK_PICK(V, W, G, M, 2)
-  MK_PICK_DT(kFwd, 0, 0, 0) MK_PICK_DT(kFwd, 0, 1, 0) MK_PICK_DT(kFwd, 1, 0, 0) MK_PICK_DT(kFwd, 1, 1, 0)
-  MK_PICK_DT(kFwd, 0, 2, 0) MK_PICK_DT(kFwd, 1, 2, 0) MK_PICK_DT(kFwd, 0, 3, 0) MK_PICK_DT(kFwd, 1, 3, 0)
-  MK_PICK(kAdj, 0, 0, 0, 0) MK_PICK(kAdj, 0, 1, 0, 0) MK_PICK(kAdj, 1, 0, 0, 0) MK_PICK(kAdj, 1, 1, 0, 0)
-  MK_PICK_DT(kPg, 1, 0, 0) MK_PICK_DT(kPg, 1, 1, 0) MK_PICK_DT(kPg, 1, 0, 1) MK_PICK_DT(kPg, 1, 1, 1)
+#define MK_PICK(V, A, G, M, D) \
+  if (var == V && acc == A && gauss == G && mom == M && dt == D) return (KernelFn)scan_kernel<V, K, R, A, G, M, D>;
+#define MK_PICK_DT(V, A, G, M) MK_PICK(V, A, G, M, 0) MK_PICK(V, A, G, M, 1) MK_PICK(V, A, G, M, 2)
+#define MK_PICK_FWD(A) MK_PICK_DT(kFwd, A, 0, 0) MK_PICK_DT(kFwd, A, 1, 0) MK_PICK_DT(kFwd, A, 2, 0) MK_PICK_DT(kFwd, A, 3, 0)
+  MK_PICK_FWD(kAccF32) MK_PICK_FWD(kAccF64) MK_PICK_FWD(kAccMixed)
+  MK_PICK(kAdj, kAccMixed, 0, 0, 0) MK_PICK(kAdj, kAccMixed, 1, 0, 0) MK_PICK(kAdj, kAccF64, 0, 0, 0) MK_PICK(kAdj, kAccF64, 1, 0, 0)
+  MK_PICK_DT(kPg, kAccF64, 0, 0) MK_PICK_DT(kPg, kAccF64, 1, 0) MK_PICK_DT(kPg, kAccF64, 0, 1) MK_PICK_DT(kPg, kAccF64, 1, 1)
+#undef MK_PICK_FWD
 #undef MK_PICK_DT
 #undef MK_PICK
   return nullptr;

@@ -18,6 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _header_functions():
     src = open(os.path.join(ROOT, "include", "morlet.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"^\s*#.*$", "", src, flags=re.M)   # preprocessor lines (macros are not symbols)
     return sorted(set(re.findall(r"\b(\w+)\s*\(", src)) - {"defined", "if", "return", "sizeof"})
 
 
@@ -510,3 +511,30 @@ def test_image_backward_workspace_keeps_the_header_first():
         assert L.gauss_smooth2d_backward(h, 1 << 20, 1 << 20, 1 << 20, 100, None) == _abi.MORLET_ERR_WORKSPACE
     finally:
         _abi.morlet_destroy(h)
+
+
+@pytest.mark.parametrize("which", ["scalogram", "differentiation"])
+def test_workload_scales_lowest_order_chosen_by_oracle(which):
+    # every scale of the batched workloads (32 scales 4..4096 of the ragged scalogram, 16
+    # scales 8..2048 of the differentiation batch), K = 5, error-optimal windows: at the
+    # library's window the oracle picks the lowest order itself (argmin of the fitted
+    # wavelet's error, Sec. III-A), and for windows of at most 700 also over the full range
+    # 0..L-K+1; both must equal the library's choice, and the fits must agree
+    s = np.arange(32 if which == "scalogram" else 16, dtype=np.float64)
+    sigmas = 4.0 * 1024.0 ** (s / 31) if which == "scalogram" else 8.0 * 256.0 ** (s / 15)
+    xis = 6.0 / sigmas
+    hs = _abi.morlet_scalogram_plan([1000, 3000], list(sigmas), list(xis), 5, 0.0)
+    try:
+        infos = [_abi.morlet_scalogram_scale_info(hs, i, 5) for i in range(len(sigmas))]
+    finally:
+        _abi.morlet_destroy(hs)
+    for sg, xi, info in zip(sigmas, xis, infos):
+        L = info["L"]
+        ps = O.select_PS(float(sg), float(xi), 5, L)
+        assert ps == info["P_S"], (sg, L, ps, info["P_S"])
+        if L <= 700:
+            assert O.select_PS_full(float(sg), float(xi), 5, L) == ps, (sg, L)
+        m, l = O.fit_morlet(float(sg), float(xi), 5, L, ps)
+        scale = max(np.abs(m).max(), np.abs(l).max())
+        assert np.allclose(info["cos_coef"], m, rtol=1e-9, atol=1e-12 * scale), (sg, L)
+        assert np.allclose(info["sin_coef"], l, rtol=1e-9, atol=1e-12 * scale), (sg, L)

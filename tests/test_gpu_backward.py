@@ -1,6 +1,6 @@
 """Backward pass of the HIP path against the FP64 oracle: the adjoint (dLoss/dx), the
 parameter gradients (dLoss/dsigma, dLoss/dxi with the plan frozen), the batched scalogram
-backward and the autograd layer. Bars: relative L2 1e-5 for dLoss/dx (1e-6 compensated),
+backward and the autograd layer. Bars: relative L2 1e-5 for dLoss/dx (1e-6 in float64),
 relative 1e-5 for the parameter gradients."""
 import sys
 
@@ -10,6 +10,7 @@ import torch
 
 import workloads
 from oracle import morlet_oracle as O
+from oracle_ps import checked_ps
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +36,7 @@ def _announce(*a):
 def _oracle_plan(kind, sigma, K, info, mode):
     if kind == "morlet":
         return O.plan_morlet(sigma, 6.0 / sigma, K, info["L"], mode=mode,
-                             n0=info["n0"] if mode == "asft" else None, P_S=info["P_S"])
+                             n0=info["n0"] if mode == "asft" else None, P_S=checked_ps(sigma, 6.0 / sigma, K, info))
     return O.plan_gauss(sigma, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None)
 
 
@@ -43,7 +44,7 @@ CASES = [(1024, 16.0, 4, 64, 16), (50000, 300.0, 6, 1200, 16), (9000, 40.0, 5, 0
          (20000, 100.0, 5, 400, 8), (5000, 30.0, 4, 0, 4)]
 
 
-@pytest.mark.parametrize("accum", ["f32", "compensated"])
+@pytest.mark.parametrize("accum", ["f32", "f64"])
 @pytest.mark.parametrize("mode", ["sft", "asft"])
 @pytest.mark.parametrize("kind", ["morlet", "gauss"])
 @pytest.mark.parametrize("N,sigma,K,L,tile", CASES)
@@ -68,7 +69,7 @@ def test_backward_matches_oracle(N, sigma, K, L, tile, kind, mode, accum):
     p = _oracle_plan(kind, sigma, K, info, mode)
     gn = g.cpu().numpy().astype(np.complex128 if kind == "morlet" else np.float64)
     want_gx = O.adjoint(gn, p)
-    tol = 1e-6 if accum == "compensated" else 1e-5
+    tol = 1e-6 if accum == "f64" else 1e-5
     assert rel(gx.cpu().numpy(), want_gx) <= tol, rel(gx.cpu().numpy(), want_gx)
     want_gp = O.param_grads(x.astype(np.float64), gn, p)
     got_gp = gp.cpu().numpy()
@@ -134,7 +135,7 @@ def test_scalogram_backward_small(mode, schedule):
     for s in range(len(sigmas)):
         info = plan.scale_info(s)
         p = O.plan_morlet(sigmas[s], xis[s], 5, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None,
-                          P_S=info["P_S"])
+                          P_S=checked_ps(sigmas[s], xis[s], 5, info))
         for b in range(len(lengths)):
             n = lengths[b]
             o = plan.out_offset(b, s)
@@ -164,15 +165,23 @@ def test_autograd_layer_and_central_differences(mode):
     p = layer.plan()
     info = p.info()
     op = O.plan_morlet(sigma, xi, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None,
-                       P_S=info["P_S"])
+                       P_S=checked_ps(sigma, xi, K, info))
     xd = x.detach().cpu().numpy().astype(np.float64)
     wd = w.cpu().numpy().astype(np.float64)
     Wo = O.forward(xd, op)
     go = 2 * wd * Wo
     want = O.param_grads(xd, go, op)
+    # the backward at the cotangent autograd handed it (2 w W with the layer's own float32 W),
+    # against the oracle's gradients at that same cotangent: float64 all the way to .grad
+    assert layer.sigma.grad.dtype == torch.float64 and layer.xi.grad.dtype == torch.float64
+    gl = 2 * wd * W.detach().cpu().numpy().astype(np.complex128)
+    want_l = O.param_grads(xd, gl, op)
+    assert abs(layer.sigma.grad.item() - want_l[0]) <= 1e-5 * abs(want_l[0]), (layer.sigma.grad.item(), want_l[0])
+    assert abs(layer.xi.grad.item() - want_l[1]) <= 1e-5 * abs(want_l[1]), (layer.xi.grad.item(), want_l[1])
+    assert rel(x.grad.cpu().numpy(), O.adjoint(gl, op)) <= 1e-5
+    # and the whole chain (float32 forward included) against the oracle's own loss gradient
     assert abs(layer.sigma.grad.item() - want[0]) <= 1e-4 * abs(want[0]), (layer.sigma.grad.item(), want[0])
     assert abs(layer.xi.grad.item() - want[1]) <= 1e-4 * abs(want[1]), (layer.xi.grad.item(), want[1])
-    assert rel(x.grad.cpu().numpy(), O.adjoint(go, op)) <= 1e-4
 
     def loss_o(s, xx):
         m, l = O.fit_morlet(s, xx, K, op.L, op.P_S)
@@ -211,7 +220,7 @@ def test_differentiation_workload_sampled(schedule):
     plans = []
     for s in range(S):
         info = plan.scale_info(s)
-        plans.append(O.plan_morlet(sigmas[s], xis[s], 5, info["L"], P_S=info["P_S"]))
+        plans.append(O.plan_morlet(sigmas[s], xis[s], 5, info["L"], P_S=checked_ps(sigmas[s], xis[s], 5, info)))
     for b in (0, 17, 40, 63):
         want = sum(O.adjoint(gn[b, s], plans[s]) for s in range(S))
         assert rel(gxn[b], want) <= 1e-5, (b, rel(gxn[b], want))
@@ -276,7 +285,7 @@ def test_backward_with_edge_extension(N, sigma, K, L, kind, mode):
     (200, 66.0, 5, 256, "asft", 10, 16, "f32"),              # N < L
     (1024, 16.0, 4, 64, "sft", None, 16, "f32"),
     (50000, 300.0, 6, 1200, "asft", 0, 16, "f32"),
-    (50000, 300.0, 6, 1200, "sft", None, 32, "compensated"),
+    (50000, 300.0, 6, 1200, "sft", None, 32, "f64"),
     (30001, 100.0, 5, 0, "asft", 0, 8, "f32"),
     (3000, 12.0, 3, 0, "sft", None, 4, "f32"),
 ])
@@ -302,7 +311,7 @@ def test_differential_backward(N, sigma, K, L, mode, n0, tile, accum, order):
     info = plan.info()
     p = O.plan_gauss_deriv(sigma, K, info["L"], order, mode=mode, n0=info["n0"] if mode == "asft" else None)
     want = O.adjoint(g.astype(np.float64), p)
-    assert rel(gx, want) <= (1e-6 if accum == "compensated" else 1e-5), rel(gx, want)
+    assert rel(gx, want) <= (1e-6 if accum == "f64" else 1e-5), rel(gx, want)
     lhs = float(np.dot(g.astype(np.float64), y.astype(np.float64)))
     rhs = float(np.dot(x.astype(np.float64), gx.astype(np.float64)))
     assert abs(lhs - rhs) <= 2e-5 * (np.linalg.norm(g) * np.linalg.norm(y) + 1e-30), (lhs, rhs)
@@ -337,3 +346,38 @@ def test_differential_backward_with_edge_extension(N, sigma, K, L, order, mode):
     lhs = float(np.dot(g.astype(np.float64), y.astype(np.float64)))
     rhs = float(np.dot(x.astype(np.float64), gx.astype(np.float64)))
     assert abs(lhs - rhs) <= 2e-5 * (np.linalg.norm(g) * np.linalg.norm(y) + np.sqrt(N)), (lhs, rhs)
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_layer_refits_into_its_table(mode):
+    # an optimizer step moves sigma and xi; the layer refits its plan's coefficients into the
+    # same device table (window, lowest order and shift frozen): the forward then equals, bit
+    # for bit, a fresh plan built at the new parameters with the same window, order and shift,
+    # and the oracle at those frozen settings
+    import paper_2110_11866_amd as M
+    _announce("layer-refit", mode)
+    N, sigma, xi, K = 6000, 30.0, 6 / 30.0, 5
+    rng = np.random.default_rng(8)
+    x = torch.from_numpy(rng.standard_normal(N).astype(np.float32)).cuda()
+    layer = M.MorletTransform(N, sigma, xi, K, 0, mode=mode)
+    info0 = layer.plan().info()
+    handle = layer.plan().handle
+    with torch.no_grad():
+        layer.sigma.mul_(1.03)
+        layer.xi.mul_(0.98)
+    W1 = layer(x)
+    torch.cuda.synchronize()
+    assert layer.plan().handle == handle
+    s1, x1 = float(layer.sigma), float(layer.xi)
+    info1 = layer.plan().info()
+    assert (info1["L"], info1["P_S"], info1["n0"]) == (info0["L"], info0["P_S"], info0["n0"])
+    fresh = M.MorletPlan(N, s1, x1, K, info0["L"])
+    if mode == "asft":
+        fresh.set("asft", info0["n0"])
+    assert fresh.info()["P_S"] == info0["P_S"]
+    W2 = fresh.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(W1.view(torch.float32), W2.view(torch.float32))
+    op = O.plan_morlet(s1, x1, K, info0["L"], mode=mode, n0=info0["n0"] if mode == "asft" else None,
+                       P_S=info0["P_S"])
+    assert rel(W1.detach().cpu().numpy(), O.forward(x.double().cpu().numpy(), op)) <= 1e-5

@@ -7,10 +7,11 @@ import pytest
 import torch
 
 from oracle import morlet_oracle as O
+from oracle_ps import checked_ps
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f32": 1e-5, "compensated": 1e-6}
+TOL = {"f32": 1e-5, "f64": 1e-6, "mixed": 1e-5}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -32,7 +33,7 @@ def _oracle_plans(plan, W, mode):
     import paper_2110_11866_amd as M
     ix, iy = plan.axis_info(0), plan.axis_info(1)
     # the row pass's order offset P_S, from a 1-D plan of the same row parameters
-    P_S = M.MorletPlan(W, plan.sigma_x, plan.xi, plan.K_x, ix["L"]).info()["P_S"]
+    P_S = checked_ps(plan.sigma_x, plan.xi, plan.K_x, M.MorletPlan(W, plan.sigma_x, plan.xi, plan.K_x, ix["L"]).info())
     px = O.plan_morlet(plan.sigma_x, plan.xi, plan.K_x, ix["L"], mode=mode,
                        n0=ix["n0"] if mode == "asft" else None, P_S=P_S)
     py = O.plan_gauss(plan.sigma_y, plan.K_y, iy["L"], mode=mode, n0=iy["n0"] if mode == "asft" else None)
@@ -46,7 +47,7 @@ def _oracle_plans(plan, W, mode):
     (257, 513, 5.0, 6.0, 5, 8.0, 4, "asft", "f32", torch.float32, 16),
     (300, 200, 6.0, 4.0, 4, 4.0, 4, "sft", "f32", torch.float16, 8),
     (200, 333, 6.0, 6.0, 5, 6.0, 4, "asft", "f32", torch.bfloat16, 4),
-    (640, 480, 16.0, 6.0, 6, 16.0, 6, "asft", "compensated", torch.float32, 32),
+    (640, 480, 16.0, 6.0, 6, 16.0, 6, "asft", "f64", torch.float32, 32),
     (64, 4096, 2.0, 6.0, 4, 100.0, 4, "sft", "f32", torch.float32, 16),
     (1000, 70, 3.0, 5.0, 5, 2.5, 3, "asft", "f32", torch.float32, 16),
 ])
@@ -146,3 +147,26 @@ def test_gabor_parameter_gradients(H, W, sx, xi0, Kx, sy, Ky, mode):
     want_x = sum(O.param_grads(x64[r], g1[r], px) for r in range(H))
     want = np.array([want_y, want_x[0], want_x[1]])
     assert np.all(np.abs(gp - want) <= 1e-5 * np.abs(want) + 1e-9), (gp, want)
+
+
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_gabor_4096_benchmark_workload(mode):
+    # the benchmark's 4096 x 4096 Gabor filter (Morlet rows sigma = 8, xi = 6/8, K = 5; Gaussian
+    # columns sigma = 8, K = 4; error-optimal windows): every pixel against the oracle (its lines
+    # spread over the host's cores), plus the first and last rows and columns on their own
+    import paper_2110_11866_amd as M
+    from oracle_pool import mapper, pool
+    _announce("gabor-4096", mode)
+    H = W = 4096
+    x = torch.randn(H, W, generator=torch.Generator().manual_seed(19)).cuda()
+    plan = M.Gabor2DPlan(H, W, 8.0, 6.0 / 8.0, 5, 8.0, 4, mode=mode)
+    got = plan.forward(x).cpu().numpy()
+    torch.cuda.synchronize()
+    px, py = _oracle_plans(plan, W, mode)
+    with pool() as ex:
+        want = O.gabor_2d(x.double().cpu().numpy(), px, py, map_lines=mapper(ex))
+    assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
+    ix, iy = plan.axis_info(0), plan.axis_info(1)
+    ey, ex_ = iy["L"] + iy["n0"], ix["L"] + ix["n0"]
+    for sl in (np.s_[:ey, :], np.s_[-ey:, :], np.s_[:, :ex_], np.s_[:, -ex_:]):
+        assert rel_l2(got[sl], want[sl]) <= 1e-5, (sl, rel_l2(got[sl], want[sl]))

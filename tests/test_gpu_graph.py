@@ -9,6 +9,7 @@ import pytest
 import torch
 
 from oracle import morlet_oracle as O
+from oracle_ps import checked_ps
 
 pytestmark = pytest.mark.gpu
 
@@ -103,7 +104,7 @@ def test_autotune_single_and_scalogram():
     assert choice["R"] in (4, 8, 16, 32) and choice["schedule"] == "tiles"
     got = plan.forward(xt).cpu().numpy()
     info = plan.info()
-    p = O.plan_morlet(sigma, 6 / sigma, 5, info["L"], mode="asft", n0=info["n0"], P_S=info["P_S"])
+    p = O.plan_morlet(sigma, 6 / sigma, 5, info["L"], mode="asft", n0=info["n0"], P_S=checked_ps(sigma, 6 / sigma, 5, info))
     want = O.forward(x.astype(np.float64), p)
     assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-5
 
@@ -119,7 +120,7 @@ def test_autotune_single_and_scalogram():
     for b in range(len(lengths)):
         for s in range(len(sigmas)):
             info = sp.scale_info(s)
-            p = O.plan_morlet(sigmas[s], 6 / sigmas[s], 5, info["L"], mode="asft", n0=info["n0"], P_S=info["P_S"])
+            p = O.plan_morlet(sigmas[s], 6 / sigmas[s], 5, info["L"], mode="asft", n0=info["n0"], P_S=checked_ps(sigmas[s], 6 / sigmas[s], 5, info))
             want = O.forward(xs[offs[b]:offs[b + 1]].astype(np.float64), p)
             o = sp.out_offset(b, s)
             got = W[o:o + lengths[b]]

@@ -1,7 +1,7 @@
 """Precision stress: N = 2^22 random walk plus white noise stored as float16 / bfloat16,
 sigma in {1024, 65536}, K = 6, window 4 sigma. Every scan mode against the FP64 oracle on
 the dequantised stored values: float32 scans (SFT, ASFT) within 1e-5 relative L2, the
-compensated (float64) scan within 1e-6."""
+float64 scan within 1e-6."""
 import sys
 
 import numpy as np
@@ -36,7 +36,8 @@ def _oracle(xq, key, sigma, K, L, mode, n0):
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
 @pytest.mark.parametrize("sigma", [1024.0, 65536.0])
 @pytest.mark.parametrize("mode,accum,tol", [("sft", "f32", 1e-5), ("asft", "f32", 1e-5),
-                                            ("sft", "compensated", 1e-6), ("asft", "compensated", 1e-6)])
+                                            ("sft", "mixed", 1e-5), ("asft", "mixed", 1e-5),
+                                            ("sft", "f64", 1e-6), ("asft", "f64", 1e-6)])
 def test_precision_stress(signal, dtype, sigma, mode, accum, tol):
     import paper_2110_11866_amd as M
     print("[case] precision", dtype, sigma, mode, accum, flush=True)

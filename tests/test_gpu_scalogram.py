@@ -8,6 +8,7 @@ import torch
 
 import workloads
 from oracle import morlet_oracle as O
+from oracle_ps import checked_ps
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +37,7 @@ def _check_rows(plan, W, x_used, rows, mode, tol):
         n = plan.lengths[b]
         info = plan.scale_info(s)
         p = O.plan_morlet(plan.sigmas[s], plan.xis[s], plan.K, info["L"], mode=mode,
-                          n0=info["n0"] if mode == "asft" else None, P_S=info["P_S"])
+                          n0=info["n0"] if mode == "asft" else None, P_S=checked_ps(plan.sigmas[s], plan.xis[s], plan.K, info))
         want = O.forward(x_used[offs[b]:offs[b] + n], p)
         o = plan.out_offset(b, s)
         got = W[o:o + n]
@@ -49,7 +50,7 @@ def _check_rows(plan, W, x_used, rows, mode, tol):
 
 @pytest.mark.parametrize("schedule", ["tiles", "rows"])
 @pytest.mark.parametrize("tile", [4, 8, 16, 32])
-@pytest.mark.parametrize("mode,accum,tol", [("sft", "f32", 1e-5), ("asft", "f32", 1e-5), ("asft", "compensated", 1e-6)])
+@pytest.mark.parametrize("mode,accum,tol", [("sft", "f32", 1e-5), ("asft", "f32", 1e-5), ("asft", "f64", 1e-6), ("asft", "mixed", 1e-5)])
 def test_small_ragged_batch_all_rows(mode, accum, tol, tile, schedule):
     # ragged lengths including empty, shorter than the window, and multi-tile signals
     import paper_2110_11866_amd as M
@@ -100,3 +101,47 @@ def test_full_ragged_scalogram_sampled_rows(mode, tile, schedule):
     rows = [(int(rng.integers(0, 256)), int(rng.integers(0, 32))) for _ in range(36)]
     rows += [(int(np.argmax(lengths)), 31), (int(np.argmin(lengths)), 31), (0, 0), (255, 31)]
     _check_rows(plan, W, xt.double().cpu().numpy(), rows, mode, 1e-5)
+
+
+def test_full_ragged_scalogram_every_row():
+    # the benchmark's launch (ASFT, default tile and schedule): all 256 x 32 = 8192 rows against
+    # the oracle, each over the whole row and, separately, over its first and last L + n0
+    # outputs (the partial windows at the signal's ends), on the host's cores
+    import time
+    import paper_2110_11866_amd as M
+    from oracle_pool import host_workers, pool, scalogram_chunk_errors
+    _announce("ragged-full-every-row")
+    t0 = time.perf_counter()
+    x, lengths, sigmas, xis = workloads.ragged_scalogram()
+    plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode="asft")
+    xt = torch.from_numpy(x).cuda()
+    W = plan.forward(xt).cpu().numpy()
+    torch.cuda.synchronize()
+    S, B = len(sigmas), len(lengths)
+    plans, edges = [], []
+    for s in range(S):
+        info = plan.scale_info(s)
+        plans.append(O.plan_morlet(sigmas[s], xis[s], 5, info["L"], mode="asft", n0=info["n0"],
+                                   P_S=checked_ps(sigmas[s], xis[s], 5, info)))
+        edges.append(info["L"] + info["n0"])
+    rows = [(b * S + s, b, s) for b in range(B) for s in range(S)]
+    tasks = []
+    for c in range(0, len(rows), 64):
+        chunk = rows[c:c + 64]
+        ids = [(rid, b, int(lengths[b])) for rid, b, s in chunk]
+        gots = [W[plan.out_offset(b, s):plan.out_offset(b, s) + int(lengths[b])] for _, b, s in chunk]
+        tasks.append((ids, gots, [plans[s] for _, _, s in chunk], [edges[s] for _, _, s in chunk]))
+    nw = host_workers()
+    _announce(f"GPU and plans {time.perf_counter() - t0:.1f} s; {len(tasks)} chunks on {nw} workers")
+    res = []
+    with pool(nw) as ex:
+        for k, part in enumerate(ex.map(scalogram_chunk_errors, tasks)):
+            res.extend(part)
+            if k % 16 == 15:
+                _announce(f"{len(res)} rows checked, {time.perf_counter() - t0:.1f} s")
+    assert len(res) == B * S
+    worst = max(res, key=lambda r: r[1])
+    worst_edge = max(res, key=lambda r: max(r[2], r[3]))
+    _announce("worst row", worst, "worst edge", worst_edge, f"{time.perf_counter() - t0:.1f} s")
+    bad = [r for r in res if r[1] > 1e-5 or r[2] > 1e-5 or r[3] > 1e-5]
+    assert not bad, bad[:10]

@@ -10,10 +10,11 @@ import pytest
 import torch
 
 from oracle import morlet_oracle as O
+from oracle_ps import checked_ps
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f32": 1e-5, "compensated": 1e-6}
+TOL = {"f32": 1e-5, "f64": 1e-6, "mixed": 1e-5}
 DT = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
 
 
@@ -36,7 +37,7 @@ def _draw(seed):
     rng = np.random.default_rng(seed)
     kind = ["morlet", "gauss", "gd1", "gd2"][int(rng.integers(0, 4))]
     mode = ["sft", "asft"][int(rng.integers(0, 2))]
-    accum = ["f32", "compensated"][int(rng.integers(0, 2))]
+    accum = ["f32", "f64"][int(rng.integers(0, 2))]
     dt = ["f32", "f16", "bf16"][int(rng.integers(0, 3))]
     tile = [4, 8, 16, 32][int(rng.integers(0, 4))]
     edge = bool(rng.integers(0, 4) == 0)
@@ -69,7 +70,7 @@ def test_random_single_signal(seed):
     info = plan.info()
     n0 = info["n0"] if mode == "asft" else None
     if kind == "morlet":
-        p = O.plan_morlet(sigma, xi, K, info["L"], mode=mode, n0=n0, P_S=info["P_S"])
+        p = O.plan_morlet(sigma, xi, K, info["L"], mode=mode, n0=n0, P_S=checked_ps(sigma, xi, K, info))
     elif kind == "gauss":
         p = O.plan_gauss(sigma, K, info["L"], mode=mode, n0=n0)
     else:
@@ -114,7 +115,7 @@ def test_random_scalogram(seed):
                 continue
             info = plan.scale_info(s)
             p = O.plan_morlet(sigmas[s], xis[s], K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None,
-                              P_S=info["P_S"])
+                              P_S=checked_ps(sigmas[s], xis[s], K, info))
             want = O.forward(x[offs[b]:offs[b + 1]].astype(np.float64), p)
             o = plan.out_offset(b, s)
             assert rel_l2(W[o:o + lengths[b]], want) <= 1e-5, (b, s, rel_l2(W[o:o + lengths[b]], want))
@@ -128,7 +129,7 @@ def test_random_backward(seed):
     rng = np.random.default_rng(9000 + seed)
     kind = ["morlet", "gauss"][int(rng.integers(0, 2))]
     mode = ["sft", "asft"][int(rng.integers(0, 2))]
-    accum = ["f32", "compensated"][int(rng.integers(0, 2))]
+    accum = ["f32", "f64"][int(rng.integers(0, 2))]
     tile = [4, 8, 16, 32][int(rng.integers(0, 4))]
     N = int(math.exp(rng.uniform(0.0, math.log(1e5))))
     sigma = float(math.exp(rng.uniform(math.log(2.0), math.log(1000.0))))
@@ -148,7 +149,7 @@ def test_random_backward(seed):
     torch.cuda.synchronize()
     info = plan.info()
     n0 = info["n0"] if mode == "asft" else None
-    p = (O.plan_morlet(sigma, 6.0 / sigma, K, info["L"], mode=mode, n0=n0, P_S=info["P_S"]) if kind == "morlet"
+    p = (O.plan_morlet(sigma, 6.0 / sigma, K, info["L"], mode=mode, n0=n0, P_S=checked_ps(sigma, 6.0 / sigma, K, info)) if kind == "morlet"
          else O.plan_gauss(sigma, K, info["L"], mode=mode, n0=n0))
     gn = g.astype(np.complex128 if kind == "morlet" else np.float64)
     assert rel_l2(gx.cpu().numpy(), O.adjoint(gn, p)) <= TOL[accum]

@@ -873,3 +873,28 @@ def test_edge_extension_brute_force(mode, N):
     h, s = (O.asft_kernel(pl), pl.n0) if mode == "asft" else (O.kterm_morlet(pl), 0)
     want = np.array([sum(h[k + L] * x[min(max(n - s - k, 0), N - 1)] for k in range(-L, L + 1)) for n in range(N)])
     assert np.allclose(O.forward_edge(x, pl), want, rtol=1e-11, atol=1e-13)
+
+
+# ---------------------------------------------------------------- lowest-order search (Sec. III-A, Sec. V-A)
+def test_select_PS_cap_equals_full_argmin():
+    # select_PS stops its search K orders above the carrier; the reading of Sec. III-A is the
+    # argmin over every admissible lowest order 0..L-K+1. Seeded sweep over small windows,
+    # carriers xi0 from 0.5 to 20 and 1..12 terms, plus a few windows of several hundred
+    rng = np.random.default_rng(77)
+    cases = []
+    for _ in range(60):
+        sigma = float(np.exp(rng.uniform(np.log(1.5), np.log(40.0))))
+        K = int(rng.integers(1, 13))
+        xi0 = float(rng.uniform(0.5, 20.0))
+        L = max(K + 1, int(round(sigma * rng.uniform(1.5, 5.0))))
+        cases.append((sigma, xi0, K, L))
+    cases += [(100.0, 6.0, 5, 262), (160.0, 6.0, 6, 480), (250.0, 12.0, 4, 625), (120.0, 2.0, 8, 360)]
+    for sigma, xi0, K, L in cases:
+        capped = O.select_PS(sigma, xi0 / sigma, K, L)
+        full = O.select_PS_full(sigma, xi0 / sigma, K, L)
+        assert capped == full, (sigma, xi0, K, L, capped, full)
+
+
+def test_default_n0_rounds_halves_up():
+    # the default shift max(1, round(sigma/8)) with halves rounded up
+    assert [O.default_n0(s) for s in (1.0, 4.0, 12.0, 20.0, 28.0, 64.0, 8192.0)] == [1, 1, 2, 3, 4, 8, 1024]
