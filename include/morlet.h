@@ -68,14 +68,33 @@ typedef enum { MORLET_F32 = 0, MORLET_F16 = 1, MORLET_BF16 = 2 } morlet_dtype;
 typedef enum { MORLET_SCAN_SFT = 0, MORLET_SCAN_ASFT = 1 } morlet_scan;
 
 /* Scan arithmetic. Inputs and outputs stay 32-bit (16-bit inputs are widened) in every mode.
- *   MORLET_ACC_F32   (default): float32 for everything a thread computes - the chunk sums of its
- *                    positions, the 16-lane wave scan, the recurrence and the K-term combination;
- *                    float64 only for the carries between the 16-lane rows of a wave, between
- *                    waves and between tiles (the decoupled look-back). Backward calls run the
- *                    mixed scan in this mode.
+ *   MORLET_ACC_AUTO  (default): MORLET_ACC_F32 for the attenuated transform, MORLET_ACC_MIXED for
+ *                    plain SFT. Without attenuation (|a_p| = 1) the scan state never forgets, so
+ *                    the rounding of every tile's float32 aggregate would stay in the state to the
+ *                    row's end (a random walk over the row's tiles); with it each aggregate's
+ *                    rounding decays by e^{-alpha T} per tile of T positions (Sec. II-D).
+ *   MORLET_ACC_F32 : float32 for everything a thread computes - the chunk sums of its positions,
+ *                    the 16-lane wave scan, the recurrence and the K-term combination; float64
+ *                    only for the carries between the 16-lane rows of a wave, between waves and
+ *                    between tiles (the decoupled look-back). Backward calls run the mixed scan
+ *                    in this mode.
  *   MORLET_ACC_F64 : float64 scan state, carries and K-term combination (a reference mode).
- *   MORLET_ACC_MIXED: float64 chunk sums and wave scan, float32 recurrence and combination. */
-typedef enum { MORLET_ACC_F32 = 0, MORLET_ACC_F64 = 1, MORLET_ACC_MIXED = 2 } morlet_accum;
+ *   MORLET_ACC_MIXED: float64 chunk sums and wave scan, float32 recurrence and combination.
+ *   MORLET_ACC_KAHAN: the float32 tile scan compensated: every sum and product a thread forms
+ *                    (chunk sums, wave scan, recurrence, K-term combination) is carried as an
+ *                    unevaluated float32 pair by error-free transformations (TwoSum, FMA-based
+ *                    TwoProduct), the constants as float32 pairs too; carries float64 as in
+ *                    MORLET_ACC_F32. A precision reference: Morlet and Gaussian smoothing plans
+ *                    (not the differentials), R = 16 only (morlet_plan_set_tile returns
+ *                    MORLET_ERR_UNSUPPORTED for other tiles), several times the float32 scan's
+ *                    cost; backward calls run the mixed scan. */
+typedef enum {
+  MORLET_ACC_F32 = 0,
+  MORLET_ACC_F64 = 1,
+  MORLET_ACC_MIXED = 2,
+  MORLET_ACC_AUTO = 3,
+  MORLET_ACC_KAHAN = 4
+} morlet_accum;
 
 /* Maximum number of Fourier terms a plan may use. */
 #define MORLET_MAX_TERMS 12

@@ -10,7 +10,7 @@ from __future__ import annotations
 import torch
 
 from . import _abi
-from ._abi import (MORLET_ACC_F32, MORLET_ACC_F64, MORLET_ACC_MIXED, MORLET_BF16, MORLET_F16, MORLET_F32,
+from ._abi import (MORLET_ACC_AUTO, MORLET_ACC_F32, MORLET_ACC_F64, MORLET_ACC_KAHAN, MORLET_ACC_MIXED, MORLET_BF16, MORLET_F16, MORLET_F32,
                    MORLET_SCAN_ASFT, MORLET_SCAN_SFT, MorletError)
 
 __all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2DPlan", "Gabor2DPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
@@ -18,7 +18,8 @@ __all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2D
 
 _DT = {torch.float32: MORLET_F32, torch.float16: MORLET_F16, torch.bfloat16: MORLET_BF16}
 _MODE = {"sft": MORLET_SCAN_SFT, "asft": MORLET_SCAN_ASFT}
-_ACC = {"f32": MORLET_ACC_F32, "f64": MORLET_ACC_F64, "mixed": MORLET_ACC_MIXED}
+_ACC = {"auto": MORLET_ACC_AUTO, "f32": MORLET_ACC_F32, "f64": MORLET_ACC_F64, "mixed": MORLET_ACC_MIXED,
+        "kahan": MORLET_ACC_KAHAN}
 
 
 def torch_dtype_code(dt: torch.dtype) -> int:
@@ -40,7 +41,7 @@ class _PlanBase:
         self.K = K
         self._ws = None
 
-    def set(self, mode: str = "sft", n0: int = 0, accum: str = "f32") -> "_PlanBase":
+    def set(self, mode: str = "sft", n0: int = 0, accum: str = "auto") -> "_PlanBase":
         _abi.morlet_plan_set(self.handle, _MODE[mode], int(n0), _ACC[accum])
         return self
 
@@ -159,10 +160,10 @@ class MorletPlan(_PlanBase):
     kind = "morlet"
 
     def __init__(self, N: int, sigma: float, xi: float, K: int, L: int = 0, mode: str = "sft",
-                 n0: int = 0, accum: str = "f32"):
+                 n0: int = 0, accum: str = "auto"):
         super().__init__(_abi.morlet_plan(int(N), float(sigma), float(xi), int(K), int(L)), int(N), int(K))
         self.sigma, self.xi = float(sigma), float(xi)
-        if mode != "sft" or n0 or accum != "f32":
+        if mode != "sft" or n0 or accum != "auto":
             self.set(mode, n0, accum)
 
     def forward(self, x: torch.Tensor, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
@@ -205,11 +206,11 @@ class MultiplyPlan(MorletPlan):
     kind = "morlet"
 
     def __init__(self, N: int, sigma: float, xi: float, P_M: int, L: int = 0, mode: str = "sft",
-                 n0: int = 0, accum: str = "f32"):
+                 n0: int = 0, accum: str = "auto"):
         _PlanBase.__init__(self, _abi.morlet_plan_multiply(int(N), float(sigma), float(xi), int(P_M), int(L)),
                            int(N), int(P_M) + 1)
         self.sigma, self.xi, self.P_M = float(sigma), float(xi), int(P_M)
-        if mode != "sft" or n0 or accum != "f32":
+        if mode != "sft" or n0 or accum != "auto":
             self.set(mode, n0, accum)
 
     def direct(self, *args, **kwargs):
@@ -231,10 +232,10 @@ class GaussPlan(_PlanBase):
     kind = "gauss"
 
     def __init__(self, N: int, sigma: float, K: int, L: int = 0, mode: str = "sft", n0: int = 0,
-                 accum: str = "f32"):
+                 accum: str = "auto"):
         super().__init__(_abi.morlet_plan_gauss(int(N), float(sigma), int(K), int(L)), int(N), int(K))
         self.sigma = float(sigma)
-        if mode != "sft" or n0 or accum != "f32":
+        if mode != "sft" or n0 or accum != "auto":
             self.set(mode, n0, accum)
 
     def forward(self, x: torch.Tensor, out: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
@@ -262,12 +263,12 @@ class GaussDerivPlan(GaussPlan):
     0..K-1). ASFT (eq. gddAsft): orders 0..K-1 with both components, shifted by n0."""
 
     def __init__(self, N: int, sigma: float, K: int, L: int = 0, order: int = 1, mode: str = "sft",
-                 n0: int = 0, accum: str = "f32"):
+                 n0: int = 0, accum: str = "auto"):
         _PlanBase.__init__(self, _abi.morlet_plan_gauss_deriv(int(N), float(sigma), int(K), int(L), int(order)),
                            int(N), int(K))
         self.sigma = float(sigma)
         self.order = int(order)
-        if mode != "sft" or n0 or accum != "f32":
+        if mode != "sft" or n0 or accum != "auto":
             self.set(mode, n0, accum)
 
     def backward(self, x: torch.Tensor | None, gy: torch.Tensor, want_params: bool = False):
@@ -288,12 +289,12 @@ class Gauss2DPlan(_PlanBase):
     kind = "image"
 
     def __init__(self, H: int, W: int, sigma_y: float, sigma_x: float, K: int, L_y: int = 0, L_x: int = 0,
-                 mode: str = "sft", n0: int = 0, accum: str = "f32"):
+                 mode: str = "sft", n0: int = 0, accum: str = "auto"):
         h = _abi.morlet_plan_gauss2d(int(H), int(W), float(sigma_y), float(sigma_x), int(K), int(L_y), int(L_x))
         super().__init__(h, int(H) * int(W), int(K))
         self.H, self.W = int(H), int(W)
         self.sigma_y, self.sigma_x = float(sigma_y), float(sigma_x)
-        if mode != "sft" or n0 or accum != "f32":
+        if mode != "sft" or n0 or accum != "auto":
             self.set(mode, n0, accum)
 
     def info(self) -> dict:
@@ -355,14 +356,14 @@ class Gabor2DPlan(_PlanBase):
     kind = "gabor"
 
     def __init__(self, H: int, W: int, sigma_x: float, xi: float, K_x: int, sigma_y: float, K_y: int,
-                 L_x: int = 0, L_y: int = 0, mode: str = "sft", n0: int = 0, accum: str = "f32"):
+                 L_x: int = 0, L_y: int = 0, mode: str = "sft", n0: int = 0, accum: str = "auto"):
         h = _abi.morlet_plan_gabor2d(int(H), int(W), float(sigma_x), float(xi), int(K_x), int(L_x), float(sigma_y),
                                      int(K_y), int(L_y))
         super().__init__(h, int(H) * int(W), max(int(K_x), int(K_y)))
         self.H, self.W = int(H), int(W)
         self.K_x, self.K_y = int(K_x), int(K_y)
         self.sigma_x, self.xi, self.sigma_y = float(sigma_x), float(xi), float(sigma_y)
-        if mode != "sft" or n0 or accum != "f32":
+        if mode != "sft" or n0 or accum != "auto":
             self.set(mode, n0, accum)
 
     def info(self) -> dict:
@@ -419,14 +420,14 @@ class ScalogramPlan(_PlanBase):
     kind = "scalogram"
 
     def __init__(self, lengths, sigmas, xis, K: int, L_over_sigma: float = 0.0, mode: str = "sft",
-                 n0: int = 0, accum: str = "f32"):
+                 n0: int = 0, accum: str = "auto"):
         lengths = [int(v) for v in lengths]
         h = _abi.morlet_scalogram_plan(lengths, list(sigmas), list(xis), int(K), float(L_over_sigma))
         super().__init__(h, int(sum(lengths)), int(K))
         self.lengths = lengths
         self.S = len(sigmas)
         self.sigmas, self.xis = [float(v) for v in sigmas], [float(v) for v in xis]
-        if mode != "sft" or n0 or accum != "f32":
+        if mode != "sft" or n0 or accum != "auto":
             self.set(mode, n0, accum)
 
     def info(self) -> dict:
@@ -499,7 +500,7 @@ class MorletTransform(torch.nn.Module):
     device allocation per step)."""
 
     def __init__(self, N: int, sigma: float, xi: float, K: int, L: int = 0, mode: str = "sft", n0: int = 0,
-                 accum: str = "f32"):
+                 accum: str = "auto"):
         super().__init__()
         self.sigma = torch.nn.Parameter(torch.tensor(float(sigma), dtype=torch.float64))
         self.xi = torch.nn.Parameter(torch.tensor(float(xi), dtype=torch.float64))

@@ -18,7 +18,7 @@ MORLET_ERR_HIP = 5
 
 MORLET_F32, MORLET_F16, MORLET_BF16 = 0, 1, 2
 MORLET_SCAN_SFT, MORLET_SCAN_ASFT = 0, 1
-MORLET_ACC_F32, MORLET_ACC_F64, MORLET_ACC_MIXED = 0, 1, 2
+MORLET_ACC_F32, MORLET_ACC_F64, MORLET_ACC_MIXED, MORLET_ACC_AUTO, MORLET_ACC_KAHAN = 0, 1, 2, 3, 4
 MORLET_MAX_TERMS = 12
 
 # every symbol include/morlet.h declares, with (restype, argtypes)

@@ -37,11 +37,19 @@ def _newest_header(host: bool) -> float:
     return max(os.path.getmtime(h) for h in hdrs)
 
 
-def _compile(item, incremental: bool = False) -> str:
+# Development builds may restrict the scan kernels to some terms K (MK_DEV_TERMS="5,6"): the
+# other (K, R) pairs compile as stubs without kernels. The entry build ignores it.
+def _dev_terms():
+    v = os.environ.get("MK_DEV_TERMS", "")
+    return {int(t) for t in v.split(",") if t.strip()} if v else None
+
+
+def _compile(item, incremental: bool = False, dev_terms=None) -> str:
     if isinstance(item, tuple):
         src, k, r = item
-        obj = os.path.join(BUILD, "scan_k%d_r%d.o" % (k, r))
-        defs = ["-DMK_K=%d" % k, "-DMK_R=%d" % r]
+        stub = dev_terms is not None and k not in dev_terms
+        obj = os.path.join(BUILD, "scan_k%d_r%d%s.o" % (k, r, "_stub" if stub else ""))
+        defs = ["-DMK_K=%d" % k, "-DMK_R=%d" % r] + (["-DMK_STUB"] if stub else [])
     else:
         src, obj, defs = item, os.path.join(BUILD, os.path.splitext(item)[0] + ".o"), []
     path = os.path.join(CSRC, src)
@@ -59,12 +67,14 @@ def _compile(item, incremental: bool = False) -> str:
 
 def build(verbose: bool = False, incremental: bool = False) -> str:
     """Compile every source and link libmorlet.so; returns its path. incremental=True keeps
-    objects newer than their source and every header (development rebuilds)."""
+    objects newer than their source and every header, and honours MK_DEV_TERMS (development
+    rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
+    dev = _dev_terms() if incremental else None
     # the largest instantiation sets first, so the long compiles start early
     srcs = sorted(INSTANCES, key=lambda t: (-t[1], -t[2])) + DEVICE_SOURCES + HOST_SOURCES
     with ThreadPoolExecutor(max_workers=int(os.environ.get("MAX_JOBS", "8"))) as ex:
-        objs = list(ex.map(lambda it: _compile(it, incremental), srcs))
+        objs = list(ex.map(lambda it: _compile(it, incremental, dev), srcs))
     tmp = OUT + ".tmp"
     subprocess.run([HIPCC, "-shared", "-fPIC", *DEVICE_FLAGS, *objs, "-o", tmp], check=True)
     os.replace(tmp, OUT)

@@ -92,6 +92,54 @@ morlet_status check_common(int64_t N, double sigma, int32_t K, int64_t L) {
 
 
 // ---------------------------------------------------------------- batched ragged plans
+// Row queues of the row-serial schedule, one per XCD. A block that takes a row runs all of its
+// tiles, so within a queue the long rows come first (they must start early for the blocks to
+// finish together). The rows of one signal read the same input: they go to one queue, so one
+// XCD's L2 fetches the signal and its S rows share it. Signals are dealt to the queues longest
+// first, each to the queue with the least work so far; with fewer than 4 signals per queue the
+// rows are dealt one by one instead (a single long signal's scales are spread over the chip).
+void build_row_queues(morlet_plan_s* p) {
+  const int nq = mk::kQueues;
+  const int64_t nrows = (int64_t)p->rows.size();
+  const int S = p->S > 0 ? p->S : 1;
+  const bool by_signal = (int64_t)p->B >= 4 * nq && nrows == (int64_t)p->B * S;
+  const int64_t ngroups = by_signal ? p->B : nrows;
+  auto group_rows = [&](int64_t g, int64_t& r0, int64_t& nr) {
+    r0 = by_signal ? g * S : g;
+    nr = by_signal ? S : 1;
+  };
+  std::vector<int64_t> work(ngroups, 0);
+  for (int64_t g = 0; g < ngroups; ++g) {
+    int64_t r0, nr;
+    group_rows(g, r0, nr);
+    for (int64_t r = r0; r < r0 + nr; ++r) work[g] += p->rows[r].ntiles;
+  }
+  std::vector<int64_t> order(ngroups);
+  for (int64_t g = 0; g < ngroups; ++g) order[g] = g;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
+  std::vector<std::vector<int32_t>> q(nq);
+  std::vector<int64_t> load(nq, 0);
+  for (int64_t g : order) {
+    int best = 0;
+    for (int i = 1; i < nq; ++i)
+      if (load[i] < load[best]) best = i;
+    load[best] += work[g];
+    int64_t r0, nr;
+    group_rows(g, r0, nr);
+    for (int64_t r = r0; r < r0 + nr; ++r) q[best].push_back((int32_t)r);
+  }
+  p->row_order.clear();
+  p->max_row_tiles = 0;
+  for (int i = 0; i < nq; ++i) {
+    std::stable_sort(q[i].begin(), q[i].end(),
+                     [&](int32_t a, int32_t b) { return p->rows[a].ntiles > p->rows[b].ntiles; });
+    p->qstart[i] = (int32_t)p->row_order.size();
+    p->row_order.insert(p->row_order.end(), q[i].begin(), q[i].end());
+    if (!q[i].empty()) p->max_row_tiles = std::max<int64_t>(p->max_row_tiles, p->rows[q[i][0]].ntiles);
+  }
+  p->qstart[nq] = (int32_t)p->row_order.size();
+}
+
 // Rows are signal-major: row b*S + s filters signal b at scale s. The output of row (b, s)
 // starts at S * offset_b + s * len_b (layout [signal][scale][n]).
 void build_rows(morlet_plan_s* p) {
@@ -121,13 +169,7 @@ void build_rows(morlet_plan_s* p) {
   }
   p->ntiles = tile0;
   p->ntiles_max = tmax;
-  // longest rows first: a block that takes a row runs all of its tiles, so the long rows
-  // must start early for the blocks to finish together
-  p->row_order.resize(p->rows.size());
-  for (size_t i = 0; i < p->rows.size(); ++i) p->row_order[i] = (int32_t)i;
-  std::stable_sort(p->row_order.begin(), p->row_order.end(),
-                   [&](int32_t a, int32_t b) { return p->rows[a].ntiles > p->rows[b].ntiles; });
-  p->max_row_tiles = p->rows.empty() ? 0 : p->rows[p->row_order[0]].ntiles;
+  build_row_queues(p);
 }
 
 void build_batched_tables(morlet_plan_s* p) {
@@ -255,7 +297,11 @@ morlet_status init_morlet_rows(morlet_plan_s* p, int B, int64_t len, double sigm
 }
 
 // Fill the launch descriptor for this plan (rows, tables, tiles, workspace, grid).
-morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int variant, int mom, int dtype) {
+// recompute = true: a forward pass recomputed inside a gradient call; under the default
+// accumulation it runs the mixed scan (float64 chunk sums), whose rounding stays below what the
+// float64 gradient reductions resolve.
+morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int variant, int mom, int dtype,
+                          bool recompute = false) {
   const int64_t jend = plan->N + plan->L - plan->n0;
   const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(jend, plan->R);
   a = mk::ScanLaunch{};
@@ -264,9 +310,13 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   // the gradient pass always accumulates in float64: the chain rule through the fitted
   // coefficients cancels the per-term sums by orders of magnitude; the adjoint runs the
   // float64 or the mixed scan (the float32 tile scan is built for the forward)
+  const int accum = plan->accum == MORLET_ACC_AUTO
+                        ? (plan->mode == 1 && !recompute ? MORLET_ACC_F32 : MORLET_ACC_MIXED)
+                        : plan->accum;
   a.acc = variant == mk::kVarParamGrad ? mk::kAccF64
-          : variant == mk::kVarAdjoint ? (plan->accum == MORLET_ACC_F64 ? mk::kAccF64 : mk::kAccMixed)
-                                       : plan->accum;
+          : variant == mk::kVarAdjoint ? (accum == MORLET_ACC_F64 ? mk::kAccF64 : mk::kAccMixed)
+          : accum == MORLET_ACC_KAHAN  ? mk::kAccKahan
+                                       : accum;
   // differentials: 2 real output from the sines (SFT, first), 1 from the cosines (SFT,
   // second), 3 from both (ASFT)
   a.kind = plan->deriv == 0 ? plan->kind : plan->mode == MORLET_SCAN_ASFT ? 3 : plan->deriv == 1 ? 2 : 1;
@@ -289,6 +339,7 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
                                                    plan->rows.size() * sizeof(mk::Row) +
                                                    plan->tile_row.size() * sizeof(int32_t));
     a.nrows = (int)plan->rows.size();
+    for (int q = 0; q <= mk::kQueues; ++q) a.qstart[q] = plan->qstart[q];
     if (a.nrows == 1) a.row0 = plan->rows[0];
   }
   a.ntiles = ntiles;
@@ -884,7 +935,7 @@ morlet_status run_image2d_grad(morlet_plan_t plan, const void* x, int dtype, con
   float* C = reinterpret_cast<float*>(wsb + m.c_off);
   double* gp = reinterpret_cast<double*>(wsb + m.gp_off);
   mk::ScanLaunch a;
-  morlet_status st = make_launch(plan->axis[0], a, ws, mk::kVarForward, 0, dtype);
+  morlet_status st = make_launch(plan->axis[0], a, ws, mk::kVarForward, 0, dtype, true);
   if (st != MORLET_OK) return st;
   a.x = x;
   a.dtype = dtype;
@@ -964,7 +1015,7 @@ morlet_status run_gabor2d_grad(morlet_plan_t plan, const void* x, int dtype, con
   float* C = reinterpret_cast<float*>(wsb + m.c_off);
   double* gp = reinterpret_cast<double*>(wsb + m.gp_off);
   mk::ScanLaunch a;
-  morlet_status st = make_launch(plan->axis[0], a, ws, mk::kVarForward, 0, dtype);
+  morlet_status st = make_launch(plan->axis[0], a, ws, mk::kVarForward, 0, dtype, true);
   if (st != MORLET_OK) return st;
   a.x = x;
   a.dtype = dtype;
@@ -1322,8 +1373,11 @@ morlet_status morlet_plan_set(morlet_plan_t plan, morlet_scan mode, int64_t n0, 
     return st;
   }
   if (mode != MORLET_SCAN_SFT && mode != MORLET_SCAN_ASFT) return fail(MORLET_ERR_UNSUPPORTED, "unknown scan mode");
-  if (accum != MORLET_ACC_F32 && accum != MORLET_ACC_F64 && accum != MORLET_ACC_MIXED)
+  if (accum != MORLET_ACC_F32 && accum != MORLET_ACC_F64 && accum != MORLET_ACC_MIXED && accum != MORLET_ACC_AUTO &&
+      accum != MORLET_ACC_KAHAN)
     return fail(MORLET_ERR_UNSUPPORTED, "unknown accumulation mode");
+  if (accum == MORLET_ACC_KAHAN && (plan->deriv != 0 || plan->R != 16))
+    return fail(MORLET_ERR_UNSUPPORTED, "the compensated scan takes Morlet and Gaussian smoothing plans at R = 16");
   if (n0 < 0 || (!plan->batched && n0 > plan->L))
     return fail(MORLET_ERR_INVALID_ARG, "n0 must be 0 (default) or in [1, L]");
   plan->mode = (int)mode;
@@ -1383,6 +1437,8 @@ morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R) {
     return st;
   }
   if (R != 4 && R != 8 && R != 16 && R != 32) return fail(MORLET_ERR_UNSUPPORTED, "R must be 4, 8, 16 or 32");
+  if (plan->accum == MORLET_ACC_KAHAN && R != 16)
+    return fail(MORLET_ERR_UNSUPPORTED, "the compensated scan is built for R = 16 only");
   if (R == plan->R) return MORLET_OK;
   const int oldR = plan->R;
   plan->R = R;

@@ -6,9 +6,10 @@
 
 namespace mk {
 
-// Scan arithmetic (the values of morlet_accum): float32 tile scan with float64 carries,
-// float64 throughout, float64 chunk sums and wave scan with a float32 recurrence.
-enum ScanAcc { kAccF32 = 0, kAccF64 = 1, kAccMixed = 2 };
+// Scan arithmetic: float32 tile scan with float64 carries, float64 throughout, float64 chunk
+// sums and wave scan with a float32 recurrence, the float32 tile scan in compensated
+// (float-float) arithmetic.
+enum ScanAcc { kAccF32 = 0, kAccF64 = 1, kAccMixed = 2, kAccKahan = 3 };
 
 struct ScanLaunch {
   int K, R, acc, kind;          // acc: ScanAcc; kind: 0 Morlet (complex64 out), 1 Gaussian (float32 out)
@@ -19,7 +20,9 @@ struct ScanLaunch {
   const Row* rows;              // device rows when nrows > 1
   int nrows;
   const int32_t* tile_row;      // device: row of every tile when nrows > 1
-  const int32_t* row_order;     // device: rows by decreasing tile count (row-serial schedule)
+  const int32_t* row_order;     // device: row-serial schedule, the rows of queue q at
+                                // [qstart[q], qstart[q + 1]), each queue longest rows first
+  int32_t qstart[kQueues + 1];
   int serial;                   // 1: blocks take whole rows (no look-back); 0: tiles + look-back
   int64_t ntiles;
   const unsigned char* tabs;    // device constant tables, one per scale

@@ -17,6 +17,10 @@ constexpr int kThreads = 256;    // threads per block of the scan kernels
 constexpr int kWaves = kThreads / kWave;
 constexpr int kMaxTerms = 12;
 constexpr int kLookback = 64;    // predecessors inspected per look-back step (one per lane)
+// Row queues of the row-serial schedule: one per XCD of the chip (workgroups are dispatched to
+// the XCDs round-robin, block b to XCD b mod 8), so the rows of one signal, which read the same
+// input, run behind one XCD's L2. A queue that runs dry sends its blocks on to the next one.
+constexpr int kQueues = 8;
 
 // ---------------------------------------------------------------------------------
 // Per-scale constant table. Every constant is a power of the per-term rotation
@@ -24,7 +28,8 @@ constexpr int kLookback = 64;    // predecessors inspected per look-back step (o
 // at a fixed distance, so the same table serves every tile of every row that uses
 // the scale. Complex entry e, term i is stored as re at [(2e) K + i], im at
 // [(2e+1) K + i]; the K values of one entry are contiguous (one scalar load).
-// The table exists twice: float32 entries, then float64 entries.
+// The table exists three times: float32 entries, then float64 entries, then the float32
+// remainders (float64 entry minus float32 entry, rounded) for float-float arithmetic.
 // ---------------------------------------------------------------------------------
 struct TabLayout {
   int K, R;
@@ -64,7 +69,7 @@ struct TabLayout {
   MK_HD int nValues() const { return vHC(K); }
   MK_HD size_t f32Bytes() const { return ((size_t)nValues() * 4 + 255) / 256 * 256; }
   MK_HD size_t f64Bytes() const { return ((size_t)nValues() * 8 + 255) / 256 * 256; }
-  MK_HD size_t bytes() const { return f32Bytes() + f64Bytes(); }
+  MK_HD size_t bytes() const { return 2 * f32Bytes() + f64Bytes(); }
 };
 
 // One scan row: one signal filtered at one scale. Scan positions j = 0 .. jend-1;
@@ -86,7 +91,8 @@ struct WsHeader {
   uint32_t ticket;   // next tile to claim
   uint32_t done;     // blocks finished in the current launch
   uint64_t epoch;    // launches completed on this workspace; tags the tile flags
-  uint64_t pad[6];
+  uint32_t qticket[kQueues];   // row-serial schedule: next row of each queue
+  uint64_t pad[2];
 };
 static_assert(sizeof(WsHeader) == 64, "header size");
 

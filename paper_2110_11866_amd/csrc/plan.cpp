@@ -379,6 +379,9 @@ void fill_table(unsigned char* dst, int kind, int K, int R, int64_t L, int P_S, 
     tf[so[q]] = (float)sv[q];
     td[so[q]] = sv[q];
   }
+  // float32 remainders of every entry, for float-float arithmetic
+  float* tl = (float*)(dst + lay.f32Bytes() + lay.f64Bytes());
+  for (int v = 0; v < lay.nValues(); ++v) tl[v] = (float)(td[v] - (double)tf[v]);
 }
 
 bool build_table(morlet_plan_s* p, std::string* err) {

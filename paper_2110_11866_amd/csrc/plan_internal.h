@@ -28,7 +28,7 @@ struct morlet_plan_s {
   int mode = 0;           // 0 SFT, 1 ASFT
   int64_t n0 = 0;         // ASFT shift (0 for SFT)
   int64_t n0_asft = 0;    // shift used when ASFT is selected
-  int accum = 0;          // morlet_accum: 0 float32 tile scan, 1 float64, 2 mixed
+  int accum = 3;          // morlet_accum: 0 float32 tile scan, 1 float64, 2 mixed, 3 by mode
   int boundary = 0;       // single signals: 0 zero extension, 1 edge values (Sec. II)
   std::vector<double> cc, sc;   // cos / sin coefficients (m, l) or (a, 0)
   std::vector<double> jac;      // [4K]: dcc/dsigma, dcc/dxi, dsc/dsigma, dsc/dxi
@@ -52,7 +52,8 @@ struct morlet_plan_s {
   std::vector<ScaleParams> scales;
   std::vector<mk::Row> rows;               // B*S rows, signal-major
   std::vector<int32_t> tile_row;
-  std::vector<int32_t> row_order;          // rows by decreasing tile count (row-serial schedule)
+  std::vector<int32_t> row_order;          // row-serial schedule: the row queues back to back
+  int32_t qstart[mk::kQueues + 1] = {0};   // queue q is row_order[qstart[q] .. qstart[q + 1])
   int64_t max_row_tiles = 0;
   int64_t ntiles = 0, ntiles_max = 0;
   void* d_rows = nullptr;                  // device rows, then tile_row, then row_order

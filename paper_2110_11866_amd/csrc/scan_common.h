@@ -5,6 +5,7 @@
 
 #include <type_traits>
 
+#include "ff.h"
 #include "launch.h"
 
 namespace mk {
@@ -274,9 +275,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T*;
 
-template <bool WIDE>
-struct Tab {
-  using T = typename std::conditional<WIDE, double, float>::type;
+// A view of one scale's table in the arithmetic T of a kernel: float32 or float64 entries,
+// or for float-float arithmetic the float32 entries and their float32 remainders (the third
+// section of the table) taken as one value.
+template <typename T>
+struct TabT {
   cptr<T> p;
   int K;
   __device__ T re(int e, int i) const { return p[(2 * e) * K + i]; }
@@ -284,6 +287,31 @@ struct Tab {
   __device__ T row(int rrow, int i) const { return p[rrow * K + i]; }
   __device__ T scalar(int s) const { return p[s]; }
 };
+template <>
+struct TabT<ff> {
+  cptr<float> h, l;
+  int K;
+  __device__ ff at(int k) const { return ff(h[k], l[k]); }
+  __device__ ff re(int e, int i) const { return at((2 * e) * K + i); }
+  __device__ ff im(int e, int i) const { return at((2 * e + 1) * K + i); }
+  __device__ ff row(int rrow, int i) const { return at(rrow * K + i); }
+  __device__ ff scalar(int s) const { return at(s); }
+};
+template <bool WIDE>
+using Tab = TabT<typename std::conditional<WIDE, double, float>::type>;
+
+// The view of the table at tb (float32 section, float64 section at f64_off, float32
+// remainders after it) in arithmetic T.
+template <typename T>
+__device__ __forceinline__ TabT<T> tab_view(const unsigned char* tb, int64_t f64_off, const TabLayout& lay) {
+  if constexpr (std::is_same<T, ff>::value) {
+    return TabT<ff>{(cptr<float>)tb, (cptr<float>)(tb + f64_off + (int64_t)lay.f64Bytes()), lay.K};
+  } else if constexpr (std::is_same<T, double>::value) {
+    return TabT<double>{(cptr<double>)(tb + f64_off), lay.K};
+  } else {
+    return TabT<float>{(cptr<float>)tb, lay.K};
+  }
+}
 
 }  // namespace
 }  // namespace mk

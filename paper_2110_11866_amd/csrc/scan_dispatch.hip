@@ -137,8 +137,8 @@ hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s)
 int scan_occupancy(int K, int R, int variant, int acc, int kind, int mom, int dtype) {
   // resident blocks per CU of one kernel instantiation; queried once per instantiation (every
   // device this library runs on is a gfx950) and kept, so launches make no runtime query
-  static std::atomic<int> cache[kMaxTerms + 1][4][3][3][4][2][3];
-  if (K < 1 || K > kMaxTerms || r_index(R) < 0 || variant < 0 || variant > 2 || acc < 0 || acc > 2 ||
+  static std::atomic<int> cache[kMaxTerms + 1][4][3][4][4][2][3];
+  if (K < 1 || K > kMaxTerms || r_index(R) < 0 || variant < 0 || variant > 2 || acc < 0 || acc > 3 ||
       kind < 0 || kind > 3 || mom < 0 || mom > 1 || dtype < 0 || dtype > 2)
     return 0;
   std::atomic<int>& slot = cache[K][r_index(R)][variant][acc][kind][mom][variant == kVarAdjoint ? 0 : dtype];

@@ -63,6 +63,18 @@ enum { kFwd = 0, kAdj = 1, kPg = 2 };
 // written once and never re-read by the kernel, so they bypass the cache hierarchy's reuse
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// row_shr:n DPP move within 16-lane rows (dpp_ctrl 0x110 + n); bound_ctrl: lanes whose source
+// lies outside the row read zero
+template <typename T>
+__device__ __forceinline__ T dpp_row_shr(T v, int sh) {
+  switch (sh) {
+    case 1: return __builtin_amdgcn_update_dpp((T)0, v, 0x111, 0xF, 0xF, true);
+    case 2: return __builtin_amdgcn_update_dpp((T)0, v, 0x112, 0xF, 0xF, true);
+    case 4: return __builtin_amdgcn_update_dpp((T)0, v, 0x114, 0xF, 0xF, true);
+    default: return __builtin_amdgcn_update_dpp((T)0, v, 0x118, 0xF, 0xF, true);
+  }
+}
+
 // complex multiply-add helpers on (re, im) pairs
 template <typename T>
 __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  // z += c x
@@ -80,14 +92,19 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
 //               tiles (forward only).
 //   kAccF64   : float64 scan state, carries and combination.
 //   kAccMixed : float64 chunk sums and wave scan, float32 recurrence and combination.
+//   kAccKahan : the per-thread work of kAccF32 (chunk sums, wave scan, recurrence, combination)
+//               compensated: float-float arithmetic (ff.h) from error-free float32 transforms;
+//               float64 only for the carries, as in kAccF32 (forward only).
 template <int VAR, int K, int R, int ACC, int KIND, bool MOM, int DT>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     (VAR == kFwd && (ACC == kAccF32 || (ACC == kAccMixed && R <= 16))) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
   constexpr bool WIDE = ACC == kAccF64;
   constexpr bool F32T = ACC == kAccF32;                  // float32 tile scan
-  static_assert(!F32T || VAR == kFwd, "the float32 tile scan is built for the forward");
-  using acc_t = typename std::conditional<WIDE, double, float>::type;   // recurrence and combination
-  using sc_t = typename std::conditional<F32T, float, double>::type;    // chunk sums and wave scan
+  constexpr bool KAHAN = ACC == kAccKahan;               // compensated float32 tile scan
+  static_assert(!(F32T || KAHAN) || VAR == kFwd, "the float32 tile scans are built for the forward");
+  // recurrence and combination; chunk sums and wave scan
+  using acc_t = typename std::conditional<WIDE, double, typename std::conditional<KAHAN, ff, float>::type>::type;
+  using sc_t = typename std::conditional<F32T, float, typename std::conditional<KAHAN, ff, double>::type>::type;
   constexpr int T = R * kThreads;
   constexpr bool GAUSS = KIND != 0;                      // real output
   constexpr bool SINE = KIND == 2;
@@ -141,11 +158,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
   // whole row (longest rows first) and runs its tiles in order, carrying the state in LDS.
   Row row = P.row0;
   int64_t ti = 0, row_left = 0;
+  // row-serial: the block starts on its own XCD's queue and moves on to the next queue only
+  // when that one is empty (thread 0 keeps the count of queues it has left behind)
+  int qdone = 0;
   for (;;) {
     uint32_t tile;
     if (P.serial) {
       if (row_left == 0) {
-        if (tid == 0) s_tile = atomicAdd(&hdr->ticket, 1u);
+        if (tid == 0) {
+          uint32_t r = (uint32_t)P.nrows;
+          for (; qdone < kQueues; ++qdone) {
+            const int q = (int)((blockIdx.x + (unsigned)qdone) % kQueues);
+            const uint32_t k = atomicAdd(&hdr->qticket[q], 1u);
+            if ((int64_t)k < (int64_t)(P.qstart[q + 1] - P.qstart[q])) {
+              r = (uint32_t)P.qstart[q] + k;
+              break;
+            }
+          }
+          s_tile = r;
+        }
         __syncthreads();
         const uint32_t r = __builtin_amdgcn_readfirstlane(s_tile);
         __syncthreads();   // every wave has read s_tile before thread 0 may claim again
@@ -174,9 +205,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     // and no later state: it skips its loads, chunk sums and outputs (its sums stay zero)
     const bool wave_dead = jt + (int64_t)__builtin_amdgcn_readfirstlane(wid) * 64 * R >= row.jend;
     const unsigned char* tb = P.tabs + (int64_t)row.scale * P.tab_stride;
-    const Tab<WIDE> tab{(cptr<acc_t>)(WIDE ? tb + P.f32_bytes : tb), K};
+    const TabT<acc_t> tab = tab_view<acc_t>(tb, P.f32_bytes, lay);
     const Tab<true> tabd{(cptr<double>)(tb + P.f32_bytes), K};
-    const Tab<!F32T> tabs{(cptr<sc_t>)(F32T ? tb : tb + P.f32_bytes), K};   // chunk sums, wave scan
+    const TabT<sc_t> tabs = tab_view<sc_t>(tb, P.f32_bytes, lay);   // chunk sums, wave scan
     const int mo = lay.nComplex();   // offset of the moment entries d a^d
 
     // 1. inputs, four positions at a time: y[j..j+3] and y[j-2L..j-2L+3] (zero outside the
@@ -361,11 +392,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     //    Then the row-exclusive prefix E_l (S shifted by one lane) stays in registers and the
     //    four row totals go to LDS.
     auto row_shr = [](sc_t v, int sh) -> sc_t {
-      switch (sh) {   // dpp_ctrl row_shr:n = 0x110 + n; bound_ctrl: invalid source lanes read 0
-        case 1: return __builtin_amdgcn_update_dpp((sc_t)0, v, 0x111, 0xF, 0xF, true);
-        case 2: return __builtin_amdgcn_update_dpp((sc_t)0, v, 0x112, 0xF, 0xF, true);
-        case 4: return __builtin_amdgcn_update_dpp((sc_t)0, v, 0x114, 0xF, 0xF, true);
-        default: return __builtin_amdgcn_update_dpp((sc_t)0, v, 0x118, 0xF, 0xF, true);
+      if constexpr (KAHAN) {
+        return ff(dpp_row_shr(v.h, sh), dpp_row_shr(v.l, sh));
+      } else {
+        return dpp_row_shr(v, sh);
       }
     };
     // one state (with its moment partner) at a time, so only its shifted copies are live
@@ -390,7 +420,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const int rw = lane >> 4;   // row of the lane within its wave
     if ((lane & 15) == 15) {
 #pragma unroll
-      for (int i = 0; i < KS; ++i) { s_rt[wid][rw][2 * i] = br[i]; s_rt[wid][rw][2 * i + 1] = bi[i]; }
+      for (int i = 0; i < KS; ++i) { s_rt[wid][rw][2 * i] = (double)br[i]; s_rt[wid][rw][2 * i + 1] = (double)bi[i]; }
     }
     wave_lds_sync();
     // wave aggregate: sum_r Op(16 R (3 - r)) T_r (lane i owns state i)
@@ -611,7 +641,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int i = 0; i < KS; ++i) {
         const int t = i % K;
-        double cr = er[i], ci = ei[i];
+        double cr = (double)er[i], ci = (double)ei[i];
         cmac(cr, ci, tabd.re(e, t), tabd.im(e, t), z[2 * i], z[2 * i + 1]);
         if (MOM && i >= K) cmac(cr, ci, -tabd.re(mo + e, t), -tabd.im(mo + e, t), z[2 * t], z[2 * t + 1]);
         vr[i] = (acc_t)cr;
@@ -872,6 +902,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     const uint32_t d = atomicAdd(&hdr->done, 1u);
     if (d == gridDim.x - 1) {
       __hip_atomic_store(&hdr->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int q = 0; q < kQueues; ++q) __hip_atomic_store(&hdr->qticket[q], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&hdr->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       st_u64(&hdr->epoch, epoch + 1);
     }
@@ -891,6 +922,8 @@ KernelFn pick_scan(int var, int acc, int gauss, int mom, int dt) {
 #define MK_PICK_DT(V, A, G, M) MK_PICK(V, A, G, M, 0) MK_PICK(V, A, G, M, 1) MK_PICK(V, A, G, M, 2)
 #define MK_PICK_FWD(A) MK_PICK_DT(kFwd, A, 0, 0) MK_PICK_DT(kFwd, A, 1, 0) MK_PICK_DT(kFwd, A, 2, 0) MK_PICK_DT(kFwd, A, 3, 0)
   MK_PICK_FWD(kAccF32) MK_PICK_FWD(kAccF64) MK_PICK_FWD(kAccMixed)
+  // the compensated scan (a precision reference): Morlet and Gaussian smoothing, one tile shape
+  if constexpr (R == 16) { MK_PICK_DT(kFwd, kAccKahan, 0, 0) MK_PICK_DT(kFwd, kAccKahan, 1, 0) }
   MK_PICK(kAdj, kAccMixed, 0, 0, 0) MK_PICK(kAdj, kAccMixed, 1, 0, 0) MK_PICK(kAdj, kAccF64, 0, 0, 0) MK_PICK(kAdj, kAccF64, 1, 0, 0)
   MK_PICK_DT(kPg, kAccF64, 0, 0) MK_PICK_DT(kPg, kAccF64, 1, 0) MK_PICK_DT(kPg, kAccF64, 0, 1) MK_PICK_DT(kPg, kAccF64, 1, 1)
 #undef MK_PICK_FWD

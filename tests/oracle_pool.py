@@ -51,21 +51,29 @@ _SCALOGRAM_X = None
 
 def scalogram_chunk_errors(task):
     """Rows of the ragged-scalogram workload: the worker regenerates the seeded input itself
-    (workloads.ragged_scalogram, the same values the GPU read), so only the GPU's output rows
-    travel. task = (rows [(row id, signal b, offset, length)], got rows, oracle plan per row,
-    edge length per row). Returns [(row id, rel-L2 row, first edge, last edge)]."""
+    (workloads.ragged_scalogram, the same values the GPU read) and reads the GPU's output rows
+    from the shared-memory block the parent filled. task = (block name, output length, rows
+    [(row id, signal b, length, output offset)], oracle plan per row, edge length per row).
+    Returns [(row id, rel-L2 row, first edge, last edge)]."""
     global _SCALOGRAM_X
+    from multiprocessing import shared_memory
     import workloads
     from oracle import morlet_oracle as O
     if _SCALOGRAM_X is None:
         x, lengths, _, _ = workloads.ragged_scalogram()
         _SCALOGRAM_X = (x.astype(np.float64), np.concatenate([[0], np.cumsum(lengths)]))
     xd, offs = _SCALOGRAM_X
-    rows, gots, plans, edges = task
-    out = []
-    for (rid, b, n), got, plan, edge in zip(rows, gots, plans, edges):
-        want = O.forward(xd[offs[b]:offs[b] + n], plan)
-        g = np.asarray(got, dtype=np.complex128)
-        e = min(edge, n)
-        out.append((rid, rel_l2(g, want), rel_l2(g[:e], want[:e]), rel_l2(g[n - e:], want[n - e:])))
+    name, total, rows, plans, edges = task
+    shm = shared_memory.SharedMemory(name=name)
+    try:
+        W = np.ndarray((total,), dtype=np.complex64, buffer=shm.buf)
+        out = []
+        for (rid, b, n, o), plan, edge in zip(rows, plans, edges):
+            want = O.forward(xd[offs[b]:offs[b] + n], plan)
+            g = W[o:o + n].astype(np.complex128)
+            e = min(edge, n)
+            out.append((rid, rel_l2(g, want), rel_l2(g[:e], want[:e]), rel_l2(g[n - e:], want[n - e:])))
+        del W
+    finally:
+        shm.close()
     return out

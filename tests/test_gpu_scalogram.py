@@ -50,7 +50,10 @@ def _check_rows(plan, W, x_used, rows, mode, tol):
 
 @pytest.mark.parametrize("schedule", ["tiles", "rows"])
 @pytest.mark.parametrize("tile", [4, 8, 16, 32])
-@pytest.mark.parametrize("mode,accum,tol", [("sft", "f32", 1e-5), ("asft", "f32", 1e-5), ("asft", "f64", 1e-6), ("asft", "mixed", 1e-5)])
+# plain float32 SFT (an explicit choice; the default runs the mixed scan for SFT) keeps every
+# rounding of its undamped state: at R = 32 its error reaches about 1.2e-5 on these rows
+@pytest.mark.parametrize("mode,accum,tol", [("sft", "auto", 1e-5), ("sft", "f32", 3e-5), ("asft", "f32", 1e-5),
+                                            ("asft", "f64", 1e-6), ("asft", "mixed", 1e-5)])
 def test_small_ragged_batch_all_rows(mode, accum, tol, tile, schedule):
     # ragged lengths including empty, shorter than the window, and multi-tile signals
     import paper_2110_11866_amd as M
@@ -125,20 +128,28 @@ def test_full_ragged_scalogram_every_row():
                                    P_S=checked_ps(sigmas[s], xis[s], 5, info)))
         edges.append(info["L"] + info["n0"])
     rows = [(b * S + s, b, s) for b in range(B) for s in range(S)]
-    tasks = []
-    for c in range(0, len(rows), 64):
-        chunk = rows[c:c + 64]
-        ids = [(rid, b, int(lengths[b])) for rid, b, s in chunk]
-        gots = [W[plan.out_offset(b, s):plan.out_offset(b, s) + int(lengths[b])] for _, b, s in chunk]
-        tasks.append((ids, gots, [plans[s] for _, _, s in chunk], [edges[s] for _, _, s in chunk]))
-    nw = host_workers()
-    _announce(f"GPU and plans {time.perf_counter() - t0:.1f} s; {len(tasks)} chunks on {nw} workers")
-    res = []
-    with pool(nw) as ex:
-        for k, part in enumerate(ex.map(scalogram_chunk_errors, tasks)):
-            res.extend(part)
-            if k % 16 == 15:
-                _announce(f"{len(res)} rows checked, {time.perf_counter() - t0:.1f} s")
+    # the GPU's output goes to the workers through one shared-memory block (each reads its rows
+    # in place), so only row ids, offsets and the oracle plans travel with the tasks
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(create=True, size=W.nbytes)
+    try:
+        np.ndarray(W.shape, dtype=W.dtype, buffer=shm.buf)[:] = W
+        tasks = []
+        for c in range(0, len(rows), 64):
+            chunk = rows[c:c + 64]
+            ids = [(rid, b, int(lengths[b]), plan.out_offset(b, s)) for rid, b, s in chunk]
+            tasks.append((shm.name, W.shape[0], ids, [plans[s] for _, _, s in chunk], [edges[s] for _, _, s in chunk]))
+        nw = host_workers()
+        _announce(f"GPU and plans {time.perf_counter() - t0:.1f} s; {len(tasks)} chunks on {nw} workers")
+        res = []
+        with pool(nw) as ex:
+            for k, part in enumerate(ex.map(scalogram_chunk_errors, tasks)):
+                res.extend(part)
+                if k % 16 == 15:
+                    _announce(f"{len(res)} rows checked, {time.perf_counter() - t0:.1f} s")
+    finally:
+        shm.close()
+        shm.unlink()
     assert len(res) == B * S
     worst = max(res, key=lambda r: r[1])
     worst_edge = max(res, key=lambda r: max(r[2], r[3]))
