@@ -339,6 +339,27 @@ morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int
                                double* alpha, double* cos_coef, double* sin_coef, double* jac,
                                double* kernel_relrmse);
 
+/* The forward without allocation, for callers that cannot allocate device memory or must not
+ * call hipMalloc (code under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * morlet_forward on a single-signal Morlet plan, or morlet_scalogram_forward on a scalogram
+ * plan, with the scan's workspace taken from a fixed device array inside the library
+ * (MORLET_NOALLOC_SCRATCH_BYTES = 8 MiB; each device the library runs on holds one copy until the
+ * process ends). x, W, dtype and stream as for those calls. Each call first clears the part of
+ * the array its launch reads as its start state (header and tile flags) with a fill kernel on
+ * the stream, then launches the scan; the array keeps the last call's contents. Calls that
+ * overlap in time on one device share the array and race: order them (one stream, or events).
+ * Allocates nothing and synchronises nothing; the array's address is resolved once per device
+ * when the first plan is created there (or on the first call). Takes zero-extension plans
+ * only, not the multiplication method. Errors: as morlet_forward / morlet_scalogram_forward
+ * (MORLET_ERR_INVALID_ARG for a plan that is not a Morlet plan, MORLET_ERR_UNSUPPORTED for edge
+ * extension, multiplication-method and image plans); MORLET_ERR_WORKSPACE, with nothing
+ * launched, when the launch needs more than the array: the row-serial schedule of a scalogram
+ * needs 64 bytes, the tiles schedule 64 bytes plus one tile state per tile of 256 R positions
+ * (256 bytes at K <= 5, 640 at K = 12), so a single signal of up to about 2^27 samples at K = 5,
+ * R = 16; MORLET_ERR_HIP if the array's address cannot be resolved or a launch fails. */
+#define MORLET_NOALLOC_SCRATCH_BYTES (8u << 20)
+morlet_status morlet_forward_noalloc(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W, void* stream);
+
 /* Device workspace bytes needed by forward/backward calls on this plan. */
 morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes);
 

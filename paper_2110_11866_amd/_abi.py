@@ -51,6 +51,7 @@ SIGNATURES = {
     "morlet_workspace_size": (ctypes.c_int, [_vp, _P(_sz)]),
     "morlet_workspace_init": (ctypes.c_int, [_vp, _sz, _vp]),
     "morlet_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "morlet_forward_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
     "gauss_smooth": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
     "morlet_scalogram_plan": (ctypes.c_int, [_P(_vp), _i32, _P(_i64), _i32, _P(_dbl), _P(_dbl), _i32, _dbl]),
     "morlet_scalogram_scale_info": (ctypes.c_int, [_vp, _i32, _P(_i64), _P(_i32), _P(_i64), _P(_dbl), _P(_dbl),
@@ -208,6 +209,10 @@ def morlet_workspace_init(ws_ptr: int, nbytes: int, stream: int) -> None:
 
 def morlet_forward(plan: int, x_ptr: int, dtype: int, W_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
     check(lib().morlet_forward(plan, x_ptr, dtype, W_ptr, ws_ptr, ws_bytes, stream))
+
+
+def morlet_forward_noalloc(plan: int, x_ptr: int, dtype: int, W_ptr: int, stream: int) -> None:
+    check(lib().morlet_forward_noalloc(plan, x_ptr, dtype, W_ptr, stream))
 
 
 def gauss_smooth(plan: int, x_ptr: int, dtype: int, y_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:

@@ -18,7 +18,7 @@ DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
 
 HOST_SOURCES = ["plan.cpp", "api.cpp"]
-DEVICE_SOURCES = ["scan_dispatch.hip", "direct_conv.hip", "multiply.hip", "image2d.hip", "tree.hip", "boundary.hip"]
+DEVICE_SOURCES = ["scan_dispatch.hip", "direct_conv.hip", "multiply.hip", "image2d.hip", "tree.hip", "boundary.hip", "noalloc.hip"]
 # scan kernel instantiation sets: scan_inst.hip once per (terms K, samples per thread R)
 TERMS = range(1, 13)
 TILES = (4, 8, 16, 32)

@@ -14,6 +14,7 @@
 #include "image2d.h"
 #include "launch.h"
 #include "multiply.h"
+#include "noalloc.h"
 #include "plan_internal.h"
 
 namespace {
@@ -49,6 +50,9 @@ morlet_status upload_table(morlet_plan_s* p) {
       return MORLET_OK;
     }
     p->device = dev;
+    // set-up of the fixed scratch behind morlet_forward_noalloc, once per device (its failure
+    // only disables that entry point, which retries the set-up itself)
+    (void)mk::scratch_setup(dev);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
       p->num_cus = cus;
@@ -1777,6 +1781,54 @@ void morlet_destroy(morlet_plan_t plan) {
   if (plan->d_rows) (void)hipFree(plan->d_rows);
   if (plan->d_direct) (void)hipFree(plan->d_direct);
   delete plan;
+}
+
+// ---------------------------------------------------------------- forward without allocation
+// The scan's workspace taken from the library's fixed device array (noalloc.hip): for callers
+// that cannot allocate. Only plans whose forward needs nothing but the scan's workspace.
+morlet_status morlet_forward_noalloc(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W, void* stream) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (plan->image2d || plan->multiply || plan->boundary == 1)
+    return fail(MORLET_ERR_UNSUPPORTED, "no-allocation forward: image, multiplication-method and edge-extension "
+                                        "plans need more than the scan's workspace");
+  if (plan->kind != 0) return fail(MORLET_ERR_INVALID_ARG, "morlet_forward_noalloc needs a Morlet plan");
+  if ((int)dtype < 0 || (int)dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
+  const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(plan->N + plan->L - plan->n0, plan->R);
+  if (plan->N == 0 || ntiles == 0) return MORLET_OK;
+  if (!x || !W) return fail(MORLET_ERR_INVALID_ARG, "null x or output pointer");
+  if (ntiles > ((int64_t)1 << 31)) return fail(MORLET_ERR_UNSUPPORTED, "too many tiles");
+  if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  void* ws = mk::scratch_ptr(plan->device);
+  if (!ws) {
+    // set-up missed at plan creation (or failed): resolve it now, on the plan's device
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != plan->device) {
+      (void)hipGetLastError();
+      return fail(MORLET_ERR_INVALID_ARG, "the plan's device is not the current device");
+    }
+    const hipError_t e = mk::scratch_setup(plan->device);
+    if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("scratch set-up failed: ") + hipGetErrorString(e));
+    ws = mk::scratch_ptr(plan->device);
+  }
+  mk::ScanLaunch a;
+  morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0, (int)dtype);
+  if (st != MORLET_OK) return st;
+  // the row-serial schedule uses the header only; the tiles schedule also the tile states
+  const size_t need = a.serial ? sizeof(mk::WsHeader) : mk::workspace_bytes(plan->K, ntiles);
+  if (need > mk::kScratchBytes)
+    return fail(MORLET_ERR_WORKSPACE, "the launch needs " + std::to_string(need) +
+                                          " bytes of workspace, more than the fixed scratch of " +
+                                          std::to_string(mk::kScratchBytes) + " bytes");
+  a.x = x;
+  a.dtype = (int)dtype;
+  a.out = W;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // every call clears what the launch reads as its start state (header and tile flags): the
+  // array keeps the previous call's contents, which may come from a plan of another shape
+  hipError_t e = mk::launch_zero_fill(ws, need, s);
+  if (e == hipSuccess) e = mk::launch_scan(a, mk::kVarForward, 0, s);
+  if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
+  return MORLET_OK;
 }
 
 morlet_status morlet_backward_workspace_size(morlet_plan_t plan, size_t* bytes) {

@@ -8,6 +8,7 @@
 #include "boundary.h"
 #include "image2d.h"
 #include "multiply.h"
+#include "noalloc.h"
 
 namespace mk {
 
@@ -40,5 +41,7 @@ hipError_t launch_edge_extend(const void*, int, int64_t, int64_t, float*, hipStr
 hipError_t launch_pad_center(const void*, int, int64_t, int64_t, void*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_edge_fold(const float*, int64_t, int64_t, float*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_reverse(const float*, float*, int64_t, hipStream_t) { return hipErrorNoDevice; }
+hipError_t scratch_setup(int) { return hipErrorNoDevice; }
+void* scratch_ptr(int) { return nullptr; }
 
 }  // namespace mk
