@@ -29,7 +29,8 @@ constexpr int kQueues = 8;
 // the scale. Complex entry e, term i is stored as re at [(2e) K + i], im at
 // [(2e+1) K + i]; the K values of one entry are contiguous (one scalar load).
 // The table exists three times: float32 entries, then float64 entries, then the float32
-// remainders (float64 entry minus float32 entry, rounded) for float-float arithmetic.
+// remainders (float64 entry minus float32 entry, rounded) for float-float arithmetic; a fourth
+// section holds the run matrices of the matrix-core recurrence (below).
 // ---------------------------------------------------------------------------------
 struct TabLayout {
   int K, R;
@@ -69,7 +70,21 @@ struct TabLayout {
   MK_HD int nValues() const { return vHC(K); }
   MK_HD size_t f32Bytes() const { return ((size_t)nValues() * 4 + 255) / 256 * 256; }
   MK_HD size_t f64Bytes() const { return ((size_t)nValues() * 8 + 255) / 256 * 256; }
-  MK_HD size_t bytes() const { return 2 * f32Bytes() + f64Bytes(); }
+  // Fourth section (float32): the run of kRun = 16 positions as one linear map, for the matrix
+  // cores. Output o[r] (r < 16) of a run with input differences dy[r'] and state S before the
+  // run is, per output component (real part, imaginary part),
+  //   o[r] = sum_{r' <= r} Tc[r][r'] dy[r'] + sum_k Cc[r][k] S[k] + Y y[r - 2L]
+  // with S[2t] = Re v_t, S[2t + 1] = Im v_t. Tre, Tim: 16 x 16 row-major; Cre, Cim: 16 x mCW()
+  // row-major (the state components padded with zero columns to a multiple of 4).
+  static constexpr int kRun = 16;
+  MK_HD int mCW() const { return 4 * ((2 * K + 3) / 4); }
+  MK_HD size_t mfmaOff() const { return 2 * f32Bytes() + f64Bytes(); }
+  MK_HD int mTre() const { return 0; }
+  MK_HD int mTim() const { return kRun * kRun; }
+  MK_HD int mCre() const { return 2 * kRun * kRun; }
+  MK_HD int mCim() const { return 2 * kRun * kRun + kRun * mCW(); }
+  MK_HD size_t mfmaBytes() const { return (((size_t)2 * kRun * kRun + (size_t)2 * kRun * mCW()) * 4 + 255) / 256 * 256; }
+  MK_HD size_t bytes() const { return 2 * f32Bytes() + f64Bytes() + mfmaBytes(); }
 };
 
 // One scan row: one signal filtered at one scale. Scan positions j = 0 .. jend-1;

@@ -382,6 +382,40 @@ void fill_table(unsigned char* dst, int kind, int K, int R, int64_t L, int P_S, 
   // float32 remainders of every entry, for float-float arithmetic
   float* tl = (float*)(dst + lay.f32Bytes() + lay.f64Bytes());
   for (int v = 0; v < lay.nValues(); ++v) tl[v] = (float)(td[v] - (double)tf[v]);
+  // run matrices of the matrix-core recurrence (Morlet output): with v_t after r + 1 steps
+  //   v_t[r] = a_t^{r+1} S_t + sum_{r' <= r} a_t^{r - r'} dy[r'],
+  //   o_re = gre A + gim B, o_im = gim A - gre B, A = cx y + sum_t mw_t Re v_t, B = sum_t lw_t Im v_t
+  if (kind == 0) {
+    float* tm = (float*)(dst + lay.mfmaOff());
+    const int RN = TabLayout::kRun, CW = lay.mCW();
+    std::vector<double> Tre(RN * RN, 0.0), Tim(RN * RN, 0.0), Cre(RN * CW, 0.0), Cim(RN * CW, 0.0);
+    for (int i = 0; i < K; ++i) {
+      const int64_t p = P_S + i;
+      const double mw = td[lay.rMW() * K + i], lw = td[lay.rLW() * K + i];
+      for (int r = 0; r < RN; ++r) {
+        for (int rp = 0; rp <= r; ++rp) {
+          double re, im;
+          apow(p, r - rp, L, alpha, re, im);
+          Tre[RN * r + rp] += gre * mw * re + gim * lw * im;
+          Tim[RN * r + rp] += gim * mw * re - gre * lw * im;
+        }
+        double re, im;
+        apow(p, r + 1, L, alpha, re, im);
+        Cre[CW * r + 2 * i] = gre * mw * re + gim * lw * im;
+        Cre[CW * r + 2 * i + 1] = -gre * mw * im + gim * lw * re;
+        Cim[CW * r + 2 * i] = gim * mw * re - gre * lw * im;
+        Cim[CW * r + 2 * i + 1] = -gim * mw * im - gre * lw * re;
+      }
+    }
+    for (int v = 0; v < RN * RN; ++v) {
+      tm[lay.mTre() + v] = (float)Tre[v];
+      tm[lay.mTim() + v] = (float)Tim[v];
+    }
+    for (int v = 0; v < RN * CW; ++v) {
+      tm[lay.mCre() + v] = (float)Cre[v];
+      tm[lay.mCim() + v] = (float)Cim[v];
+    }
+  }
 }
 
 bool build_table(morlet_plan_s* p, std::string* err) {

@@ -59,6 +59,13 @@ namespace {
 
 enum { kFwd = 0, kAdj = 1, kPg = 2 };
 
+// The matrix-core evaluation of the per-thread run (below) computes the same outputs as the
+// vector-ALU recurrence with a third fewer vector instructions, but on the ragged scalogram it
+// measured 1.70 ms per launch against 1.58 ms: the kernel is bound by the latency of its per-tile
+// dependency chain, not by vector issue, and the run's operand loads lengthen that chain. Off
+// until the chain is shortened.
+constexpr bool kMatrixRun = false;
+
 // four floats as a clang vector (what the nontemporal-store builtin takes); outputs are
 // written once and never re-read by the kernel, so they bypass the cache hierarchy's reuse
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -135,6 +142,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
   constexpr int kSub = R < 16 ? R : 16;                     // positions per thread per store round
   static_assert(R % kSub == 0, "R must be a multiple of the store sub-run");
   constexpr int kStride = (kStash ? 2 * NS * R : kSub * (kCplxOut ? 2 : 1)) + 4;   // floats per thread
+  // Morlet forward, R = 16, float32 recurrence: each thread's run of 16 positions is evaluated as
+  // one linear map on the matrix cores (v_mfma_f32_16x16x4_f32), outputs = Tc dy + Cc S + Y y
+  // per component (the run matrices of the table's fourth section), instead of 16 steps of the
+  // K-term recurrence and combination on the vector ALUs. The stash then holds the run's input
+  // differences dy (16 floats) and the thread's state S before the run (2K floats, zero-padded
+  // to a multiple of 4); y[j - 2L] is read again from the input (a cache hit).
+  constexpr int NKB_C = (2 * K + 3) / 4;   // k-blocks of four state components
+  constexpr bool MFMA = kMatrixRun && VAR == kFwd && KIND == 0 && R == 16 && (F32T || ACC == kAccMixed) && NS == 1 &&
+                        16 + 4 * NKB_C <= kStride;
   __shared__ __align__(16) float s_out[kWaves][(VAR == kPg && !kStash) ? 4 : 64 * kStride];
 
   WsHeader* hdr = static_cast<WsHeader*>(P.ws);
@@ -308,7 +324,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       };
       float* stash = &s_out[wid][0] + lane * kStride;
       auto keep = [&](int q, const float (&ya)[NS][4], const float (&yb)[NS][4]) {
-        if constexpr (kStash && NS == 1) {
+        if constexpr (MFMA) {
+          float d[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) d[r] = (float)((sc_t)ya[0][r] - Dd * (sc_t)yb[0][r]);
+          *reinterpret_cast<float4*>(stash + 4 * q) = make_float4(d[0], d[1], d[2], d[3]);
+        } else if constexpr (kStash && NS == 1) {
           *reinterpret_cast<float4*>(stash + 8 * q) = make_float4(ya[0][0], yb[0][0], ya[0][1], yb[0][1]);
           *reinterpret_cast<float4*>(stash + 8 * q + 4) = make_float4(ya[0][2], yb[0][2], ya[0][3], yb[0][3]);
         } else if constexpr (kStash) {
@@ -327,9 +348,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         for (int q = 0; q < R / 4; ++q) {
           float ya[NS][4], yb[NS][4];
           load_quad_fast(j0 + 4 * q, ya, yb);
-          keep(q, ya, yb);
+          if constexpr (!MFMA) keep(q, ya, yb);
 #pragma unroll
           for (int r = 0; r < 4; ++r) dyd[4 * q + r] = (sc_t)ya[0][r] - Dd * (sc_t)yb[0][r];
+          if constexpr (MFMA)
+            *reinterpret_cast<float4*>(stash + 4 * q) = make_float4((float)dyd[4 * q], (float)dyd[4 * q + 1],
+                                                                    (float)dyd[4 * q + 2], (float)dyd[4 * q + 3]);
         }
 #pragma unroll
         for (int t = 0; t < K; ++t) {
@@ -650,6 +674,64 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       const acc_t cx = tab.scalar(lay.sCX());
       const acc_t gre = tab.scalar(lay.sGre()), gim = tab.scalar(lay.sGim());
       const int64_t nb = j0 - row.jout0;   // output index of the thread's first position
+      // store sub-run u: element e (0 <= e < 64 kSub) is lane e / kSub's position
+      // kSub u + e % kSub, output nw + (e / kSub) R + kSub u + e % kSub. Lane l handles
+      // e = G l + 64 G i (G = 2 complex or 4 real per 16-byte word; G = 1 when not whole or
+      // unaligned), so one base address per lane plus a fixed stride per i.
+      auto flush = [&](int u) {
+        wave_lds_sync();
+        constexpr int C = kCplxOut ? 2 : 1;                 // floats per output
+        const int64_t nw = jt + (int64_t)wid * 64 * R - row.jout0;   // output of the wave's first position
+        const bool whole = nw >= 0 && nw + 64 * R <= row.N;
+        const float* sw = &s_out[wid][0] + (kStash ? kSub * u : 0) * C;
+        const int64_t n0u = nw + kSub * u;                  // output of lane 0's first element
+        if constexpr (VAR == kFwd && !GAUSS) {
+          float2* W = static_cast<float2*>(P.out) + row.w_off;
+          if (whole && (reinterpret_cast<uintptr_t>(W + nw) & 15) == 0) {
+            constexpr int LPR = kSub / 2;                   // lanes per sub-run
+            const float* sp = sw + (lane / LPR) * kStride + 2 * (lane % LPR) * C;
+            float2* wp = W + n0u + (int64_t)(lane / LPR) * R + 2 * (lane % LPR);
+#pragma unroll
+            for (int i = 0; i < kSub / 2; ++i)
+              __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(sp + i * (64 / LPR) * kStride),
+                                          reinterpret_cast<v4f*>(wp + (int64_t)i * (64 / LPR) * R));
+          } else {
+            const float* sp = sw + (lane / kSub) * kStride + (lane % kSub) * C;
+            const int64_t nl = n0u + (int64_t)(lane / kSub) * R + (lane % kSub);
+#pragma unroll 1
+            for (int i = 0; i < kSub; ++i) {
+              const int64_t n = nl + (int64_t)i * (64 / kSub) * R;
+              if (n >= 0 && n < row.N) W[n] = *reinterpret_cast<const float2*>(sp + i * (64 / kSub) * kStride);
+            }
+          }
+        } else {
+          float* Y = static_cast<float*>(P.out) + row.w_off;
+          // forward (Gaussian): Y[n]; adjoint: written time-reversed, Y[N - 1 - n]
+          constexpr bool rev = VAR == kAdj;
+          if (whole && (reinterpret_cast<uintptr_t>(rev ? Y + (row.N - 4 - nw) : Y + nw) & 15) == 0) {
+            constexpr int LPR = kSub / 4;
+            const float* sp = sw + (lane / LPR) * kStride + 4 * (lane % LPR);
+            const int64_t nl = n0u + (int64_t)(lane / LPR) * R + 4 * (lane % LPR);
+            float* yp = rev ? Y + (row.N - 4 - nl) : Y + nl;
+#pragma unroll
+            for (int i = 0; i < kSub / 4; ++i) {
+              const v4f v = *reinterpret_cast<const v4f*>(sp + i * (64 / LPR) * kStride);
+              if constexpr (rev) __builtin_nontemporal_store(v.wzyx, reinterpret_cast<v4f*>(yp - (int64_t)i * (64 / LPR) * R));
+              else __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(yp + (int64_t)i * (64 / LPR) * R));
+            }
+          } else {
+            const float* sp = sw + (lane / kSub) * kStride + (lane % kSub);
+            const int64_t nl = n0u + (int64_t)(lane / kSub) * R + (lane % kSub);
+#pragma unroll 1
+            for (int i = 0; i < kSub; ++i) {
+              const int64_t n = nl + (int64_t)i * (64 / kSub) * R;
+              if (n >= 0 && n < row.N) Y[rev ? row.N - 1 - n : n] = sp[i * (64 / kSub) * kStride];
+            }
+          }
+        }
+        // the next sub-run's stage writes stay behind this one's reads
+        __builtin_amdgcn_wave_barrier();
+      };
 
       if constexpr (VAR == kPg) {
         // reductions against the cotangent at the output positions n = j - jout0:
@@ -732,6 +814,97 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
           for (int w = 0; w < kWaves; ++w) sacc += s_red[w * NRED + tid];
           P.partials[(size_t)tile * NRED + tid] = sacc;
         }
+      } else if constexpr (MFMA) {
+        // The run of thread c (positions j0(c) + r, r < 16) as a 16 x 16 x 4 product per group of
+        // 16 threads: D[r][c'] = sum_k A[r][k] B[k][c'] with c = 16 g + c'. Lane l supplies
+        // A[l % 16][l / 16] and B[l / 16][l % 16] of each k-block and receives D[4 (l / 16) + v][l % 16],
+        // v < 4. The k-blocks' K index is permuted so that lane l supplies, for the Toeplitz part,
+        // the input differences dy[4 (l / 16) + kb] of its chunk (kb = 0..3: one 16-byte LDS read)
+        // and, for the state part, components NKB_C (l / 16) + kb; its results are the outputs
+        // r = 4 (l / 16) + v of chunk c, i.e. four consecutive positions.
+        if (!wave_dead) {
+          float* slot = &s_out[wid][0] + lane * kStride;
+          {
+            float st[4 * NKB_C];
+#pragma unroll
+            for (int k = 0; k < 4 * NKB_C; ++k) st[k] = k < 2 * K ? (float)((k & 1) ? vi[k >> 1] : vr[k >> 1]) : 0.0f;
+#pragma unroll
+            for (int k = 0; k < NKB_C; ++k)
+              *reinterpret_cast<float4*>(slot + 16 + 4 * k) = make_float4(st[4 * k], st[4 * k + 1], st[4 * k + 2], st[4 * k + 3]);
+          }
+          // the lane's operands from memory: its run-matrix entries and y[j - 2L] of the four
+          // chunks it computes (one request each, all in flight together)
+          const int i16 = lane & 15, q = lane >> 4;
+          const float* tm = reinterpret_cast<const float*>(tb + lay.mfmaOff());
+          const float4 m_tre = *reinterpret_cast<const float4*>(tm + lay.mTre() + 16 * i16 + 4 * q);
+          const float4 m_tim = *reinterpret_cast<const float4*>(tm + lay.mTim() + 16 * i16 + 4 * q);
+          float m_cre[NKB_C], m_cim[NKB_C], m_y[4][4];
+#pragma unroll
+          for (int kb = 0; kb < NKB_C; ++kb) {
+            m_cre[kb] = tm[lay.mCre() + lay.mCW() * i16 + NKB_C * q + kb];
+            m_cim[kb] = tm[lay.mCim() + lay.mCW() * i16 + NKB_C * q + kb];
+          }
+          {
+            const void* xs = static_cast<const char*>(P.x) + row.x_off * (DT == 0 ? 4 : 2);
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+              load4(xs, DT, jt + (int64_t)(wid * 64 + 16 * g + i16) * R + 4 * q - 2 * row.L, row.N, m_y[g]);
+          }
+          wave_lds_sync();
+          const float yre = (float)(gre * cx), yim = (float)(gim * cx);
+          // two groups at a time: four independent accumulation chains keep the matrix core busy
+#pragma unroll
+          for (int gp = 0; gp < 4; gp += 2) {
+            float* sl[2];
+            float4 d4[2];
+            float sc[2][NKB_C];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              sl[h] = &s_out[wid][0] + (16 * (gp + h) + i16) * kStride;
+              d4[h] = *reinterpret_cast<const float4*>(sl[h] + 4 * q);
+#pragma unroll
+              for (int kb = 0; kb < NKB_C; ++kb) sc[h][kb] = sl[h][16 + NKB_C * q + kb];
+            }
+            v4f dre[2], dim[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              dre[h] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+              dim[h] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+            const float tr[4] = {m_tre.x, m_tre.y, m_tre.z, m_tre.w}, ti[4] = {m_tim.x, m_tim.y, m_tim.z, m_tim.w};
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+              const float dv[2] = {kb == 0 ? d4[0].x : kb == 1 ? d4[0].y : kb == 2 ? d4[0].z : d4[0].w,
+                                   kb == 0 ? d4[1].x : kb == 1 ? d4[1].y : kb == 2 ? d4[1].z : d4[1].w};
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                dre[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kb], dv[h], dre[h], 0, 0, 0);
+                dim[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kb], dv[h], dim[h], 0, 0, 0);
+              }
+            }
+#pragma unroll
+            for (int kb = 0; kb < NKB_C; ++kb) {
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                dre[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(m_cre[kb], sc[h][kb], dre[h], 0, 0, 0);
+                dim[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(m_cim[kb], sc[h][kb], dim[h], 0, 0, 0);
+              }
+            }
+            // outputs r = 4 q + v of each chunk go to floats 2 r, 2 r + 1 of its slot (read above by
+            // this group only, before these writes)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const float* y = m_y[gp + h];
+              *reinterpret_cast<float4*>(sl[h] + 8 * q) =
+                  make_float4(fmaf(yre, y[0], dre[h][0]), fmaf(yim, y[0], dim[h][0]), fmaf(yre, y[1], dre[h][1]),
+                              fmaf(yim, y[1], dim[h][1]));
+              *reinterpret_cast<float4*>(sl[h] + 8 * q + 4) =
+                  make_float4(fmaf(yre, y[2], dre[h][2]), fmaf(yim, y[2], dim[h][2]), fmaf(yre, y[3], dre[h][3]),
+                              fmaf(yim, y[3], dim[h][3]));
+            }
+          }
+          flush(0);
+        }
       } else {
         // outputs n = j - jout0, in sub-runs of kSub positions per thread: each thread writes
         // a sub-run to the wave's LDS stage, then the wave stores the 64 sub-runs with
@@ -787,64 +960,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
             // p / (2 NS), which an earlier quad (or this one, before writing) has read
             *reinterpret_cast<float4*>(stg + 4 * qs) = make_float4(o0[0], o0[1], o0[2], o0[3]);
           }
-        };
-        // store sub-run u: element e (0 <= e < 64 kSub) is lane e / kSub's position
-        // kSub u + e % kSub, output nw + (e / kSub) R + kSub u + e % kSub. Lane l handles
-        // e = G l + 64 G i (G = 2 complex or 4 real per 16-byte word; G = 1 when not whole or
-        // unaligned), so one base address per lane plus a fixed stride per i.
-        auto flush = [&](int u) {
-          wave_lds_sync();
-          constexpr int C = kCplxOut ? 2 : 1;                 // floats per output
-          const int64_t nw = jt + (int64_t)wid * 64 * R - row.jout0;   // output of the wave's first position
-          const bool whole = nw >= 0 && nw + 64 * R <= row.N;
-          const float* sw = &s_out[wid][0] + (kStash ? kSub * u : 0) * C;
-          const int64_t n0u = nw + kSub * u;                  // output of lane 0's first element
-          if constexpr (VAR == kFwd && !GAUSS) {
-            float2* W = static_cast<float2*>(P.out) + row.w_off;
-            if (whole && (reinterpret_cast<uintptr_t>(W + nw) & 15) == 0) {
-              constexpr int LPR = kSub / 2;                   // lanes per sub-run
-              const float* sp = sw + (lane / LPR) * kStride + 2 * (lane % LPR) * C;
-              float2* wp = W + n0u + (int64_t)(lane / LPR) * R + 2 * (lane % LPR);
-#pragma unroll
-              for (int i = 0; i < kSub / 2; ++i)
-                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(sp + i * (64 / LPR) * kStride),
-                                            reinterpret_cast<v4f*>(wp + (int64_t)i * (64 / LPR) * R));
-            } else {
-              const float* sp = sw + (lane / kSub) * kStride + (lane % kSub) * C;
-              const int64_t nl = n0u + (int64_t)(lane / kSub) * R + (lane % kSub);
-#pragma unroll 1
-              for (int i = 0; i < kSub; ++i) {
-                const int64_t n = nl + (int64_t)i * (64 / kSub) * R;
-                if (n >= 0 && n < row.N) W[n] = *reinterpret_cast<const float2*>(sp + i * (64 / kSub) * kStride);
-              }
-            }
-          } else {
-            float* Y = static_cast<float*>(P.out) + row.w_off;
-            // forward (Gaussian): Y[n]; adjoint: written time-reversed, Y[N - 1 - n]
-            constexpr bool rev = VAR == kAdj;
-            if (whole && (reinterpret_cast<uintptr_t>(rev ? Y + (row.N - 4 - nw) : Y + nw) & 15) == 0) {
-              constexpr int LPR = kSub / 4;
-              const float* sp = sw + (lane / LPR) * kStride + 4 * (lane % LPR);
-              const int64_t nl = n0u + (int64_t)(lane / LPR) * R + 4 * (lane % LPR);
-              float* yp = rev ? Y + (row.N - 4 - nl) : Y + nl;
-#pragma unroll
-              for (int i = 0; i < kSub / 4; ++i) {
-                const v4f v = *reinterpret_cast<const v4f*>(sp + i * (64 / LPR) * kStride);
-                if constexpr (rev) __builtin_nontemporal_store(v.wzyx, reinterpret_cast<v4f*>(yp - (int64_t)i * (64 / LPR) * R));
-                else __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(yp + (int64_t)i * (64 / LPR) * R));
-              }
-            } else {
-              const float* sp = sw + (lane / kSub) * kStride + (lane % kSub);
-              const int64_t nl = n0u + (int64_t)(lane / kSub) * R + (lane % kSub);
-#pragma unroll 1
-              for (int i = 0; i < kSub; ++i) {
-                const int64_t n = nl + (int64_t)i * (64 / kSub) * R;
-                if (n >= 0 && n < row.N) Y[rev ? row.N - 1 - n : n] = sp[i * (64 / kSub) * kStride];
-              }
-            }
-          }
-          // the next sub-run's stage writes stay behind this one's reads
-          __builtin_amdgcn_wave_barrier();
         };
         // fast_in differs between the lanes of a wave, so each sub-run's quads run on either
         // path and the wave reconverges before the cooperative store

@@ -20,8 +20,20 @@ def host_workers(cap: int = 16) -> int:
     return max(1, min(cap, n))
 
 
+def _one_thread():
+    """Worker initializer: one BLAS/OpenMP thread per worker (the pool already fills the host's
+    cores; a thread pool per worker, sized by OMP_NUM_THREADS, would oversubscribe them)."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
 def pool(workers: int | None = None) -> ProcessPoolExecutor:
-    return ProcessPoolExecutor(max_workers=workers or host_workers(), mp_context=mp.get_context("spawn"))
+    return ProcessPoolExecutor(max_workers=workers or host_workers(), mp_context=mp.get_context("spawn"),
+                               initializer=_one_thread)
 
 
 def mapper(ex: ProcessPoolExecutor, chunksize: int = 16):
