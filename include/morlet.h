@@ -39,6 +39,9 @@
  *    with no side effect. A failed HIP launch returns MORLET_ERR_HIP. Asynchronous faults
  *    show up at the caller's next synchronisation. morlet_last_error() returns a message
  *    for the calling thread's last failure.
+ *  - Diagnostics: with the environment variable MORLET_LOG set (not "0"), plan creation, the
+ *    term chooser and the autotuner print their choices (window, lowest order, kernel error,
+ *    tile shape) on stderr.
  */
 #ifndef MORLET_H_
 #define MORLET_H_
@@ -310,7 +313,12 @@ morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule sched
  * synchronizes the stream, so it must not run under graph capture. R_out, schedule_out
  * (nullable) report the choice (MORLET_SCHED_TILES or MORLET_SCHED_ROWS). Errors as
  * morlet_forward, MORLET_ERR_ALLOC if the trial workspace cannot be allocated; on error the
- * plan keeps its tile shape and schedule. */
+ * plan keeps its tile shape and schedule.
+ * Persisted choices: when the environment variable MORLET_TUNE_CACHE names a file, a choice
+ * is appended to it as one text line (key, R, schedule, time per launch), the key made of the
+ * device architecture and the launch shape (plan kind, mode, accumulation, dtype, K, batch
+ * shape, total scan positions and largest window in powers of two); a later call whose key is in
+ * the file applies the recorded choice without timing (the last line for a key wins). */
 morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* out, int32_t reps,
                                    int32_t* R_out, int32_t* schedule_out, void* stream);
 
@@ -359,6 +367,26 @@ morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int
  * R = 16; MORLET_ERR_HIP if the array's address cannot be resolved or a launch fails. */
 #define MORLET_NOALLOC_SCRATCH_BYTES (8u << 20)
 morlet_status morlet_forward_noalloc(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W, void* stream);
+
+/* Number of terms for an accuracy target (the tuner's choice of K and L): for K = 1, 2, ...,
+ * MORLET_MAX_TERMS, the window of smallest kernel error (the L = 0 rule of morlet_plan) and its
+ * fit's relative RMSE on [-L, L] (Sec. V-A chooses the window by minimum error; the error falls
+ * with the number of terms, Table 1); returns the first K whose error is at most target, with
+ * that L and error. Host only (no device). Errors: MORLET_ERR_INVALID_ARG (sigma, xi or target
+ * not finite and > 0, null outputs), MORLET_ERR_UNSUPPORTED when no K up to MORLET_MAX_TERMS
+ * reaches the target (the outputs then hold the most accurate K). */
+morlet_status morlet_choose_terms(double sigma, double xi, double target_relrmse, int32_t* K, int64_t* L,
+                                  double* relrmse);
+/* The same for Gaussian smoothing (orders 0..K-1, eq. aproGauss). */
+morlet_status morlet_choose_terms_gauss(double sigma, double target_relrmse, int32_t* K, int64_t* L, double* relrmse);
+
+/* Test hook for callers' error paths: the nth following launch setup of any entry point
+ * (1 = the next) fails with `status` (one of the MORLET_ERR_ codes) instead of launching; later
+ * ones run normally. A call whose first launch is the failing one launches nothing; a call of
+ * several launches may stop after earlier ones, as it would on a real launch failure. nth = 0
+ * disarms. Process-wide. Errors: MORLET_ERR_INVALID_ARG (nth < 0, or a status that is not an
+ * error code). */
+morlet_status morlet_inject_failure(morlet_status status, int32_t nth);
 
 /* Device workspace bytes needed by forward/backward calls on this plan. */
 morlet_status morlet_workspace_size(morlet_plan_t plan, size_t* bytes);

@@ -13,7 +13,14 @@ from . import _abi
 from ._abi import (MORLET_ACC_AUTO, MORLET_ACC_F32, MORLET_ACC_F64, MORLET_ACC_KAHAN, MORLET_ACC_MIXED, MORLET_BF16, MORLET_F16, MORLET_F32,
                    MORLET_SCAN_ASFT, MORLET_SCAN_SFT, MorletError)
 
-__all__ = ["MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2DPlan", "Gabor2DPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
+def choose_terms(sigma: float, xi: float | None, target_relrmse: float) -> dict:
+    """Fewest Fourier terms K (with its error-optimal window L) whose fitted kernel reaches the
+    relative RMSE target; xi=None for Gaussian smoothing. Host-side (morlet_choose_terms)."""
+    K, L, e = _abi.morlet_choose_terms(float(sigma), float(xi or 0.0), float(target_relrmse), gauss=xi is None)
+    return {"K": K, "L": L, "kernel_relrmse": e}
+
+
+__all__ = ["choose_terms", "MorletPlan", "MultiplyPlan", "GaussPlan", "GaussDerivPlan", "Gauss2DPlan", "Gabor2DPlan", "ScalogramPlan", "MorletError", "torch_dtype_code", "morlet_transform",
            "MorletTransform"]
 
 _DT = {torch.float32: MORLET_F32, torch.float16: MORLET_F16, torch.bfloat16: MORLET_BF16}

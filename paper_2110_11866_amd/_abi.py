@@ -62,6 +62,9 @@ SIGNATURES = {
     "gauss_smooth_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "morlet_scalogram_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _vp, _vp, _sz, _vp]),
     "morlet_direct_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _i64, _vp]),
+    "morlet_choose_terms": (ctypes.c_int, [_dbl, _dbl, _dbl, _P(_i32), _P(_i64), _P(_dbl)]),
+    "morlet_choose_terms_gauss": (ctypes.c_int, [_dbl, _dbl, _P(_i32), _P(_i64), _P(_dbl)]),
+    "morlet_inject_failure": (ctypes.c_int, [ctypes.c_int, _i32]),
     "morlet_destroy": (None, [_vp]),
     "morlet_last_error": (ctypes.c_char_p, []),
 }
@@ -296,3 +299,19 @@ def morlet_plan_set_boundary(plan: int, boundary: int) -> None:
 def gauss_smooth2d_backward(plan: int, gy_ptr: int, gx_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
     check(lib().gauss_smooth2d_backward(plan, gy_ptr, gx_ptr, ws_ptr, ws_bytes, stream))
 
+
+def morlet_choose_terms(sigma: float, xi: float, target: float, gauss: bool = False, strict: bool = True):
+    """(K, L, kernel relRMSE) of the fewest terms reaching `target`; strict=False returns the
+    most accurate K instead of raising when no K reaches it."""
+    K, L, e = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_double()
+    if gauss:
+        st = lib().morlet_choose_terms_gauss(sigma, target, ctypes.byref(K), ctypes.byref(L), ctypes.byref(e))
+    else:
+        st = lib().morlet_choose_terms(sigma, xi, target, ctypes.byref(K), ctypes.byref(L), ctypes.byref(e))
+    if st != MORLET_OK and (strict or st != MORLET_ERR_UNSUPPORTED):
+        check(st)
+    return K.value, L.value, e.value
+
+
+def morlet_inject_failure(status: int, nth: int) -> None:
+    check(lib().morlet_inject_failure(status, nth))

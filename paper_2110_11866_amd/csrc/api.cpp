@@ -2,9 +2,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <limits>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <thread>
 #include <vector>
@@ -27,6 +34,24 @@ morlet_status fail(morlet_status s, const std::string& msg) {
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// MORLET_LOG set (to anything but "0"): plan diagnostics on stderr
+bool log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("MORLET_LOG");
+    return v && *v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+// morlet_inject_failure: the armed launch setup (counting down) fails with the armed status
+std::atomic<int> g_inject_after{0};
+std::atomic<int> g_inject_status{0};
+morlet_status injected() {
+  if (g_inject_after.load(std::memory_order_relaxed) <= 0) return MORLET_OK;
+  if (g_inject_after.fetch_sub(1, std::memory_order_relaxed) != 1) return MORLET_OK;
+  return fail((morlet_status)g_inject_status.load(std::memory_order_relaxed), "injected failure (morlet_inject_failure)");
+}
 
 int64_t default_n0(double sigma, int64_t L) {
   int64_t n0 = (int64_t)std::llround(sigma / 8.0);
@@ -81,6 +106,10 @@ morlet_status finish_plan(morlet_plan_s* p, morlet_plan_t* out) {
     delete p;
     return s;
   }
+  if (log_on())
+    std::fprintf(stderr, "morlet: plan %s N=%lld sigma=%.6g xi=%.6g K=%d L=%lld P_S=%d relrmse=%.3e\n",
+                 p->kind == 0 ? "morlet" : "gauss", (long long)p->N, p->sigma, p->xi, p->K, (long long)p->L, p->P_S,
+                 p->relrmse);
   *out = p;
   return MORLET_OK;
 }
@@ -306,6 +335,7 @@ morlet_status init_morlet_rows(morlet_plan_s* p, int B, int64_t len, double sigm
 // float64 gradient reductions resolve.
 morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int variant, int mom, int dtype,
                           bool recompute = false) {
+  if (const morlet_status inj = injected(); inj != MORLET_OK) return inj;
   const int64_t jend = plan->N + plan->L - plan->n0;
   const int64_t ntiles = plan->batched ? plan->ntiles : tiles_for(jend, plan->R);
   a = mk::ScanLaunch{};
@@ -1041,6 +1071,70 @@ morlet_status run_gabor2d_grad(morlet_plan_t plan, const void* x, int dtype, con
 }
 }  // namespace
 
+namespace {
+
+// Persisted autotuning (MORLET_TUNE_CACHE names a text file): one line per tuned plan shape,
+// "<key>\t<R>\t<rows>", the key made of the device's architecture and everything the launch
+// shape depends on (kind, mode, accumulation, input type, terms, batch shape and the sizes in
+// powers of two).
+std::mutex g_tune_mu;
+
+std::string tune_key(morlet_plan_t plan, int dtype) {
+  static std::string arch = [] {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return std::string("unknown");
+    }
+    return std::string(prop.gcnArchName);
+  }();
+  int64_t positions = 0, maxL = plan->L;
+  if (plan->batched) {
+    for (const mk::Row& r : plan->rows) positions += r.jend;
+    for (const ScaleParams& sp : plan->scales) maxL = std::max(maxL, sp.L);
+  } else {
+    positions = plan->N + plan->L;
+  }
+  auto lg = [](int64_t v) { int b = 0; while (v > 1) { v >>= 1; ++b; } return b; };
+  std::ostringstream k;
+  k << "arch=" << arch << " kind=" << plan->kind << " deriv=" << plan->deriv << " mult=" << (plan->multiply ? 1 : 0)
+    << " mode=" << plan->mode << " accum=" << plan->accum << " dtype=" << dtype << " K=" << plan->K
+    << " batched=" << (plan->batched ? 1 : 0) << " B=" << plan->B << " S=" << plan->S << " lgpos=" << lg(positions)
+    << " lgL=" << lg(maxL + 1);
+  return k.str();
+}
+
+bool tune_lookup(const std::string& key, int& R, int& rows) {
+  const char* path = std::getenv("MORLET_TUNE_CACHE");
+  if (!path || !*path) return false;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::ifstream in(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(in, line)) {   // the last entry for a key wins
+    const size_t t1 = line.find('\t');
+    if (t1 == std::string::npos || line.compare(0, t1, key) != 0 || t1 != key.size()) continue;
+    int r = 0, w = 0;
+    if (std::sscanf(line.c_str() + t1 + 1, "%d\t%d", &r, &w) == 2 && (r == 4 || r == 8 || r == 16 || r == 32)) {
+      R = r;
+      rows = w ? 1 : 0;
+      found = true;
+    }
+  }
+  return found;
+}
+
+void tune_store(const std::string& key, int R, int rows, float ms) {
+  const char* path = std::getenv("MORLET_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  std::ofstream out(path, std::ios::app);
+  out << key << '\t' << R << '\t' << rows << '\t' << ms << '\n';
+}
+
+}  // namespace
+
 extern "C" {
 
 morlet_status morlet_plan(morlet_plan_t* out, int64_t N, double sigma, double xi, int32_t K, int64_t L) {
@@ -1498,6 +1592,23 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
   if (reps < 1 || reps > 1000) return fail(MORLET_ERR_INVALID_ARG, "reps must be in [1, 1000]");
   if ((int)dtype < 0 || (int)dtype > 2) return fail(MORLET_ERR_UNSUPPORTED, "unknown dtype");
   if (!plan->d_tab) return fail(MORLET_ERR_HIP, "plan has no device table (created without a HIP device)");
+  const std::string key = tune_key(plan, (int)dtype);
+  {
+    int cR = 0, cRows = 0;
+    if (tune_lookup(key, cR, cRows)) {
+      const int R0 = plan->R;
+      morlet_status st = morlet_plan_set_tile(plan, cR);
+      if (st == MORLET_OK) {
+        if (plan->batched) plan->row_serial = cRows;
+        if (R_out) *R_out = cR;
+        if (schedule_out)
+          *schedule_out = plan->batched ? (cRows ? MORLET_SCHED_ROWS : MORLET_SCHED_TILES) : MORLET_SCHED_TILES;
+        if (log_on()) std::fprintf(stderr, "morlet: autotune cache hit %s -> R=%d rows=%d\n", key.c_str(), cR, cRows);
+        return MORLET_OK;
+      }
+      (void)morlet_plan_set_tile(plan, R0);   // a stale entry: tune again
+    }
+  }
   const int oldR = plan->R, oldSched = plan->row_serial;
   struct Cand { int R, rows; };
   std::vector<Cand> cands;
@@ -1567,6 +1678,12 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
   }
   st = morlet_plan_set_tile(plan, cands[best].R);
   plan->row_serial = plan->batched ? cands[best].rows : oldSched;
+  if (st == MORLET_OK) {
+    tune_store(key, cands[best].R, cands[best].rows, best_ms / (float)reps);
+    if (log_on())
+      std::fprintf(stderr, "morlet: autotune %s -> R=%d rows=%d (%.4f ms)\n", key.c_str(), cands[best].R,
+                   cands[best].rows, best_ms / (float)reps);
+  }
   if (R_out) *R_out = cands[best].R;
   if (schedule_out) *schedule_out = plan->batched ? (cands[best].rows ? MORLET_SCHED_ROWS : MORLET_SCHED_TILES) : MORLET_SCHED_TILES;
   return st;
@@ -1680,6 +1797,13 @@ morlet_status morlet_scalogram_plan(morlet_plan_t* out, int32_t B, const int64_t
   if (s != MORLET_OK) {
     morlet_destroy(p);
     return s;
+  }
+  if (log_on()) {
+    std::fprintf(stderr, "morlet: scalogram B=%d S=%d K=%d rows=%zu tiles=%lld\n", p->B, p->S, p->K, p->rows.size(),
+                 (long long)p->ntiles);
+    for (int q = 0; q < p->S; ++q)
+      std::fprintf(stderr, "morlet:   scale %d sigma=%.6g xi=%.6g L=%lld P_S=%d relrmse=%.3e\n", q, p->scales[q].sigma,
+                   p->scales[q].xi, (long long)p->scales[q].L, p->scales[q].P_S, p->scales[q].relrmse);
   }
   *out = p;
   return MORLET_OK;
@@ -1935,6 +2059,54 @@ morlet_status morlet_direct_forward(morlet_plan_t plan, const void* x, morlet_dt
                                               slabs, part, static_cast<float2*>(W), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(MORLET_ERR_HIP, std::string("launch failed: ") + hipGetErrorString(e));
   return MORLET_OK;
+}
+
+morlet_status morlet_inject_failure(morlet_status status, int32_t nth) {
+  if (nth < 0) return fail(MORLET_ERR_INVALID_ARG, "nth must be >= 0");
+  if (nth > 0 && (status == MORLET_OK || (int)status < 0 || (int)status > (int)MORLET_ERR_HIP))
+    return fail(MORLET_ERR_INVALID_ARG, "status must be one of the MORLET_ERR_ codes");
+  g_inject_status.store((int)status, std::memory_order_relaxed);
+  g_inject_after.store(nth, std::memory_order_relaxed);
+  return MORLET_OK;
+}
+
+static morlet_status choose_terms(double sigma, double xi, bool gauss, double target, int32_t* K, int64_t* L,
+                                  double* relrmse) {
+  if (!finite_pos(sigma) || (!gauss && !finite_pos(xi))) return fail(MORLET_ERR_INVALID_ARG, "sigma and xi must be finite and > 0");
+  if (!finite_pos(target)) return fail(MORLET_ERR_INVALID_ARG, "target must be finite and > 0");
+  if (!K || !L || !relrmse) return fail(MORLET_ERR_INVALID_ARG, "null output");
+  int bestK = 0;
+  int64_t bestL = 0;
+  double best = std::numeric_limits<double>::infinity();
+  for (int k = 1; k <= MORLET_MAX_TERMS; ++k) {
+    const int64_t l = mk::select_L(sigma, gauss ? 0.0 : xi, k, gauss);
+    const double e = mk::err_at_L(sigma, gauss ? 0.0 : xi, k, l, gauss);
+    if (log_on()) std::fprintf(stderr, "morlet: choose_terms sigma=%.6g K=%d L=%lld relrmse=%.3e\n", sigma, k, (long long)l, e);
+    if (e < best) {
+      best = e;
+      bestK = k;
+      bestL = l;
+    }
+    if (e <= target) {
+      *K = k;
+      *L = l;
+      *relrmse = e;
+      return MORLET_OK;
+    }
+  }
+  *K = bestK;
+  *L = bestL;
+  *relrmse = best;
+  return fail(MORLET_ERR_UNSUPPORTED, "no number of terms up to MORLET_MAX_TERMS reaches the target");
+}
+
+morlet_status morlet_choose_terms(double sigma, double xi, double target_relrmse, int32_t* K, int64_t* L,
+                                  double* relrmse) {
+  return choose_terms(sigma, xi, false, target_relrmse, K, L, relrmse);
+}
+
+morlet_status morlet_choose_terms_gauss(double sigma, double target_relrmse, int32_t* K, int64_t* L, double* relrmse) {
+  return choose_terms(sigma, 0.0, true, target_relrmse, K, L, relrmse);
 }
 
 const char* morlet_last_error(void) { return g_err.c_str(); }

@@ -190,7 +190,6 @@ int select_ps(double sigma, double xi, int K, int64_t L, double* best_err) {
   return best;
 }
 
-namespace {
 double err_at_L(double sigma, double xi, int K, int64_t L, bool gauss) {
   if (gauss) {
     std::vector<double> g, none;
@@ -203,7 +202,6 @@ double err_at_L(double sigma, double xi, int K, int64_t L, bool gauss) {
   select_ps(sigma, xi, K, L, &e);
   return e;
 }
-}  // namespace
 
 int64_t select_L(double sigma, double xi, int K, bool gauss) {
   // Grid L = round(c sigma), c = 1.50, 1.52, ..., 5.00, searched coarse to fine: every

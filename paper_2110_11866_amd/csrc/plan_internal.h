@@ -94,6 +94,8 @@ Fit fit_orders(const std::vector<double>& tre, const std::vector<double>& tim, i
 
 int select_ps(double sigma, double xi, int K, int64_t L, double* best_err);
 int64_t select_L(double sigma, double xi, int K, bool gauss);
+// kernel relRMSE of the K-term fit on [-L, L] (Morlet: at the best lowest order)
+double err_at_L(double sigma, double xi, int K, int64_t L, bool gauss);
 
 void jacobian(morlet_plan_s* p);
 // Fill p->h_tab for the plan's current mode and R; returns false on bad parameters.

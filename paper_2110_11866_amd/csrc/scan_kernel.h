@@ -131,6 +131,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
   __shared__ double s_e[kWaves][2 * KS];
   __shared__ double s_p[2 * KS];
   __shared__ double s_lb[2 * KS];                // look-back: a state vector on its way through Op
+  // row-serial schedule: the row's constants of the block-level combination (a^{16 R k}, k < 4,
+  // and a^{64 R w}, w <= kWaves, per term), copied from the table when a block takes a row, so the
+  // chain of combination steps reads LDS instead of waiting on memory at each step. Up to K = 5
+  // (the copy then fits beside the stash without costing a block per CU).
+  constexpr bool KCACHE = !MOM && K <= 5;
+  __shared__ double s_k[KCACHE ? 9 : 1][2 * K];
   __shared__ double s_red[(VAR == kPg) ? kWaves * NRED : 1];
   // Per-wave LDS slab, each thread's slots padded by 16 bytes. Forward and adjoint: the
   // thread's R input pairs (y[j], y[j-2L]; per stream for the adjoint's two) stashed by step 2
@@ -198,6 +204,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         __syncthreads();   // every wave has read s_tile before thread 0 may claim again
         if ((int64_t)r >= P.nrows) break;
         load_row(((cptr<int32_t>)P.row_order)[r], row);
+        if constexpr (KCACHE) {
+          const cptr<double> td = (cptr<double>)(P.tabs + (int64_t)row.scale * P.tab_stride + P.f32_bytes);
+          if (tid < 9 * K) {
+            const int slot = tid / K, t = tid % K;
+            const int e = slot < 4 ? lay.eLANE(16 * slot) : lay.eWV(slot - 4);
+            s_k[slot][2 * t] = td[(2 * e) * K + t];
+            s_k[slot][2 * t + 1] = td[(2 * e + 1) * K + t];
+          }
+          __syncthreads();
+        }
         ti = 0;
         row_left = row.ntiles;
         if (row_left == 0) continue;
@@ -409,6 +425,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       cmac(outr, outi, tabd.re(e, t), tabd.im(e, t), v[2 * lane], v[2 * lane + 1]);
       if (MOM && lane >= K) cmac(outr, outi, -tabd.re(mo + e, t), -tabd.im(mo + e, t), v[2 * t], v[2 * t + 1]);
     };
+    // the same with the constant of slot `slot` of the row's LDS copy (row-serial schedule)
+    auto op_c = [&](int slot, int e, const double* v, double& outr, double& outi) {
+      if constexpr (KCACHE) {
+        if (P.serial) {
+          const int t = lane % K;
+          outr = 0; outi = 0;
+          cmac(outr, outi, s_k[slot][2 * t], s_k[slot][2 * t + 1], v[2 * lane], v[2 * lane + 1]);
+          return;
+        }
+      }
+      op_lds(e, v, outr, outi);
+    };
 
     // 3. inclusive scan within each row of 16 lanes: S_l = sum_{m <= l, same row} Op(R (l - m)) B_m,
     //    where Op(d) multiplies a state by a^d (and, for a moment state, subtracts d a^d times
@@ -453,7 +481,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         double cr, ci;
-        op_lds(lay.eLANE(16 * (3 - r)), &s_rt[wid][r][0], cr, ci);
+        op_c(3 - r, lay.eLANE(16 * (3 - r)), &s_rt[wid][r][0], cr, ci);
         Ar += cr; Ai += ci;
       }
       s_wagg[par][wid][2 * lane] = Ar;
@@ -470,7 +498,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       wave_lds_sync();
       for (int w = 0; w < wid; ++w) {
         double cr = 0, ci = 0;
-        if (lane < KS) op_lds(lay.eWV(1), &s_e[wid][0], cr, ci);
+        if (lane < KS) op_c(5, lay.eWV(1), &s_e[wid][0], cr, ci);
         wave_lds_sync();
         if (lane < KS) {
           s_e[wid][2 * lane] = cr + s_wagg[par][w][2 * lane];
@@ -480,7 +508,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       }
       if (lane < KS) {
         double cr = 0, ci = 0;
-        if (ti > 0) op_lds(lay.eWV(wid), cin, cr, ci);
+        if (ti > 0) op_c(4 + wid, lay.eWV(wid), cin, cr, ci);
         s_xw[wid][2 * lane] = s_e[wid][2 * lane] + cr;
         s_xw[wid][2 * lane + 1] = s_e[wid][2 * lane + 1] + ci;
       }
@@ -489,11 +517,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int w = 0; w < kWaves; ++w) {
           double cr, ci;
-          op_lds(lay.eWV(kWaves - 1 - w), &s_wagg[par][w][0], cr, ci);
+          op_c(4 + kWaves - 1 - w, lay.eWV(kWaves - 1 - w), &s_wagg[par][w][0], cr, ci);
           Ar += cr; Ai += ci;
         }
         double cr = 0, ci = 0;
-        if (ti > 0) op_lds(lay.eWV(kWaves), cin, cr, ci);
+        if (ti > 0) op_c(4 + kWaves, lay.eWV(kWaves), cin, cr, ci);
         s_c[(ti + 1) & 1][2 * lane] = cr + Ar;
         s_c[(ti + 1) & 1][2 * lane + 1] = ci + Ai;
       }
@@ -648,12 +676,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
     //    only after this one.
     const bool has_out = (jt + T > row.jout0) && (row.jout0 + row.N > jt);
     if (has_out) {
+      // the thread's carry constants a^{R (l mod 16)}, requested before the chain of row states
+      // (where the registers allow: up to K = 5)
+      [[maybe_unused]] double kcr[K], kci[K];
+      if constexpr (KCACHE) {
+        const int e = lay.eLANE(lane & 15);
+#pragma unroll
+        for (int t = 0; t < K; ++t) { kcr[t] = tabd.re(e, t); kci[t] = tabd.im(e, t); }
+      }
       // Z_{r+1} overwrites T_r in place (each lane rewrites only its own state of it)
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         if (lane < KS) {
           double cr, ci;
-          op_lds(lay.eLANE(16), r == 0 ? &s_xw[wid][0] : &s_rt[wid][r - 1][0], cr, ci);
+          op_c(1, lay.eLANE(16), r == 0 ? &s_xw[wid][0] : &s_rt[wid][r - 1][0], cr, ci);
           s_rt[wid][r][2 * lane] += cr;
           s_rt[wid][r][2 * lane + 1] += ci;
         }
@@ -666,7 +702,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       for (int i = 0; i < KS; ++i) {
         const int t = i % K;
         double cr = (double)er[i], ci = (double)ei[i];
-        cmac(cr, ci, tabd.re(e, t), tabd.im(e, t), z[2 * i], z[2 * i + 1]);
+        if constexpr (KCACHE) cmac(cr, ci, kcr[t], kci[t], z[2 * i], z[2 * i + 1]);
+        else cmac(cr, ci, tabd.re(e, t), tabd.im(e, t), z[2 * i], z[2 * i + 1]);
         if (MOM && i >= K) cmac(cr, ci, -tabd.re(mo + e, t), -tabd.im(mo + e, t), z[2 * t], z[2 * t + 1]);
         vr[i] = (acc_t)cr;
         vi[i] = (acc_t)ci;

@@ -128,6 +128,19 @@ int main() {
   EXPECT(morlet_plan_set(p, MORLET_SCAN_ASFT, 0, MORLET_ACC_F32) == MORLET_OK);
   morlet_destroy(p);
   morlet_destroy(nullptr);
+  // term chooser and the failure hook (host only)
+  {
+    int32_t K = 0;
+    int64_t L = 0;
+    double e = 0;
+    EXPECT(morlet_choose_terms(16.0, 6.0 / 16.0, 1e-2, &K, &L, &e) == MORLET_OK && K >= 1 && e <= 1e-2);
+    EXPECT(morlet_choose_terms_gauss(8.0, 1e-4, &K, &L, &e) == MORLET_OK && e <= 1e-4);
+    EXPECT(morlet_choose_terms(16.0, 6.0 / 16.0, 1e-300, &K, &L, &e) == MORLET_ERR_UNSUPPORTED);
+    EXPECT(morlet_choose_terms(16.0, 6.0 / 16.0, 1e-2, nullptr, &L, &e) == MORLET_ERR_INVALID_ARG);
+    EXPECT(morlet_inject_failure(MORLET_ERR_HIP, -1) == MORLET_ERR_INVALID_ARG);
+    EXPECT(morlet_inject_failure(MORLET_OK, 2) == MORLET_ERR_INVALID_ARG);
+    EXPECT(morlet_inject_failure(MORLET_ERR_HIP, 0) == MORLET_OK);
+  }
   if (g_fail) std::fprintf(stderr, "%d checks failed\n", g_fail);
   else std::printf("abi driver: all checks passed\n");
   return g_fail ? 1 : 0;

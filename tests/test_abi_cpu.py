@@ -538,3 +538,44 @@ def test_workload_scales_lowest_order_chosen_by_oracle(which):
         scale = max(np.abs(m).max(), np.abs(l).max())
         assert np.allclose(info["cos_coef"], m, rtol=1e-9, atol=1e-12 * scale), (sg, L)
         assert np.allclose(info["sin_coef"], l, rtol=1e-9, atol=1e-12 * scale), (sg, L)
+
+
+def _oracle_err(sigma, xi, K, L, gauss):
+    k = np.arange(-L, L + 1)
+    if gauss:
+        return O.kernel_relrmse(O.kterm_gauss(O.plan_gauss(sigma, K, L)), O.gaussian(sigma, k))
+    return O.kernel_relrmse(O.kterm_morlet(O.plan_morlet(sigma, xi, K, L)), O.morlet(sigma, xi, k))
+
+
+@pytest.mark.parametrize("sigma,target,gauss", [(16.0, 1e-2, False), (40.0, 1e-3, False), (300.0, 3e-2, False),
+                                                (8.0, 1e-4, True), (64.0, 1e-6, True), (12.0, 5e-3, False)])
+def test_choose_terms_is_fewest_reaching_target(sigma, target, gauss):
+    # the chooser's error is the oracle's at the same (K, L); it reaches the target; one term
+    # fewer, at that count's own error-optimal window, does not
+    xi = 6.0 / sigma
+    K, L, e = _abi.morlet_choose_terms(sigma, xi, target, gauss=gauss)
+    assert 1 <= K <= _abi.MORLET_MAX_TERMS
+    # the library forms the residual from the normal equations (|g|^2 minus the projection), whose
+    # relative precision is a few ulps of |g|^2 over residual^2: 1e-7 at an error of 4e-5
+    assert math.isclose(e, _oracle_err(sigma, xi, K, L, gauss), rel_tol=max(1e-9, 1e-15 / e ** 2))
+    assert e <= target
+    if K > 1:
+        h = _abi.morlet_plan_gauss(100, sigma, K - 1, 0) if gauss else _abi.morlet_plan(100, sigma, xi, K - 1, 0)
+        try:
+            L1 = _abi.morlet_plan_info(h, K - 1)["L"]
+        finally:
+            _abi.morlet_destroy(h)
+        assert _oracle_err(sigma, xi, K - 1, L1, gauss) > target
+
+
+def test_choose_terms_reports_best_when_unreachable():
+    K, L, e = _abi.morlet_choose_terms(16.0, 6.0 / 16.0, 1e-30, strict=False)
+    assert K >= 1 and e > 1e-30
+    with pytest.raises(_abi.MorletError) as ex:
+        _abi.morlet_choose_terms(16.0, 6.0 / 16.0, 1e-30)
+    assert ex.value.status == _abi.MORLET_ERR_UNSUPPORTED
+    with pytest.raises(_abi.MorletError):
+        _abi.morlet_choose_terms(-1.0, 1.0, 1e-3)
+    with pytest.raises(_abi.MorletError):
+        _abi.morlet_inject_failure(_abi.MORLET_OK, 1)
+    _abi.morlet_inject_failure(_abi.MORLET_ERR_HIP, 0)   # disarmed
