@@ -52,8 +52,8 @@ def _parse():
     ap.add_argument("--mode", default="asft", choices=["sft", "asft"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", type=int, default=16, choices=[4, 8, 16, 32], help="samples per thread")
-    ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "rows"],
-                    help="batched launch schedule (scalogram, image2d and gabor2d workloads)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "rows", "segments"],
+                    help="launch schedule (rows: scalogram-shaped workloads; segments: one long row)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of this many MB (counter calibration for HBM bytes)")
     return ap.parse_args()
@@ -252,10 +252,15 @@ def bench_differentiation(args, torch, M):
     wt = torch.from_numpy(np.tile(w.reshape(1, S, N), (B, 1, 1)).reshape(-1)).to(dev)
     out = torch.empty(S * B * N, dtype=torch.complex64, device=dev)
     ws = plan.workspace(dev, backward=True)
+    # dLoss/dW = 2 w W: the constant 2 w is formed once, and the product runs on the float view
+    # of W (w broadcast over the real and imaginary parts) into a buffer kept across steps
+    w2 = (2 * wt).unsqueeze(-1)
+    g = torch.empty_like(out)
+    g_re = torch.view_as_real(g)
 
     def step():
         W = plan.forward(xt, out=out, ws=ws)
-        g = 2 * wt * W
+        torch.mul(torch.view_as_real(W), w2, out=g_re)
         return plan.backward(xt, g)
 
     ms_step, kern_ms = _timed(torch, step, args.steps, args.warmup)
@@ -290,7 +295,7 @@ def bench_gauss_deriv(args, torch, M):
     dev = torch.device("cuda:0")
     x = torch.randn(N, generator=torch.Generator().manual_seed(11)).to(dev)
     plan = M.GaussDerivPlan(N, sigma, K, 0, order=1, mode=args.mode)
-    plan.set_tile(args.tile)
+    plan.set_tile(args.tile).set_schedule(args.schedule)
     out = torch.empty(N, dtype=torch.float32, device=dev)
     ws = plan.workspace(dev)
     ms_step, kern_ms = _timed(torch, lambda: plan.forward(x, out=out, ws=ws), args.steps, args.warmup)
@@ -306,7 +311,7 @@ def bench_gauss_deriv(args, torch, M):
         "dtype": "f32",
         "config": {"workload": f"gauss_deriv: one float32 N(0,1) signal, N=2^26, sigma={sigma:g}, K={K} ({terms}), "
                                f"window L={info['L']} (error-optimal), float32 out",
-                   "tile_R": args.tile},
+                   "tile_R": args.tile, "schedule": args.schedule},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "kernel_ms": kern_ms,
@@ -454,7 +459,7 @@ def bench_paper_scale(args, torch, M):
     x = workloads.paper_scale_signal(N)
     xt = torch.from_numpy(x).to(dev)
     plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=args.mode)
-    plan.set_tile(args.tile)
+    plan.set_tile(args.tile).set_schedule(args.schedule)
     info = plan.info()
     out = torch.empty(N, dtype=torch.complex64, device=dev)
     ws = plan.workspace(dev)

@@ -292,26 +292,44 @@ morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R);
 typedef enum { MORLET_BOUNDARY_ZERO = 0, MORLET_BOUNDARY_EDGE = 1 } morlet_boundary;
 morlet_status morlet_plan_set_boundary(morlet_plan_t plan, morlet_boundary boundary);
 
-/* How a batched plan's launch distributes its rows (signal x scale) over the persistent
+/* How a plan's forward launch distributes its rows (signal x scale) over the persistent
  * blocks. MORLET_SCHED_TILES: blocks take single tiles in row order and resolve each
- * tile's incoming state with the decoupled look-back. MORLET_SCHED_ROWS: a block takes a
- * whole row (longest rows first) and carries the state from tile to tile itself, so no
- * block waits on another. MORLET_SCHED_AUTO (default): rows when the longest row has no
- * more tiles than one block's share of all tiles, else tiles. Single-signal plans always
- * use tiles. Both schedules are deterministic; they differ only in the float64 rounding of
- * the carried states. Host-only, no device work. */
-typedef enum { MORLET_SCHED_AUTO = 0, MORLET_SCHED_TILES = 1, MORLET_SCHED_ROWS = 2 } morlet_schedule;
+ * tile's incoming state with the decoupled look-back. MORLET_SCHED_ROWS (plans of several
+ * rows): a block takes a whole row (longest rows first) and carries the state from tile to
+ * tile itself, so no block waits on another. MORLET_SCHED_SEGMENTS (a launch of one row:
+ * single-signal plans, a scalogram of one signal and one scale): the row is cut into segments
+ * of equal tile counts, about two per resident block; a first launch runs every segment from a
+ * zero state without outputs and keeps its end state, a one-wave launch turns those into each
+ * segment's incoming state, and a second launch runs the segments again with outputs, each
+ * block carrying the state through its segment's tiles as in the rows schedule (the input is
+ * read twice; no block waits on another). Elsewhere it acts as AUTO. MORLET_SCHED_AUTO
+ * (default): rows when the longest row has no more tiles than one block's share of all tiles;
+ * segments for one row of at least two tiles per resident block; else tiles. The schedules are
+ * deterministic; they differ only in the float64 rounding of the carried states. The adjoint
+ * and gradient passes use tiles or rows. Host-only, no device work. */
+typedef enum {
+  MORLET_SCHED_AUTO = 0,
+  MORLET_SCHED_TILES = 1,
+  MORLET_SCHED_ROWS = 2,
+  MORLET_SCHED_SEGMENTS = 3
+} morlet_schedule;
 morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule schedule);
+
+/* Segments schedule: tiles per segment, 1..4096, or 0 (default) for the automatic length
+ * ceil(tiles / (2 x resident blocks)). The length sets the float64 rounding of the carried
+ * states, not the result otherwise. Host-only; MORLET_ERR_INVALID_ARG outside [0, 4096]. */
+morlet_status morlet_plan_set_segments(morlet_plan_t plan, int32_t tiles_per_segment);
 
 /* Autotuner: times this plan's forward launch on the caller's input x (device, dtype) for each
  * tile shape (R = 16, 32, 8, 4, in that order; a shape the plan cannot take is skipped) and,
- * for a scalogram plan, each schedule (tiles, rows): one warm-up launch, then `reps` launches
+ * each schedule the plan can take (tiles; rows for several rows; segments for one row, except
+ * multiplication-method plans): one warm-up launch, then `reps` launches
  * (1..1000) timed with HIP events on `stream`; keeps the fastest (ties: the earlier
  * candidate) as the plan's tile shape and schedule. out (device) receives the
  * trial outputs: any buffer of the forward's output size, overwritten. A setup call: it
  * allocates and frees its own workspace and events, rebuilds the tables synchronously and
  * synchronizes the stream, so it must not run under graph capture. R_out, schedule_out
- * (nullable) report the choice (MORLET_SCHED_TILES or MORLET_SCHED_ROWS). Errors as
+ * (nullable) report the choice (MORLET_SCHED_TILES, _ROWS or _SEGMENTS). Errors as
  * morlet_forward, MORLET_ERR_ALLOC if the trial workspace cannot be allocated; on error the
  * plan keeps its tile shape and schedule.
  * Persisted choices: when the environment variable MORLET_TUNE_CACHE names a file, a choice
@@ -364,7 +382,9 @@ morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int
  * launched, when the launch needs more than the array: the row-serial schedule of a scalogram
  * needs 64 bytes, the tiles schedule 64 bytes plus one tile state per tile of 256 R positions
  * (256 bytes at K <= 5, 640 at K = 12), so a single signal of up to about 2^27 samples at K = 5,
- * R = 16; MORLET_ERR_HIP if the array's address cannot be resolved or a launch fails. */
+ * R = 16; the segments schedule (the automatic choice for long single signals) 64 bytes plus
+ * 16 K bytes per segment (about two segments per resident block); MORLET_ERR_HIP if the
+ * array's address cannot be resolved or a launch fails. */
 #define MORLET_NOALLOC_SCRATCH_BYTES (8u << 20)
 morlet_status morlet_forward_noalloc(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* W, void* stream);
 

@@ -68,12 +68,19 @@ class _PlanBase:
         return self
 
     def set_schedule(self, schedule: str) -> "_PlanBase":
-        """Batched launches: "auto", "tiles" (look-back between tiles) or "rows" (a block
-        runs whole rows)."""
-        code = {"auto": _abi.MORLET_SCHED_AUTO, "tiles": _abi.MORLET_SCHED_TILES, "rows": _abi.MORLET_SCHED_ROWS}
+        """Forward launch schedule: "auto", "tiles" (look-back between tiles), "rows" (a block
+        runs whole rows; several rows) or "segments" (one long row in segments: a pass for
+        the segment states, then a pass with outputs)."""
+        code = {"auto": _abi.MORLET_SCHED_AUTO, "tiles": _abi.MORLET_SCHED_TILES, "rows": _abi.MORLET_SCHED_ROWS,
+                "segments": _abi.MORLET_SCHED_SEGMENTS}
         if schedule not in code:
-            raise ValueError("schedule must be auto, tiles or rows")
+            raise ValueError("schedule must be auto, tiles, rows or segments")
         _abi.morlet_plan_set_schedule(self.handle, code[schedule])
+        return self
+
+    def set_segments(self, tiles: int) -> "_PlanBase":
+        """Segments schedule: tiles per segment (0: automatic)."""
+        _abi.morlet_plan_set_segments(self.handle, int(tiles))
         return self
 
     def info(self) -> dict:
@@ -95,13 +102,14 @@ class _PlanBase:
 
     def autotune(self, x: torch.Tensor, reps: int = 5) -> dict:
         """Time the forward on x for each tile shape (and schedule, for scalograms) and keep
-        the fastest; returns {"R": 4 | 8 | 16 | 32, "schedule": "tiles" | "rows"}."""
+        the fastest; returns {"R": 4 | 8 | 16 | 32, "schedule": "tiles" | "rows" | "segments"}."""
         self._check_x(x)
         out = self._out_like(x)
         R, sched = _abi.morlet_plan_autotune(self.handle, x.data_ptr(), torch_dtype_code(x.dtype), out.data_ptr(),
                                              int(reps), _stream())
         self._ws = None
-        return {"R": R, "schedule": "rows" if sched == _abi.MORLET_SCHED_ROWS else "tiles"}
+        names = {_abi.MORLET_SCHED_ROWS: "rows", _abi.MORLET_SCHED_SEGMENTS: "segments"}
+        return {"R": R, "schedule": names.get(sched, "tiles")}
 
     def workspace_bytes(self) -> int:
         return _abi.morlet_workspace_size(self.handle)

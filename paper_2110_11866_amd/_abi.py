@@ -45,6 +45,7 @@ SIGNATURES = {
     "morlet_plan_refit": (ctypes.c_int, [_vp, _dbl, _dbl, _vp]),
     "morlet_plan_set_tile": (ctypes.c_int, [_vp, _i32]),
     "morlet_plan_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "morlet_plan_set_segments": (ctypes.c_int, [_vp, _i32]),
     "morlet_plan_autotune": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _i32, _P(_i32), _P(_i32), _vp]),
     "morlet_plan_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i32), _P(_i64), _P(_dbl), _P(_dbl), _P(_dbl),
                                         _P(_dbl), _P(_dbl)]),
@@ -177,11 +178,15 @@ def morlet_plan_set_tile(plan: int, R: int) -> None:
     check(lib().morlet_plan_set_tile(plan, R))
 
 
-MORLET_SCHED_AUTO, MORLET_SCHED_TILES, MORLET_SCHED_ROWS = 0, 1, 2
+MORLET_SCHED_AUTO, MORLET_SCHED_TILES, MORLET_SCHED_ROWS, MORLET_SCHED_SEGMENTS = 0, 1, 2, 3
 
 
 def morlet_plan_set_schedule(plan: int, schedule: int) -> None:
     check(lib().morlet_plan_set_schedule(plan, schedule))
+
+
+def morlet_plan_set_segments(plan: int, tiles: int) -> None:
+    check(lib().morlet_plan_set_segments(plan, tiles))
 
 
 def morlet_plan_autotune(plan: int, x: int, dtype: int, out: int, reps: int, stream: int) -> tuple[int, int]:

@@ -397,7 +397,29 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
       a.grid = (int)(a.nrows < cap ? a.nrows : cap);
     }
   }
+  // Segments schedule for a forward launch of one row: chosen, or automatic when the row has at
+  // least two tiles per resident block. About two segments per block (the ticket balances them),
+  // at most 64 x 64 tiles each (the reach of the table's look-back weights). The segment states
+  // sit in the workspace after its header (within what the tiles schedule needs).
+  a.nseg = 0;
+  if (variant == mk::kVarForward && a.nrows == 1 && ntiles >= 2 &&
+      (plan->row_serial == 2 || (plan->row_serial == -1 && ntiles >= 2 * cap))) {
+    int64_t len = plan->seg_tiles > 0 ? plan->seg_tiles : (ntiles + 2 * cap - 1) / (2 * cap);
+    if (len > (int64_t)mk::kLookback * mk::kLookback) len = (int64_t)mk::kLookback * mk::kLookback;
+    a.seg_len = (int)len;
+    a.nseg = (ntiles + len - 1) / len;
+    a.serial = 1;
+    a.grid = (int)(a.nseg < cap ? a.nseg : cap);
+    a.segstate = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + sizeof(mk::WsHeader));
+  }
   return MORLET_OK;
+}
+
+// Workspace bytes a forward launch reads and writes: the header; the tiles schedule adds a tile
+// state per tile, the segments schedule a float64 state vector per segment.
+size_t launch_ws_bytes(const mk::ScanLaunch& a, int K, int64_t ntiles) {
+  if (a.nseg > 0) return sizeof(mk::WsHeader) + (size_t)a.nseg * 2 * (size_t)K * sizeof(double);
+  return a.serial ? sizeof(mk::WsHeader) : mk::workspace_bytes(K, ntiles);
 }
 
 int64_t plan_ntiles_max(morlet_plan_t plan) {
@@ -1517,8 +1539,21 @@ morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule sched
     case MORLET_SCHED_AUTO: plan->row_serial = -1; return MORLET_OK;
     case MORLET_SCHED_TILES: plan->row_serial = 0; return MORLET_OK;
     case MORLET_SCHED_ROWS: plan->row_serial = 1; return MORLET_OK;
+    case MORLET_SCHED_SEGMENTS: plan->row_serial = 2; return MORLET_OK;
   }
   return fail(MORLET_ERR_INVALID_ARG, "unknown schedule");
+}
+
+morlet_status morlet_plan_set_segments(morlet_plan_t plan, int32_t tiles_per_segment) {
+  if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
+  if (tiles_per_segment < 0 || tiles_per_segment > mk::kLookback * mk::kLookback)
+    return fail(MORLET_ERR_INVALID_ARG, "tiles per segment must be in [0, 4096]");
+  if (plan->image2d) {
+    plan->axis[0]->seg_tiles = tiles_per_segment;
+    plan->axis[1]->seg_tiles = tiles_per_segment;
+  }
+  plan->seg_tiles = tiles_per_segment;
+  return MORLET_OK;
 }
 
 morlet_status morlet_plan_set_tile(morlet_plan_t plan, int32_t R) {
@@ -1585,6 +1620,11 @@ morlet_status morlet_plan_info(morlet_plan_t plan, int64_t* L, int32_t* P_S, int
   return MORLET_OK;
 }
 
+// the schedule of a plan's row_serial value (-1 automatic, 0 tiles, 1 rows, 2 segments)
+int32_t sched_of(int rows) {
+  return rows == 1 ? MORLET_SCHED_ROWS : rows == 2 ? MORLET_SCHED_SEGMENTS : rows == 0 ? MORLET_SCHED_TILES : MORLET_SCHED_AUTO;
+}
+
 morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dtype dtype, void* out, int32_t reps,
                                    int32_t* R_out, int32_t* schedule_out, void* stream) {
   if (!plan) return fail(MORLET_ERR_INVALID_ARG, "null plan");
@@ -1599,10 +1639,9 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
       const int R0 = plan->R;
       morlet_status st = morlet_plan_set_tile(plan, cR);
       if (st == MORLET_OK) {
-        if (plan->batched) plan->row_serial = cRows;
+        plan->row_serial = cRows;
         if (R_out) *R_out = cR;
-        if (schedule_out)
-          *schedule_out = plan->batched ? (cRows ? MORLET_SCHED_ROWS : MORLET_SCHED_TILES) : MORLET_SCHED_TILES;
+        if (schedule_out) *schedule_out = sched_of(cRows);
         if (log_on()) std::fprintf(stderr, "morlet: autotune cache hit %s -> R=%d rows=%d\n", key.c_str(), cR, cRows);
         return MORLET_OK;
       }
@@ -1610,6 +1649,8 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
     }
   }
   const int oldR = plan->R, oldSched = plan->row_serial;
+  // schedules: tiles, whole rows (several rows), segments (one row)
+  const bool one_row = !plan->batched || plan->rows.size() == 1;
   struct Cand { int R, rows; };
   std::vector<Cand> cands;
   // one workspace serves every candidate: the largest of their sizes. A tile shape the plan
@@ -1627,7 +1668,11 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
     }
     need = std::max(need, b);
     cands.push_back({R, 0});
-    if (plan->batched) cands.push_back({R, 1});
+    if (one_row) {
+      if (!plan->multiply) cands.push_back({R, 2});
+    } else if (plan->batched) {
+      cands.push_back({R, 1});
+    }
   }
   if (cands.empty()) {
     (void)morlet_plan_set_tile(plan, oldR);
@@ -1677,7 +1722,7 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
     return st;
   }
   st = morlet_plan_set_tile(plan, cands[best].R);
-  plan->row_serial = plan->batched ? cands[best].rows : oldSched;
+  plan->row_serial = cands[best].rows;
   if (st == MORLET_OK) {
     tune_store(key, cands[best].R, cands[best].rows, best_ms / (float)reps);
     if (log_on())
@@ -1685,7 +1730,7 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
                    cands[best].rows, best_ms / (float)reps);
   }
   if (R_out) *R_out = cands[best].R;
-  if (schedule_out) *schedule_out = plan->batched ? (cands[best].rows ? MORLET_SCHED_ROWS : MORLET_SCHED_TILES) : MORLET_SCHED_TILES;
+  if (schedule_out) *schedule_out = sched_of(cands[best].rows);
   return st;
 }
 
@@ -1937,8 +1982,7 @@ morlet_status morlet_forward_noalloc(morlet_plan_t plan, const void* x, morlet_d
   mk::ScanLaunch a;
   morlet_status st = make_launch(plan, a, ws, mk::kVarForward, 0, (int)dtype);
   if (st != MORLET_OK) return st;
-  // the row-serial schedule uses the header only; the tiles schedule also the tile states
-  const size_t need = a.serial ? sizeof(mk::WsHeader) : mk::workspace_bytes(plan->K, ntiles);
+  const size_t need = launch_ws_bytes(a, plan->K, ntiles);
   if (need > mk::kScratchBytes)
     return fail(MORLET_ERR_WORKSPACE, "the launch needs " + std::to_string(need) +
                                           " bytes of workspace, more than the fixed scratch of " +

@@ -34,7 +34,8 @@ struct morlet_plan_s {
   std::vector<double> jac;      // [4K]: dcc/dsigma, dcc/dxi, dsc/dsigma, dsc/dxi
   double relrmse = 0;
   int R = 16;             // samples per thread
-  int row_serial = -1;    // batched schedule: -1 automatic, 0 tiles with look-back, 1 whole rows
+  int row_serial = -1;    // schedule: -1 automatic, 0 tiles with look-back, 1 whole rows, 2 segments
+  int seg_tiles = 0;      // segments schedule: tiles per segment (0: about two segments per resident block)
   int device = 0;
   int num_cus = 256;
   void* d_tab = nullptr;  // device copy of the constant table

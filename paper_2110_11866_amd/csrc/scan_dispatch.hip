@@ -109,20 +109,144 @@ __global__ __launch_bounds__(256) void pg_finalize_kernel(ScanLaunch P, int K, c
 
 // out[x_off_b + n] = sum_s part[S x_off_b + s len_b + n]: the adjoints of one signal's
 // scales summed in scale order. Row b S is scale 0 of signal b.
-__global__ void sum_scales_kernel(const float* part, float* out, const Row* rows, int B, int S, int64_t total) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    int lo = 0, hi = B - 1;   // last signal with x_off <= e
+// Four consecutive outputs per thread. Where the four lie in one signal and every scale's run of
+// them, and the four outputs, are 16-byte aligned (N a multiple of 4), each scale is one 16-byte load; otherwise the
+// elements are summed one by one. Either way every output adds its S terms in scale order, so
+// the result does not depend on the path.
+__global__ __launch_bounds__(256) void sum_scales_kernel(const float* part, float* out, const Row* rows, int B, int S,
+                                                         int64_t total) {
+  auto signal_of = [&](int64_t e) {   // last signal with x_off <= e
+    int lo = 0, hi = B - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (rows[(int64_t)mid * S].x_off <= e) lo = mid; else hi = mid - 1;
     }
-    const Row r0 = rows[(int64_t)lo * S];
-    const int64_t n = e - r0.x_off;
-    float acc = 0.f;
-    for (int s = 0; s < S; ++s) acc += part[(int64_t)S * r0.x_off + (int64_t)s * r0.N + n];
-    out[e] = acc;
+    return lo;
+  };
+  const bool aligned = ((reinterpret_cast<uintptr_t>(part) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+  for (int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; e0 < total; e0 += stride) {
+    const Row r0 = rows[(int64_t)signal_of(e0) * S];
+    const int64_t n = e0 - r0.x_off;
+    const int64_t base = (int64_t)S * r0.x_off + n;
+    if (aligned && n + 4 <= r0.N && e0 + 4 <= total && (base & 3) == 0 && (r0.N & 3) == 0) {
+      float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int s = 0; s < S; ++s) {
+        const float4 v = *reinterpret_cast<const float4*>(part + base + (int64_t)s * r0.N);
+        acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+      }
+      *reinterpret_cast<float4*>(out + e0) = acc;
+    } else {
+      for (int64_t e = e0; e < e0 + 4 && e < total; ++e) {
+        const Row r = rows[(int64_t)signal_of(e) * S];
+        const int64_t m = e - r.x_off;
+        float acc = 0.f;
+        for (int s = 0; s < S; ++s) acc += part[(int64_t)S * r.x_off + (int64_t)s * r.N + m];
+        out[e] = acc;
+      }
+    }
   }
+}
+
+// Segments schedule, between its two passes (one wave): the segment pass without outputs has
+// left in segstate[s] the state A_s at the end of segment s from a zero state at its start. The
+// state at the start of segment s is
+//   S_0 = 0,  S_{s+1} = c S_s + A_s,  c = a^{T len} (per term; every segment but the last, which
+// precedes none, has len tiles of T positions),
+// written over A_s. Lane l takes segments [l m, l m + m): it folds them from zero, the lanes'
+// folds are scanned with c^m (Hillis-Steele over the wave, the constant squared per level), and
+// each lane walks its segments again from its exclusive prefix. Float64 throughout, a fixed
+// order, so the result does not depend on timing.
+template <int K>
+__global__ __launch_bounds__(64) void seg_combine_kernel(ScanLaunch P) {
+  const int lane = threadIdx.x;
+  const TabLayout lay{K, P.R};
+  const Tab<true> tabd{(cptr<double>)(P.tabs + (int64_t)P.row0.scale * P.tab_stride + P.f32_bytes), K};
+  const int len = P.seg_len;
+  double cr[K], ci[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    if (len <= kLookback) {
+      cr[t] = tabd.re(lay.eLB(len), t);
+      ci[t] = tabd.im(lay.eLB(len), t);
+    } else {   // a^{T len} = a^{64 T (len / 64)} a^{T (len mod 64)}
+      const double pr = tabd.re(lay.eLB2(len / kLookback), t), pi = tabd.im(lay.eLB2(len / kLookback), t);
+      const double qr = tabd.re(lay.eLB(len % kLookback), t), qi = tabd.im(lay.eLB(len % kLookback), t);
+      cr[t] = pr * qr - pi * qi;
+      ci[t] = pr * qi + pi * qr;
+    }
+  }
+  const int64_t n = P.nseg, m = (n + 63) / 64;
+  const int64_t k0 = lane * m < n ? lane * m : n, k1 = k0 + m < n ? k0 + m : n;
+  double* st = P.segstate;
+  double gr[K], gi[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) { gr[t] = 0; gi[t] = 0; }
+  for (int64_t k = k0; k < k1; ++k) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const double ar = st[k * 2 * K + 2 * t], ai = st[k * 2 * K + 2 * t + 1];
+      const double nr = fma(cr[t], gr[t], fma(-ci[t], gi[t], ar));
+      gi[t] = fma(cr[t], gi[t], fma(ci[t], gr[t], ai));
+      gr[t] = nr;
+    }
+  }
+  // C = c^m, then C^(2^d) at scan level d
+  double Cr[K], Ci[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) { Cr[t] = 1; Ci[t] = 0; }
+  for (int64_t i = 0; i < m; ++i) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const double nr = Cr[t] * cr[t] - Ci[t] * ci[t];
+      Ci[t] = Cr[t] * ci[t] + Ci[t] * cr[t];
+      Cr[t] = nr;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    const int sh = 1 << d;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const double ur = __shfl_up(gr[t], sh, 64), ui = __shfl_up(gi[t], sh, 64);
+      if (lane >= sh) {
+        gr[t] += Cr[t] * ur - Ci[t] * ui;
+        gi[t] += Cr[t] * ui + Ci[t] * ur;
+      }
+      const double nr = Cr[t] * Cr[t] - Ci[t] * Ci[t];
+      Ci[t] = 2 * Cr[t] * Ci[t];
+      Cr[t] = nr;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const double ur = __shfl_up(gr[t], 1, 64), ui = __shfl_up(gi[t], 1, 64);
+    gr[t] = lane > 0 ? ur : 0.0;
+    gi[t] = lane > 0 ? ui : 0.0;
+  }
+  for (int64_t k = k0; k < k1; ++k) {
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      const double ar = st[k * 2 * K + 2 * t], ai = st[k * 2 * K + 2 * t + 1];
+      st[k * 2 * K + 2 * t] = gr[t];
+      st[k * 2 * K + 2 * t + 1] = gi[t];
+      const double nr = fma(cr[t], gr[t], fma(-ci[t], gi[t], ar));
+      gi[t] = fma(cr[t], gi[t], fma(ci[t], gr[t], ai));
+      gr[t] = nr;
+    }
+  }
+}
+
+hipError_t launch_seg_combine(const ScanLaunch& a, hipStream_t s) {
+  switch (a.K) {
+#define MK_SEG(K) \
+  case K: hipLaunchKernelGGL(seg_combine_kernel<K>, dim3(1), dim3(64), 0, s, a); break;
+    MK_SEG(1) MK_SEG(2) MK_SEG(3) MK_SEG(4) MK_SEG(5) MK_SEG(6) MK_SEG(7) MK_SEG(8) MK_SEG(9) MK_SEG(10)
+    MK_SEG(11) MK_SEG(12)
+#undef MK_SEG
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -130,6 +254,20 @@ __global__ void sum_scales_kernel(const float* part, float* out, const Row* rows
 hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s) {
   KernelFn fn = select_kernel(a.K, a.R, variant, a.acc, a.kind, mom, variant == kVarAdjoint ? 0 : a.dtype);
   if (!fn) return hipErrorInvalidValue;
+  if (a.nseg > 0) {
+    if (variant != kVarForward || !a.serial || a.nrows != 1 || !a.segstate || a.seg_len < 1 ||
+        a.seg_len > kLookback * kLookback)
+      return hipErrorInvalidValue;
+    ScanLaunch b = a;
+    b.seg_mode = 1;
+    hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kThreads), 0, s, b);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_seg_combine(a, s);
+    if (e != hipSuccess) return e;
+    b.seg_mode = 2;
+    hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kThreads), 0, s, b);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(fn, dim3(a.grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -168,7 +306,7 @@ hipError_t launch_pg_finalize(const ScanLaunch& a, int nscales, double* rowpart,
 hipError_t launch_sum_scales(const float* part, float* out, const Row* rows, int B, int S, int64_t total,
                              hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  const unsigned int blocks = (unsigned int)std::min<int64_t>((total + 255) / 256, 8192);
+  const unsigned int blocks = (unsigned int)std::min<int64_t>((total + 1023) / 1024, 8192);
   hipLaunchKernelGGL(sum_scales_kernel, dim3(blocks), dim3(256), 0, s, part, out, rows, B, S, total);
   return hipGetLastError();
 }

@@ -103,8 +103,15 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
 //               compensated: float-float arithmetic (ff.h) from error-free float32 transforms;
 //               float64 only for the carries, as in kAccF32 (forward only).
 template <int VAR, int K, int R, int ACC, int KIND, bool MOM, int DT>
+// Occupancy: the float32-state forward scans fit four waves per SIMD (at most 128 VGPRs). The
+// gradient pass runs three up to K = 5: its LDS at R = 16 (41 KB per block) leaves no room for a
+// fourth, and at K = 5 the few float64 registers it spills cost less than the third wave gains
+// (about 40 us of a 450 us pass at 64 x 32768 x 16 scales); at K = 6 it would spill 65. The rest
+// leave the register count to the compiler.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
-    (VAR == kFwd && (ACC == kAccF32 || (ACC == kAccMixed && R <= 16))) ? 4 : 1))) void scan_kernel(ScanLaunch P) {
+    (VAR == kFwd && (ACC == kAccF32 || (ACC == kAccMixed && R <= 16))) ? 4
+    : (VAR == kPg && K <= 5)                                            ? 3
+                                                                        : 1))) void scan_kernel(ScanLaunch P) {
   constexpr bool WIDE = ACC == kAccF64;
   constexpr bool F32T = ACC == kAccF32;                  // float32 tile scan
   constexpr bool KAHAN = ACC == kAccKahan;               // compensated float32 tile scan
@@ -179,31 +186,52 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
   // and resolves the tile's incoming state by the look-back. Row-serial: a block claims a
   // whole row (longest rows first) and runs its tiles in order, carrying the state in LDS.
   Row row = P.row0;
-  int64_t ti = 0, row_left = 0;
+  int64_t ti = -1, row_left = 0;   // ti: the tile in hand, its index within its row (-1: none yet)
   // row-serial: the block starts on its own XCD's queue and moves on to the next queue only
   // when that one is empty (thread 0 keeps the count of queues it has left behind)
   int qdone = 0;
+  // segments pass without outputs: an output range no tile reaches
+  if (P.seg_mode == 1) row.jout0 = (int64_t)1 << 62;
   for (;;) {
     uint32_t tile;
     if (P.serial) {
       if (row_left == 0) {
+        // the next row (rows schedule: from the queues) or segment (segments schedule: one row,
+        // through the ticket)
         if (tid == 0) {
           uint32_t r = (uint32_t)P.nrows;
-          for (; qdone < kQueues; ++qdone) {
-            const int q = (int)((blockIdx.x + (unsigned)qdone) % kQueues);
-            const uint32_t k = atomicAdd(&hdr->qticket[q], 1u);
-            if ((int64_t)k < (int64_t)(P.qstart[q + 1] - P.qstart[q])) {
-              r = (uint32_t)P.qstart[q] + k;
-              break;
+          if (P.seg_mode != 0) {
+            r = atomicAdd(&hdr->ticket, 1u);
+          } else {
+            for (; qdone < kQueues; ++qdone) {
+              const int q = (int)((blockIdx.x + (unsigned)qdone) % kQueues);
+              const uint32_t k = atomicAdd(&hdr->qticket[q], 1u);
+              if ((int64_t)k < (int64_t)(P.qstart[q + 1] - P.qstart[q])) {
+                r = (uint32_t)P.qstart[q] + k;
+                break;
+              }
             }
           }
           s_tile = r;
         }
         __syncthreads();
         const uint32_t r = __builtin_amdgcn_readfirstlane(s_tile);
+        // segments pass without outputs: the state after the segment just finished (wave 0 left
+        // it for the next tile) is that segment's end state
+        if (P.seg_mode == 1 && ti >= 0 && tid < 2 * KS) P.segstate[ti / P.seg_len * 2 * KS + tid] = s_c[(ti + 1) & 1][tid];
         __syncthreads();   // every wave has read s_tile before thread 0 may claim again
-        if ((int64_t)r >= P.nrows) break;
-        load_row(((cptr<int32_t>)P.row_order)[r], row);
+        if (P.seg_mode != 0) {
+          if ((int64_t)r >= P.nseg) break;
+          ti = (int64_t)r * P.seg_len;
+          row_left = row.ntiles - ti < P.seg_len ? row.ntiles - ti : P.seg_len;
+          // the state the segment starts from: zero in the pass without outputs
+          if (tid < 2 * KS) s_c[ti & 1][tid] = P.seg_mode == 2 ? P.segstate[(int64_t)r * 2 * KS + tid] : 0.0;
+        } else {
+          if ((int64_t)r >= P.nrows) break;
+          load_row(((cptr<int32_t>)P.row_order)[r], row);
+          ti = 0;
+          row_left = row.ntiles;
+        }
         if constexpr (KCACHE) {
           const cptr<double> td = (cptr<double>)(P.tabs + (int64_t)row.scale * P.tab_stride + P.f32_bytes);
           if (tid < 9 * K) {
@@ -212,10 +240,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
             s_k[slot][2 * t] = td[(2 * e) * K + t];
             s_k[slot][2 * t + 1] = td[(2 * e + 1) * K + t];
           }
-          __syncthreads();
         }
-        ti = 0;
-        row_left = row.ntiles;
+        if (KCACHE || P.seg_mode != 0) __syncthreads();
         if (row_left == 0) continue;
       } else {
         ++ti;

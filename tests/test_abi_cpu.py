@@ -203,7 +203,11 @@ def test_call_errors_before_launch():
         assert L.morlet_plan_set(h, 1, 65, 0) == _abi.MORLET_ERR_INVALID_ARG
         assert L.morlet_plan_set(h, 1, 0, 9) == _abi.MORLET_ERR_UNSUPPORTED
         assert L.morlet_forward(None, fake, 0, fake, fake, need, None) == _abi.MORLET_ERR_INVALID_ARG
-        assert L.morlet_plan_set_schedule(h, 3) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_plan_set_schedule(h, 4) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_plan_set_schedule(h, _abi.MORLET_SCHED_SEGMENTS) == _abi.MORLET_OK
+        assert L.morlet_plan_set_segments(h, -1) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_plan_set_segments(h, 4097) == _abi.MORLET_ERR_INVALID_ARG
+        assert L.morlet_plan_set_segments(h, 7) == _abi.MORLET_OK
         assert L.morlet_plan_set_schedule(None, 0) == _abi.MORLET_ERR_INVALID_ARG
         assert L.morlet_plan_set_schedule(h, _abi.MORLET_SCHED_ROWS) == _abi.MORLET_OK
         assert L.morlet_plan_autotune(h, fake, 0, fake, 0, None, None, None) == _abi.MORLET_ERR_INVALID_ARG

@@ -198,38 +198,45 @@ def test_autograd_layer_and_central_differences(mode):
         assert errs[1] < 1e-4 and errs[1] < errs[0], errs
 
 
-@pytest.mark.parametrize("schedule", ["auto", "rows"])
-def test_differentiation_workload_sampled(schedule):
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_differentiation_workload_sampled(mode):
     # 64 signals x 32768 samples, 16 scales sigma = 8..2048, K = 5, Loss = sum w |W|^2 with
     # w ~ U[0,1] per (scale, n) shared over the batch; gradients for x (4 signals checked in
-    # full) and for every (sigma_s, xi_s) (oracle summed over all 64 signals)
+    # full) and for every (sigma_s, xi_s) (oracle summed over all 64 signals), from the tiles and
+    # the rows schedule on the same cotangent
     import paper_2110_11866_amd as M
-    _announce("differentiation-workload", schedule)
+    _announce("differentiation-workload", mode)
     x, sigmas, xis, w = workloads.differentiation_batch()
     B, N = x.shape
     S = len(sigmas)
-    plan = M.ScalogramPlan([N] * B, sigmas, xis, 5, 0.0).set_schedule(schedule)
+    plan = M.ScalogramPlan([N] * B, sigmas, xis, 5, 0.0, mode=mode)
     xt = torch.from_numpy(x.reshape(-1)).cuda()
     W = plan.forward(xt)
     wt = torch.from_numpy(np.tile(w.reshape(1, S, N), (B, 1, 1)).reshape(-1)).cuda()
     g = (2 * wt * W).contiguous()
-    gx, gp = plan.backward(xt, g)
-    torch.cuda.synchronize()
+    got = {}
+    for schedule in ("tiles", "rows"):
+        gx, gp = plan.set_schedule(schedule).backward(xt, g)
+        torch.cuda.synchronize()
+        got[schedule] = (gx.cpu().numpy().reshape(B, N), gp.cpu().numpy())
     gn = g.cpu().numpy().astype(np.complex128).reshape(B, S, N)
-    gxn, gpn = gx.cpu().numpy().reshape(B, N), gp.cpu().numpy()
     plans = []
     for s in range(S):
         info = plan.scale_info(s)
-        plans.append(O.plan_morlet(sigmas[s], xis[s], 5, info["L"], P_S=checked_ps(sigmas[s], xis[s], 5, info)))
+        plans.append(O.plan_morlet(sigmas[s], xis[s], 5, info["L"], mode=mode,
+                                   n0=info["n0"] if mode == "asft" else None,
+                                   P_S=checked_ps(sigmas[s], xis[s], 5, info)))
     for b in (0, 17, 40, 63):
         want = sum(O.adjoint(gn[b, s], plans[s]) for s in range(S))
-        assert rel(gxn[b], want) <= 1e-5, (b, rel(gxn[b], want))
+        for schedule, (gxn, _) in got.items():
+            assert rel(gxn[b], want) <= 1e-5, (schedule, b, rel(gxn[b], want))
     want_gp = np.zeros((S, 2))
     for b in range(B):
         xb = x[b].astype(np.float64)
         for s in range(S):
             want_gp[s] += O.param_grads(xb, gn[b, s], plans[s])
-    assert np.all(np.abs(gpn - want_gp) <= 1e-5 * np.abs(want_gp)), np.abs(gpn - want_gp) / np.abs(want_gp)
+    for schedule, (_, gpn) in got.items():
+        assert np.all(np.abs(gpn - want_gp) <= 1e-5 * np.abs(want_gp)), (schedule, np.abs(gpn - want_gp) / np.abs(want_gp))
 
 
 def _fold(gxe, N, P):

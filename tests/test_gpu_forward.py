@@ -297,16 +297,18 @@ def test_gaussian_differential_asft_parity(N, sigma, K, L, n0, tile, dtype, accu
     assert rel_l2(got, want) <= TOL[accum], rel_l2(got, want)
 
 
+@pytest.mark.parametrize("schedule", ["tiles", "segments"])
 @pytest.mark.parametrize("mode", ["sft", "asft"])
-def test_long_row_crosses_super_groups(mode):
+def test_long_row_crosses_super_groups(mode, schedule):
     # one 17e6-sample row: 4153 tiles of 4096 positions, i.e. more than one super-group of
-    # 64 x 64 tiles in the look-back; checked in full, and bitwise on a repeat
+    # 64 x 64 tiles in the look-back (tiles), or 1385 segments of 3 tiles (segments, automatic
+    # length); checked in full, and bitwise on a repeat
     import paper_2110_11866_amd as M
-    _announce("long-row", mode)
+    _announce("long-row", mode, schedule)
     N, sigma, K, L = 17_000_000, 40.0, 4, 160
     x = np.random.default_rng(17).standard_normal(N).astype(np.float32)
     xt = torch.from_numpy(x).cuda()
-    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode)
+    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode).set_schedule(schedule)
     a = plan.forward(xt)
     b = plan.forward(xt)
     torch.cuda.synchronize()
@@ -317,17 +319,19 @@ def test_long_row_crosses_super_groups(mode):
     assert rel_l2(a.cpu().numpy(), want) <= 1e-5, rel_l2(a.cpu().numpy(), want)
 
 
+@pytest.mark.parametrize("schedule", ["tiles", "segments"])
 @pytest.mark.parametrize("mode", ["sft", "asft"])
-def test_max_single_row_sampled(mode):
-    # one 2^30-sample row: 262144 tiles, 64 super-groups of the look-back; outputs sampled at the
-    # ends, around tile / group / super-group boundaries and at random, each checked against the
-    # oracle's plain sum over its own window of the same (device-generated) input
+def test_max_single_row_sampled(mode, schedule):
+    # one 2^30-sample row: 262144 tiles, 64 super-groups of the look-back (tiles), or 2048
+    # segments of 128 tiles (segments, automatic length); outputs sampled at the ends, around
+    # tile / group / super-group boundaries and at random, each checked against the oracle's
+    # plain sum over its own window of the same (device-generated) input
     import paper_2110_11866_amd as M
-    _announce("max-row", mode)
+    _announce("max-row", mode, schedule)
     N, sigma, K, L = 1 << 30, 64.0, 5, 0
     gen = torch.Generator(device="cuda").manual_seed(30)
     xt = torch.randn(N, generator=gen, device="cuda")
-    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode)
+    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode).set_schedule(schedule)
     W = plan.forward(xt)
     torch.cuda.synchronize()
     info = plan.info()
@@ -336,7 +340,10 @@ def test_max_single_row_sampled(mode):
     h, shift = (O.asft_kernel(p), n0) if mode == "asft" else (O.kterm_morlet(p), 0)
     T = 16 * 256
     ns = {0, 1, L, N - 1, N - 2, N - L - 1}
-    for j in (T, 64 * T, 4096 * T, 5 * 4096 * T, 63 * 4096 * T, 64 * 4096 * T - T):
+    # tile, group and super-group boundaries; segment boundaries (128 tiles) and the boundary
+    # between two lanes' runs of 32 segments in the combination
+    for j in (T, 64 * T, 4096 * T, 5 * 4096 * T, 63 * 4096 * T, 64 * 4096 * T - T, 128 * T, 32 * 128 * T,
+              2047 * 128 * T):
         for d in (-1, 0, 1):
             ns.add(j + d - (L - n0))      # output at scan position j + d
     ns.update(int(v) for v in np.random.default_rng(31).integers(0, N, 40))

@@ -64,16 +64,23 @@ def test_noalloc_matches_scalogram_forward_on_two_calls():
 
 
 def test_noalloc_refuses_beyond_its_array():
-    # K = 12 tile states take 640 B: 2^26 samples at R = 16 need 16 385 tiles, 10.5 MB > 8 MiB
+    # tiles schedule: K = 12 tile states take 640 B, and 2^26 samples at R = 16 need 16 385 tiles,
+    # 10.5 MB > 8 MiB. The segments schedule (the automatic choice for this row) keeps one state
+    # vector per segment, well inside the array, and matches morlet_forward bit for bit.
     import paper_2110_11866_amd as M
     from paper_2110_11866_amd import _abi
     _announce("noalloc limit")
     N = 1 << 26
-    plan = M.MorletPlan(N, 8.0, 6.0 / 8.0, 12, 40)
-    x = torch.zeros(N, device="cuda")
+    plan = M.MorletPlan(N, 8.0, 6.0 / 8.0, 12, 40).set_schedule("tiles")
+    x = torch.randn(N, generator=torch.Generator(device="cuda").manual_seed(2), device="cuda")
     W = torch.zeros(N, dtype=torch.complex64, device="cuda")
     with pytest.raises(_abi.MorletError) as e:
         _noalloc(plan, x, W)
     assert e.value.status == _abi.MORLET_ERR_WORKSPACE
     torch.cuda.synchronize()
     assert int(torch.count_nonzero(W)) == 0
+    plan.set_schedule("segments")
+    want = plan.forward(x)
+    _noalloc(plan, x, W)
+    torch.cuda.synchronize()
+    assert torch.equal(W, want)
