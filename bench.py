@@ -54,6 +54,7 @@ def _parse():
     ap.add_argument("--tile", type=int, default=16, choices=[4, 8, 16, 32], help="samples per thread")
     ap.add_argument("--schedule", default="auto", choices=["auto", "tiles", "rows", "segments"],
                     help="launch schedule (rows: scalogram-shaped workloads; segments: one long row)")
+    ap.add_argument("--seg-tiles", type=int, default=0, help="segments schedule: tiles per segment (0: automatic)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run plain device copies of this many MB (counter calibration for HBM bytes)")
     return ap.parse_args()
@@ -101,6 +102,7 @@ def _timed(torch, fn, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern = [a.elapsed_time(b) for a, b in ev]
+    _timed.median = float(np.median(kern))   # the median launch, beside the mean returned
     return wall * 1e3 / steps, float(np.mean(kern))
 
 
@@ -178,6 +180,7 @@ def bench_scalogram(args, torch, M):
     out = torch.empty(S * Ntot, dtype=torch.complex64, device=dev)
     ws = plan.workspace(dev)
     ms_step, kern_ms = _timed(torch, lambda: plan.forward(xt, out=out, ws=ws), args.steps, args.warmup)
+    kern_med = _timed.median
     ss = Ntot * S
     algo_bytes = ss * 8 + Ntot * 4
     achieved = algo_bytes / (kern_ms * 1e-3) / 1e9
@@ -197,6 +200,7 @@ def bench_scalogram(args, torch, M):
                      "traffic": _measured_traffic("scan_forward_scalogram_traffic.json")
                      if (args.tile, args.schedule, args.mode) == (16, "auto", "asft") else None},
         "kernel_ms": kern_ms,
+        "kernel_ms_median": kern_med,
         "algorithmic_bytes_per_launch": algo_bytes,
     }
     # the paper's own point (N = 102400, sigma = 8192, K = 6, Sec. V-B): the scan against the
@@ -295,7 +299,7 @@ def bench_gauss_deriv(args, torch, M):
     dev = torch.device("cuda:0")
     x = torch.randn(N, generator=torch.Generator().manual_seed(11)).to(dev)
     plan = M.GaussDerivPlan(N, sigma, K, 0, order=1, mode=args.mode)
-    plan.set_tile(args.tile).set_schedule(args.schedule)
+    plan.set_tile(args.tile).set_schedule(args.schedule).set_segments(args.seg_tiles)
     out = torch.empty(N, dtype=torch.float32, device=dev)
     ws = plan.workspace(dev)
     ms_step, kern_ms = _timed(torch, lambda: plan.forward(x, out=out, ws=ws), args.steps, args.warmup)
@@ -311,7 +315,7 @@ def bench_gauss_deriv(args, torch, M):
         "dtype": "f32",
         "config": {"workload": f"gauss_deriv: one float32 N(0,1) signal, N=2^26, sigma={sigma:g}, K={K} ({terms}), "
                                f"window L={info['L']} (error-optimal), float32 out",
-                   "tile_R": args.tile, "schedule": args.schedule},
+                   "tile_R": args.tile, "schedule": args.schedule, "seg_tiles": args.seg_tiles},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "kernel_ms": kern_ms,

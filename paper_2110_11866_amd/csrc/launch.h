@@ -33,21 +33,21 @@ struct ScanLaunch {
   const void* g;                // gradient pass: cotangent at the outputs (complex64 or float32)
   double* partials;             // gradient pass: per-tile float64 partial sums
   // Segments schedule (forward, one row): the row's tiles in nseg segments of seg_len tiles
-  // (the last one shorter), a block at a time running a segment's tiles in order.
-  // seg_mode 1: no outputs, each segment's end state from a zero start into segstate;
-  // seg_mode 2: outputs, each segment starting from the state segstate holds for it.
+  // (the last one shorter). seg_mode 1 (set for the launch with outputs): blocks take segments
+  // through the ticket and run each segment's tiles in order from the state segstate holds for it.
   int seg_mode;
   int seg_len;
   int64_t nseg;                 // 0: not this schedule
   double* segstate;             // device [nseg][2 K] float64 (re, im per term), in the workspace
 };
 
-enum ScanVariant { kVarForward = 0, kVarAdjoint = 1, kVarParamGrad = 2 };
+enum ScanVariant { kVarForward = 0, kVarAdjoint = 1, kVarParamGrad = 2, kVarSegSum = 3 };
 
 // Launch a scan variant (forward, adjoint, parameter-gradient pass; mom: carry the
 // alpha-derivative states for the ASFT sigma gradient). A forward launch under the segments
-// schedule (nseg > 0) is three launches: the segment pass without outputs, the combination of
-// the segment states, and the segment pass with outputs.
+// schedule (nseg > 0) is three launches: the segment sums (one block per segment, each
+// segment's end state from a zero start), their combination into incoming states, and the scan
+// with outputs over the segments.
 hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s);
 int scan_occupancy(int K, int R, int variant, int acc, int kind, int mom, int dtype);
 // Sum per-tile partials into d/dsigma, d/dxi per scale: per-row sums into rowpart

@@ -148,21 +148,30 @@ __global__ __launch_bounds__(256) void sum_scales_kernel(const float* part, floa
   }
 }
 
-// Segments schedule, between its two passes (one wave): the segment pass without outputs has
-// left in segstate[s] the state A_s at the end of segment s from a zero state at its start. The
-// state at the start of segment s is
+// Segments schedule, between its two passes (one block): the segment sums have left in
+// segstate[s] the state A_s at the end of segment s from a zero state at its start. The state
+// at the start of segment s is
 //   S_0 = 0,  S_{s+1} = c S_s + A_s,  c = a^{T len} (per term; every segment but the last, which
 // precedes none, has len tiles of T positions),
-// written over A_s. Lane l takes segments [l m, l m + m): it folds them from zero, the lanes'
-// folds are scanned with c^m (Hillis-Steele over the wave, the constant squared per level), and
-// each lane walks its segments again from its exclusive prefix. Float64 throughout, a fixed
-// order, so the result does not depend on timing.
+// written over A_s. In rounds of 1024 segments, four consecutive ones per thread (their loads in
+// flight together): each thread folds its four (Horner with c), the folds are scanned across the
+// wave with C = c^4 (Hillis-Steele, the constant squared per level, C^lane formed from the same
+// squares), the four wave totals are chained in order through LDS, and each thread writes the
+// incoming states of its four from its exclusive prefix; the state after the round carries into
+// the next. Float64 throughout, a fixed order, so the result does not depend on timing. One wave
+// per SIMD leaves the registers for all K terms at once (without spills up to K = 6).
 template <int K>
-__global__ __launch_bounds__(64) void seg_combine_kernel(ScanLaunch P) {
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void seg_combine_kernel(ScanLaunch P) {
+  constexpr int NW = 4, NT = NW * 64, Q = 4;
+  __shared__ double s_tot[NW][2 * K];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const TabLayout lay{K, P.R};
   const Tab<true> tabd{(cptr<double>)(P.tabs + (int64_t)P.row0.scale * P.tab_stride + P.f32_bytes), K};
   const int len = P.seg_len;
+  auto cmul = [](double ar, double ai, double br, double bi, double& outr, double& outi) {
+    outr = ar * br - ai * bi;
+    outi = ar * bi + ai * br;
+  };
   double cr[K], ci[K];
 #pragma unroll
   for (int t = 0; t < K; ++t) {
@@ -170,77 +179,111 @@ __global__ __launch_bounds__(64) void seg_combine_kernel(ScanLaunch P) {
       cr[t] = tabd.re(lay.eLB(len), t);
       ci[t] = tabd.im(lay.eLB(len), t);
     } else {   // a^{T len} = a^{64 T (len / 64)} a^{T (len mod 64)}
-      const double pr = tabd.re(lay.eLB2(len / kLookback), t), pi = tabd.im(lay.eLB2(len / kLookback), t);
-      const double qr = tabd.re(lay.eLB(len % kLookback), t), qi = tabd.im(lay.eLB(len % kLookback), t);
-      cr[t] = pr * qr - pi * qi;
-      ci[t] = pr * qi + pi * qr;
+      cmul(tabd.re(lay.eLB2(len / kLookback), t), tabd.im(lay.eLB2(len / kLookback), t),
+           tabd.re(lay.eLB(len % kLookback), t), tabd.im(lay.eLB(len % kLookback), t), cr[t], ci[t]);
     }
   }
-  const int64_t n = P.nseg, m = (n + 63) / 64;
-  const int64_t k0 = lane * m < n ? lane * m : n, k1 = k0 + m < n ? k0 + m : n;
+  const int64_t n = P.nseg;
   double* st = P.segstate;
-  double gr[K], gi[K];
+  double carry_r[K], carry_i[K];   // the state entering the round
 #pragma unroll
-  for (int t = 0; t < K; ++t) { gr[t] = 0; gi[t] = 0; }
-  for (int64_t k = k0; k < k1; ++k) {
+  for (int t = 0; t < K; ++t) { carry_r[t] = 0; carry_i[t] = 0; }
+  for (int64_t base = 0; base < n; base += (int64_t)Q * NT) {
+    const int64_t k0 = base + (int64_t)Q * tid;
+    double ar[Q][K], ai[Q][K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const double ar = st[k * 2 * K + 2 * t], ai = st[k * 2 * K + 2 * t + 1];
-      const double nr = fma(cr[t], gr[t], fma(-ci[t], gi[t], ar));
-      gi[t] = fma(cr[t], gi[t], fma(ci[t], gr[t], ai));
-      gr[t] = nr;
-    }
-  }
-  // C = c^m, then C^(2^d) at scan level d
-  double Cr[K], Ci[K];
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
-  for (int t = 0; t < K; ++t) { Cr[t] = 1; Ci[t] = 0; }
-  for (int64_t i = 0; i < m; ++i) {
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const double nr = Cr[t] * cr[t] - Ci[t] * ci[t];
-      Ci[t] = Cr[t] * ci[t] + Ci[t] * cr[t];
-      Cr[t] = nr;
-    }
-  }
-#pragma unroll
-  for (int d = 0; d < 6; ++d) {
-    const int sh = 1 << d;
-#pragma unroll
-    for (int t = 0; t < K; ++t) {
-      const double ur = __shfl_up(gr[t], sh, 64), ui = __shfl_up(gi[t], sh, 64);
-      if (lane >= sh) {
-        gr[t] += Cr[t] * ur - Ci[t] * ui;
-        gi[t] += Cr[t] * ui + Ci[t] * ur;
+      for (int t = 0; t < K; ++t) {
+        ar[q][t] = k0 + q < n ? st[(k0 + q) * 2 * K + 2 * t] : 0.0;
+        ai[q][t] = k0 + q < n ? st[(k0 + q) * 2 * K + 2 * t + 1] : 0.0;
       }
-      const double nr = Cr[t] * Cr[t] - Ci[t] * Ci[t];
-      Ci[t] = 2 * Cr[t] * Ci[t];
-      Cr[t] = nr;
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < K; ++t) {
-    const double ur = __shfl_up(gr[t], 1, 64), ui = __shfl_up(gi[t], 1, 64);
-    gr[t] = lane > 0 ? ur : 0.0;
-    gi[t] = lane > 0 ? ui : 0.0;
-  }
-  for (int64_t k = k0; k < k1; ++k) {
+    // the fold of the four, then the inclusive scan over the wave; pw = C^(2^d), pl = C^lane
+    double gr[K], gi[K], pwr[K], pwi[K], plr[K], pli[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-      const double ar = st[k * 2 * K + 2 * t], ai = st[k * 2 * K + 2 * t + 1];
-      st[k * 2 * K + 2 * t] = gr[t];
-      st[k * 2 * K + 2 * t + 1] = gi[t];
-      const double nr = fma(cr[t], gr[t], fma(-ci[t], gi[t], ar));
-      gi[t] = fma(cr[t], gi[t], fma(ci[t], gr[t], ai));
-      gr[t] = nr;
+      gr[t] = 0;
+      gi[t] = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        double vr, vi;
+        cmul(cr[t], ci[t], gr[t], gi[t], vr, vi);
+        gr[t] = vr + ar[q][t];
+        gi[t] = vi + ai[q][t];
+      }
+      double c2r, c2i;
+      cmul(cr[t], ci[t], cr[t], ci[t], c2r, c2i);
+      cmul(c2r, c2i, c2r, c2i, pwr[t], pwi[t]);
+      plr[t] = 1;
+      pli[t] = 0;
     }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      const int sh = 1 << d;
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const double ur = __shfl_up(gr[t], sh, 64), ui = __shfl_up(gi[t], sh, 64);
+        double vr, vi;
+        if (lane >= sh) {
+          cmul(pwr[t], pwi[t], ur, ui, vr, vi);
+          gr[t] += vr;
+          gi[t] += vi;
+        }
+        if (lane & sh) {
+          cmul(plr[t], pli[t], pwr[t], pwi[t], vr, vi);
+          plr[t] = vr;
+          pli[t] = vi;
+        }
+        cmul(pwr[t], pwi[t], pwr[t], pwi[t], vr, vi);
+        pwr[t] = vr;
+        pwi[t] = vi;
+      }
+    }
+    // pw is now C^64, the step across one wave
+    if (lane == 63) {
+#pragma unroll
+      for (int t = 0; t < K; ++t) { s_tot[wid][2 * t] = gr[t]; s_tot[wid][2 * t + 1] = gi[t]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      // Y: the state entering each wave in turn, from the round's carry; the one entering this
+      // thread's wave is kept, the one after the last wave is the next round's carry
+      double yr = carry_r[t], yi = carry_i[t], wr = 0, wi = 0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) {
+        if (v == wid) { wr = yr; wi = yi; }
+        double vr, vi;
+        cmul(pwr[t], pwi[t], yr, yi, vr, vi);
+        yr = vr + s_tot[v][2 * t];
+        yi = vi + s_tot[v][2 * t + 1];
+      }
+      carry_r[t] = yr;
+      carry_i[t] = yi;
+      // the thread's incoming state: the wave-exclusive prefix plus C^lane times the wave's entry
+      const double er = __shfl_up(gr[t], 1, 64), ei = __shfl_up(gi[t], 1, 64);
+      double vr, vi;
+      cmul(plr[t], pli[t], wr, wi, vr, vi);
+      double sr = (lane > 0 ? er : 0.0) + vr, si = (lane > 0 ? ei : 0.0) + vi;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (k0 + q < n) {
+          st[(k0 + q) * 2 * K + 2 * t] = sr;
+          st[(k0 + q) * 2 * K + 2 * t + 1] = si;
+        }
+        cmul(cr[t], ci[t], sr, si, vr, vi);
+        sr = vr + ar[q][t];
+        si = vi + ai[q][t];
+      }
+    }
+    __syncthreads();   // s_tot is rewritten by the next round
   }
 }
 
 hipError_t launch_seg_combine(const ScanLaunch& a, hipStream_t s) {
   switch (a.K) {
 #define MK_SEG(K) \
-  case K: hipLaunchKernelGGL(seg_combine_kernel<K>, dim3(1), dim3(64), 0, s, a); break;
+  case K: hipLaunchKernelGGL(seg_combine_kernel<K>, dim3(1), dim3(256), 0, s, a); break;
     MK_SEG(1) MK_SEG(2) MK_SEG(3) MK_SEG(4) MK_SEG(5) MK_SEG(6) MK_SEG(7) MK_SEG(8) MK_SEG(9) MK_SEG(10)
     MK_SEG(11) MK_SEG(12)
 #undef MK_SEG
@@ -258,13 +301,14 @@ hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s)
     if (variant != kVarForward || !a.serial || a.nrows != 1 || !a.segstate || a.seg_len < 1 ||
         a.seg_len > kLookback * kLookback)
       return hipErrorInvalidValue;
-    ScanLaunch b = a;
-    b.seg_mode = 1;
-    hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kThreads), 0, s, b);
+    KernelFn sum = select_kernel(a.K, a.R, kVarSegSum, 0, 0, 0, a.dtype);
+    if (!sum || a.nseg > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sum, dim3((unsigned)a.nseg), dim3(kThreads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = launch_seg_combine(a, s);
     if (e != hipSuccess) return e;
-    b.seg_mode = 2;
+    ScanLaunch b = a;
+    b.seg_mode = 1;
     hipLaunchKernelGGL(fn, dim3(b.grid), dim3(kThreads), 0, s, b);
     return hipGetLastError();
   }

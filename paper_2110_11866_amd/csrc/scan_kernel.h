@@ -57,7 +57,7 @@
 namespace mk {
 namespace {
 
-enum { kFwd = 0, kAdj = 1, kPg = 2 };
+enum { kFwd = 0, kAdj = 1, kPg = 2, kSegSum = 3 };
 
 // The matrix-core evaluation of the per-thread run (below) computes the same outputs as the
 // vector-ALU recurrence with a third fewer vector instructions, but on the ragged scalogram it
@@ -186,12 +186,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
   // and resolves the tile's incoming state by the look-back. Row-serial: a block claims a
   // whole row (longest rows first) and runs its tiles in order, carrying the state in LDS.
   Row row = P.row0;
-  int64_t ti = -1, row_left = 0;   // ti: the tile in hand, its index within its row (-1: none yet)
+  int64_t ti = 0, row_left = 0;
   // row-serial: the block starts on its own XCD's queue and moves on to the next queue only
   // when that one is empty (thread 0 keeps the count of queues it has left behind)
   int qdone = 0;
-  // segments pass without outputs: an output range no tile reaches
-  if (P.seg_mode == 1) row.jout0 = (int64_t)1 << 62;
   for (;;) {
     uint32_t tile;
     if (P.serial) {
@@ -216,16 +214,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         }
         __syncthreads();
         const uint32_t r = __builtin_amdgcn_readfirstlane(s_tile);
-        // segments pass without outputs: the state after the segment just finished (wave 0 left
-        // it for the next tile) is that segment's end state
-        if (P.seg_mode == 1 && ti >= 0 && tid < 2 * KS) P.segstate[ti / P.seg_len * 2 * KS + tid] = s_c[(ti + 1) & 1][tid];
         __syncthreads();   // every wave has read s_tile before thread 0 may claim again
         if (P.seg_mode != 0) {
           if ((int64_t)r >= P.nseg) break;
           ti = (int64_t)r * P.seg_len;
           row_left = row.ntiles - ti < P.seg_len ? row.ntiles - ti : P.seg_len;
-          // the state the segment starts from: zero in the pass without outputs
-          if (tid < 2 * KS) s_c[ti & 1][tid] = P.seg_mode == 2 ? P.segstate[(int64_t)r * 2 * KS + tid] : 0.0;
+          // the state the segment starts from
+          if (tid < 2 * KS) s_c[ti & 1][tid] = P.segstate[(int64_t)r * 2 * KS + tid];
         } else {
           if ((int64_t)r >= P.nrows) break;
           load_row(((cptr<int32_t>)P.row_order)[r], row);
@@ -1087,6 +1082,100 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
+// Segments schedule, first pass: the state at the end of every segment from a zero state at its
+// start,
+//   A_s = sum_{j in segment s} a^{e_s - 1 - j} dy[j]   (e_s: the segment's end position),
+// the same quantity the rows schedule carries from tile to tile, here without the scan inside the
+// tiles: thread c of the block forms its chunk sum B_{t,c} over positions [jt + R c, jt + R c + R)
+// of every tile t of the segment (in float64, by the same Horner steps as the scan), folds them
+// over the tiles, Acc <- a^T Acc + B, weights the fold by a^{R (255 - c)} (its distance to a tile's
+// end), and the block adds the 256 weighted states in a fixed order. One block per segment; no
+// block waits on another.
+template <int K, int R, int DT>
+__global__ __launch_bounds__(kThreads) void seg_sum_kernel(ScanLaunch P) {
+  constexpr int T = R * kThreads;
+  __shared__ double s_sum[kWaves][2 * K];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const Row row = P.row0;
+  const TabLayout lay{K, R};
+  const unsigned char* tb = P.tabs + (int64_t)row.scale * P.tab_stride;
+  const TabT<double> tab{(cptr<double>)(tb + P.f32_bytes), K};
+  const double D = tab.scalar(lay.sD());
+  const void* xs = static_cast<const char*>(P.x) + row.x_off * (DT == 0 ? 4 : 2);
+  const int64_t s = blockIdx.x;
+  const int64_t t0 = s * P.seg_len;
+  const int64_t t1 = t0 + P.seg_len < row.ntiles ? t0 + P.seg_len : row.ntiles;
+  double ar[K], ai[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) { ar[t] = 0; ai[t] = 0; }
+  for (int64_t ti = t0; ti < t1; ++ti) {
+    const int64_t j0 = ti * T + (int64_t)tid * R;
+    double dy[R];
+    const bool fast = (j0 - 2 * row.L >= 0) && (j0 + R <= row.N) &&
+                      ((reinterpret_cast<uintptr_t>(static_cast<const char*>(xs) + (j0 - 2 * row.L) * (DT == 0 ? 4 : 2)) |
+                        reinterpret_cast<uintptr_t>(static_cast<const char*>(xs) + j0 * (DT == 0 ? 4 : 2))) &
+                       (DT == 0 ? 15 : 7)) == 0;
+#pragma unroll
+    for (int q = 0; q < R / 4; ++q) {
+      float ya[4], yb[4];
+      if (fast) {
+        ld4_fast<DT>(xs, j0 + 4 * q, ya);
+        ld4_fast<DT>(xs, j0 + 4 * q - 2 * row.L, yb);
+      } else {
+        load4(xs, DT, j0 + 4 * q, row.N, ya);
+        load4(xs, DT, j0 + 4 * q - 2 * row.L, row.N, yb);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dy[4 * q + r] = fma(-D, (double)yb[r], (double)ya[r]);
+    }
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+      // B = sum_r a^{R-1-r} dy[r], four positions per Horner step (a^1 .. a^4 of the term's block)
+      const int hc = lay.vHC(t);
+      const double a1r = tab.scalar(hc), a1i = tab.scalar(hc + 1), a2r = tab.scalar(hc + 2), a2i = tab.scalar(hc + 3);
+      const double a3r = tab.scalar(hc + 4), a3i = tab.scalar(hc + 5), a4r = tab.scalar(hc + 6), a4i = tab.scalar(hc + 7);
+      double Br = 0, Bi = 0;
+#pragma unroll
+      for (int q = 0; q < R / 4; ++q) {
+        const double d0 = dy[4 * q], d1 = dy[4 * q + 1], d2 = dy[4 * q + 2], d3 = dy[4 * q + 3];
+        const double cr = fma(a3r, d0, fma(a2r, d1, fma(a1r, d2, d3)));
+        const double ci = fma(a3i, d0, fma(a2i, d1, a1i * d2));
+        if (q == 0) {
+          Br = cr;
+          Bi = ci;
+        } else {
+          const double nr = fma(a4r, Br, fma(-a4i, Bi, cr));
+          Bi = fma(a4r, Bi, fma(a4i, Br, ci));
+          Br = nr;
+        }
+      }
+      // Acc <- a^T Acc + B
+      const double cr = tab.re(lay.eWV(kWaves), t), ci = tab.im(lay.eWV(kWaves), t);
+      const double nr = fma(cr, ar[t], fma(-ci, ai[t], Br));
+      ai[t] = fma(cr, ai[t], fma(ci, ar[t], Bi));
+      ar[t] = nr;
+    }
+  }
+  // weight a^{R (255 - c)} = a^{64 R (3 - w)} a^{R (63 - l)}, then the block sum
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const double pr = tab.re(lay.eWV(kWaves - 1 - wid), t), pi = tab.im(lay.eWV(kWaves - 1 - wid), t);
+    const double qr = tab.re(lay.eLANE(63 - lane), t), qi = tab.im(lay.eLANE(63 - lane), t);
+    const double wr = pr * qr - pi * qi, wi = pr * qi + pi * qr;
+    double vr = wr * ar[t] - wi * ai[t], vi = wr * ai[t] + wi * ar[t];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) { vr += __shfl_xor(vr, off, 64); vi += __shfl_xor(vi, off, 64); }
+    if (lane == 0) { s_sum[wid][2 * t] = vr; s_sum[wid][2 * t + 1] = vi; }
+  }
+  __syncthreads();
+  if (tid < 2 * K) {
+    double v = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) v += s_sum[w][tid];
+    P.segstate[s * 2 * K + tid] = v;
+  }
+}
+
 }  // namespace
 
 using KernelFn = void (*)(ScanLaunch);
@@ -1104,6 +1193,9 @@ KernelFn pick_scan(int var, int acc, int gauss, int mom, int dt) {
   if constexpr (R == 16) { MK_PICK_DT(kFwd, kAccKahan, 0, 0) MK_PICK_DT(kFwd, kAccKahan, 1, 0) }
   MK_PICK(kAdj, kAccMixed, 0, 0, 0) MK_PICK(kAdj, kAccMixed, 1, 0, 0) MK_PICK(kAdj, kAccF64, 0, 0, 0) MK_PICK(kAdj, kAccF64, 1, 0, 0)
   MK_PICK_DT(kPg, kAccF64, 0, 0) MK_PICK_DT(kPg, kAccF64, 1, 0) MK_PICK_DT(kPg, kAccF64, 0, 1) MK_PICK_DT(kPg, kAccF64, 1, 1)
+  // the segments schedule's pass without outputs (one per input type)
+  if (var == kSegSum) return dt == 0 ? (KernelFn)seg_sum_kernel<K, R, 0> : dt == 1 ? (KernelFn)seg_sum_kernel<K, R, 1>
+                              : dt == 2 ? (KernelFn)seg_sum_kernel<K, R, 2> : nullptr;
 #undef MK_PICK_FWD
 #undef MK_PICK_DT
 #undef MK_PICK
