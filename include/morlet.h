@@ -296,17 +296,18 @@ morlet_status morlet_plan_set_boundary(morlet_plan_t plan, morlet_boundary bound
  * blocks. MORLET_SCHED_TILES: blocks take single tiles in row order and resolve each
  * tile's incoming state with the decoupled look-back. MORLET_SCHED_ROWS (plans of several
  * rows): a block takes a whole row (longest rows first) and carries the state from tile to
- * tile itself, so no block waits on another. MORLET_SCHED_SEGMENTS (a launch of one row:
- * single-signal plans, a scalogram of one signal and one scale): the row is cut into segments
- * of equal tile counts, about two per resident block; a first launch runs every segment from a
- * zero state without outputs and keeps its end state, a one-wave launch turns those into each
- * segment's incoming state, and a second launch runs the segments again with outputs, each
- * block carrying the state through its segment's tiles as in the rows schedule (the input is
- * read twice; no block waits on another). Elsewhere it acts as AUTO. MORLET_SCHED_AUTO
- * (default): rows when the longest row has no more tiles than one block's share of all tiles;
- * segments for one row of at least two tiles per resident block; else tiles. The schedules are
- * deterministic; they differ only in the float64 rounding of the carried states. The adjoint
- * and gradient passes use tiles or rows. Host-only, no device work. */
+ * tile itself, so no block waits on another. MORLET_SCHED_SEGMENTS (launches of at most eight
+ * rows: single-signal plans, the multiplication method's three rows, small scalograms): every
+ * row is cut into segments of equal tile counts, about two per resident block over all rows; a
+ * first launch forms every segment's end state from a zero start (one block per segment,
+ * without outputs), a second (one block per row) turns those into each segment's incoming
+ * state, and a third runs the segments with outputs, each block carrying the state through its
+ * segment's tiles as in the rows schedule (the input is read twice; no block waits on another).
+ * For more rows it acts as AUTO. MORLET_SCHED_AUTO (default): rows when the longest row has no
+ * more tiles than one block's share of all tiles; else segments for at most eight rows with at
+ * least two tiles per resident block; else tiles. The schedules are deterministic; they differ
+ * only in the float64 rounding of the carried states. The adjoint and gradient passes use tiles
+ * or rows. Host-only, no device work. */
 typedef enum {
   MORLET_SCHED_AUTO = 0,
   MORLET_SCHED_TILES = 1,
@@ -322,8 +323,8 @@ morlet_status morlet_plan_set_segments(morlet_plan_t plan, int32_t tiles_per_seg
 
 /* Autotuner: times this plan's forward launch on the caller's input x (device, dtype) for each
  * tile shape (R = 16, 32, 8, 4, in that order; a shape the plan cannot take is skipped) and,
- * each schedule the plan can take (tiles; rows for several rows; segments for one row, except
- * multiplication-method plans): one warm-up launch, then `reps` launches
+ * each schedule the plan can take (tiles; rows for several rows; segments for at most eight
+ * rows): one warm-up launch, then `reps` launches
  * (1..1000) timed with HIP events on `stream`; keeps the fastest (ties: the earlier
  * candidate) as the plan's tile shape and schedule. out (device) receives the
  * trial outputs: any buffer of the forward's output size, overwritten. A setup call: it

@@ -390,27 +390,37 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   // every block then runs whole rows, longest first, carrying the state from tile to tile
   // in LDS, and no tile waits on another block.
   a.serial = 0;
-  if (plan->batched && a.nrows > 1 && plan->row_serial != 0) {
+  if (plan->batched && a.nrows > 1 && plan->row_serial != 0 && !(plan->row_serial == 2 && a.nrows <= mk::kQueues)) {
     const int64_t share = (ntiles + cap - 1) / cap;
     if (plan->row_serial == 1 || plan->max_row_tiles <= share) {
       a.serial = 1;
       a.grid = (int)(a.nrows < cap ? a.nrows : cap);
     }
   }
-  // Segments schedule for a forward launch of one row: chosen, or automatic when the row has at
-  // least two tiles per resident block. About two segments per block (the ticket balances them),
-  // at most 64 x 64 tiles each (the reach of the table's look-back weights). The segment states
+  // Segments schedule for a forward launch of at most eight rows that the rows schedule did not
+  // take: chosen, or automatic when the launch has at least two tiles per resident block. About
+  // two segments per block over all rows (the ticket balances them), at most 64 x 64 tiles each
+  // (the reach of the table's look-back weights), every row cut on its own. The segment states
   // sit in the workspace after its header (within what the tiles schedule needs).
   a.nseg = 0;
-  if (variant == mk::kVarForward && a.nrows == 1 && ntiles >= 2 &&
+  if (variant == mk::kVarForward && !a.serial && a.nrows >= 1 && a.nrows <= mk::kQueues && ntiles >= 2 &&
       (plan->row_serial == 2 || (plan->row_serial == -1 && ntiles >= 2 * cap))) {
     int64_t len = plan->seg_tiles > 0 ? plan->seg_tiles : (ntiles + 2 * cap - 1) / (2 * cap);
     if (len > (int64_t)mk::kLookback * mk::kLookback) len = (int64_t)mk::kLookback * mk::kLookback;
-    a.seg_len = (int)len;
-    a.nseg = (ntiles + len - 1) / len;
-    a.serial = 1;
-    a.grid = (int)(a.nseg < cap ? a.nseg : cap);
-    a.segstate = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + sizeof(mk::WsHeader));
+    int64_t nseg = 0;
+    a.seg_start[0] = 0;
+    for (int r = 0; r < a.nrows; ++r) {
+      const int64_t nt = a.nrows == 1 ? a.row0.ntiles : (int64_t)plan->rows[r].ntiles;
+      nseg += (nt + len - 1) / len;
+      a.seg_start[r + 1] = (int32_t)nseg;
+    }
+    if (nseg > 0) {
+      a.seg_len = (int)len;
+      a.nseg = nseg;
+      a.serial = 1;
+      a.grid = (int)(a.nseg < cap ? a.nseg : cap);
+      a.segstate = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + sizeof(mk::WsHeader));
+    }
   }
   return MORLET_OK;
 }
@@ -1649,8 +1659,8 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
     }
   }
   const int oldR = plan->R, oldSched = plan->row_serial;
-  // schedules: tiles, whole rows (several rows), segments (one row)
-  const bool one_row = !plan->batched || plan->rows.size() == 1;
+  // schedules: tiles, whole rows (several rows), segments (at most eight rows)
+  const size_t nrows = plan->batched ? plan->rows.size() : 1;
   struct Cand { int R, rows; };
   std::vector<Cand> cands;
   // one workspace serves every candidate: the largest of their sizes. A tile shape the plan
@@ -1668,11 +1678,8 @@ morlet_status morlet_plan_autotune(morlet_plan_t plan, const void* x, morlet_dty
     }
     need = std::max(need, b);
     cands.push_back({R, 0});
-    if (one_row) {
-      if (!plan->multiply) cands.push_back({R, 2});
-    } else if (plan->batched) {
-      cands.push_back({R, 1});
-    }
+    if (nrows > 1) cands.push_back({R, 1});
+    if (nrows <= (size_t)mk::kQueues) cands.push_back({R, 2});
   }
   if (cands.empty()) {
     (void)morlet_plan_set_tile(plan, oldR);

@@ -32,12 +32,14 @@ struct ScanLaunch {
   int grid;                     // persistent grid size
   const void* g;                // gradient pass: cotangent at the outputs (complex64 or float32)
   double* partials;             // gradient pass: per-tile float64 partial sums
-  // Segments schedule (forward, one row): the row's tiles in nseg segments of seg_len tiles
-  // (the last one shorter). seg_mode 1 (set for the launch with outputs): blocks take segments
-  // through the ticket and run each segment's tiles in order from the state segstate holds for it.
+  // Segments schedule (forward, at most kQueues rows): each row's tiles in segments of seg_len
+  // tiles (its last one shorter), the segments of row r numbered [seg_start[r], seg_start[r + 1]).
+  // seg_mode 1 (set for the launch with outputs): blocks take segments through the ticket and run
+  // each segment's tiles in order from the state segstate holds for it.
   int seg_mode;
   int seg_len;
   int64_t nseg;                 // 0: not this schedule
+  int32_t seg_start[kQueues + 1];
   double* segstate;             // device [nseg][2 K] float64 (re, im per term), in the workspace
 };
 

@@ -148,9 +148,9 @@ __global__ __launch_bounds__(256) void sum_scales_kernel(const float* part, floa
   }
 }
 
-// Segments schedule, between its two passes (one block): the segment sums have left in
+// Segments schedule, between its two passes (one block per row): the segment sums have left in
 // segstate[s] the state A_s at the end of segment s from a zero state at its start. The state
-// at the start of segment s is
+// at the start of the row's segment s is
 //   S_0 = 0,  S_{s+1} = c S_s + A_s,  c = a^{T len} (per term; every segment but the last, which
 // precedes none, has len tiles of T positions),
 // written over A_s. In rounds of 1024 segments, four consecutive ones per thread (their loads in
@@ -165,8 +165,10 @@ __global__ __launch_bounds__(256) void seg_combine_kernel(ScanLaunch P) {
   constexpr int NW = 4, NT = NW * 64, Q = 4;
   __shared__ double s_tot[NW][2 * K];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int rr = blockIdx.x;   // one block per row
+  const Row row = P.nrows == 1 ? P.row0 : P.rows[rr];
   const TabLayout lay{K, P.R};
-  const Tab<true> tabd{(cptr<double>)(P.tabs + (int64_t)P.row0.scale * P.tab_stride + P.f32_bytes), K};
+  const Tab<true> tabd{(cptr<double>)(P.tabs + (int64_t)row.scale * P.tab_stride + P.f32_bytes), K};
   const int len = P.seg_len;
   auto cmul = [](double ar, double ai, double br, double bi, double& outr, double& outi) {
     outr = ar * br - ai * bi;
@@ -183,8 +185,8 @@ __global__ __launch_bounds__(256) void seg_combine_kernel(ScanLaunch P) {
            tabd.re(lay.eLB(len % kLookback), t), tabd.im(lay.eLB(len % kLookback), t), cr[t], ci[t]);
     }
   }
-  const int64_t n = P.nseg;
-  double* st = P.segstate;
+  const int64_t n = P.seg_start[rr + 1] - P.seg_start[rr];
+  double* st = P.segstate + (int64_t)P.seg_start[rr] * 2 * K;
   double carry_r[K], carry_i[K];   // the state entering the round
 #pragma unroll
   for (int t = 0; t < K; ++t) { carry_r[t] = 0; carry_i[t] = 0; }
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(256) void seg_combine_kernel(ScanLaunch P) {
 hipError_t launch_seg_combine(const ScanLaunch& a, hipStream_t s) {
   switch (a.K) {
 #define MK_SEG(K) \
-  case K: hipLaunchKernelGGL(seg_combine_kernel<K>, dim3(1), dim3(256), 0, s, a); break;
+  case K: hipLaunchKernelGGL(seg_combine_kernel<K>, dim3(a.nrows), dim3(256), 0, s, a); break;
     MK_SEG(1) MK_SEG(2) MK_SEG(3) MK_SEG(4) MK_SEG(5) MK_SEG(6) MK_SEG(7) MK_SEG(8) MK_SEG(9) MK_SEG(10)
     MK_SEG(11) MK_SEG(12)
 #undef MK_SEG
@@ -298,8 +300,8 @@ hipError_t launch_scan(const ScanLaunch& a, int variant, int mom, hipStream_t s)
   KernelFn fn = select_kernel(a.K, a.R, variant, a.acc, a.kind, mom, variant == kVarAdjoint ? 0 : a.dtype);
   if (!fn) return hipErrorInvalidValue;
   if (a.nseg > 0) {
-    if (variant != kVarForward || !a.serial || a.nrows != 1 || !a.segstate || a.seg_len < 1 ||
-        a.seg_len > kLookback * kLookback)
+    if (variant != kVarForward || !a.serial || a.nrows < 1 || a.nrows > kQueues || !a.segstate || a.seg_len < 1 ||
+        a.seg_len > kLookback * kLookback || a.seg_start[0] != 0 || a.seg_start[a.nrows] != a.nseg)
       return hipErrorInvalidValue;
     KernelFn sum = select_kernel(a.K, a.R, kVarSegSum, 0, 0, 0, a.dtype);
     if (!sum || a.nseg > 0x7fffffff) return hipErrorInvalidValue;

@@ -217,7 +217,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         __syncthreads();   // every wave has read s_tile before thread 0 may claim again
         if (P.seg_mode != 0) {
           if ((int64_t)r >= P.nseg) break;
-          ti = (int64_t)r * P.seg_len;
+          int q = 0;   // the segment's row
+          while (q + 1 < P.nrows && (int32_t)r >= P.seg_start[q + 1]) ++q;
+          if (P.nrows != 1) load_row(q, row);
+          ti = (int64_t)((int32_t)r - P.seg_start[q]) * P.seg_len;
           row_left = row.ntiles - ti < P.seg_len ? row.ntiles - ti : P.seg_len;
           // the state the segment starts from
           if (tid < 2 * KS) s_c[ti & 1][tid] = P.segstate[(int64_t)r * 2 * KS + tid];
@@ -1096,14 +1099,22 @@ __global__ __launch_bounds__(kThreads) void seg_sum_kernel(ScanLaunch P) {
   constexpr int T = R * kThreads;
   __shared__ double s_sum[kWaves][2 * K];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const Row row = P.row0;
+  const int64_t s = blockIdx.x;
+  int rr = 0;   // the segment's row
+  while (rr + 1 < P.nrows && s >= P.seg_start[rr + 1]) ++rr;
+  Row row = P.row0;
+  if (P.nrows != 1) {
+    const cptr<Row> rp = (cptr<Row>)P.rows + rr;
+    row.x_off = rp->x_off; row.w_off = rp->w_off; row.N = rp->N; row.L = rp->L;
+    row.jout0 = rp->jout0; row.jend = rp->jend; row.tile0 = rp->tile0;
+    row.scale = rp->scale; row.ntiles = rp->ntiles;
+  }
   const TabLayout lay{K, R};
   const unsigned char* tb = P.tabs + (int64_t)row.scale * P.tab_stride;
   const TabT<double> tab{(cptr<double>)(tb + P.f32_bytes), K};
   const double D = tab.scalar(lay.sD());
   const void* xs = static_cast<const char*>(P.x) + row.x_off * (DT == 0 ? 4 : 2);
-  const int64_t s = blockIdx.x;
-  const int64_t t0 = s * P.seg_len;
+  const int64_t t0 = (s - P.seg_start[rr]) * P.seg_len;
   const int64_t t1 = t0 + P.seg_len < row.ntiles ? t0 + P.seg_len : row.ntiles;
   double ar[K], ai[K];
 #pragma unroll

@@ -1,11 +1,11 @@
-"""The segments schedule of a single long row against the FP64 oracle: the row cut into segments
-of equal tile counts, a launch for each segment's end state from a zero start, a one-wave
-combination of those into each segment's incoming state, and a launch with outputs. Cases cover
-one-tile segments with more segments than the combining wave has lanes (several per lane),
-several tiles per segment with a ragged last segment, segments longer than 64 tiles (the second
-level of the look-back weights), the automatic length, Morlet, Gaussian and Gaussian differential
-plans in every accumulation, and agreement with the tiles schedule. Bar: relative L2 1e-5 (float32
-scan), 1e-6 (float64)."""
+"""The segments schedule against the FP64 oracle: every row cut into segments of equal tile
+counts, a launch for each segment's end state from a zero start, a combination of those into
+each segment's incoming state (one block per row), and a launch with outputs. Cases cover
+one-tile segments (several per thread of the combination), several tiles per segment with a
+ragged last segment, segments longer than 64 tiles (the second level of the look-back weights),
+the automatic length, Morlet, Gaussian and Gaussian differential plans in every accumulation,
+launches of several rows (a small scalogram, the multiplication method's three rows), and
+agreement with the tiles schedule. Bar: relative L2 1e-5 (float32 scan), 1e-6 (float64)."""
 import sys
 
 import numpy as np
@@ -126,3 +126,51 @@ def test_segments_against_tiles(mode):
     torch.cuda.synchronize()
     an, bn = a.cpu().numpy(), b.cpu().numpy()
     assert rel_l2(bn, an) <= 1e-6, rel_l2(bn, an)
+
+
+@pytest.mark.parametrize("seg", [3, 0])
+def test_scalogram_few_rows_segments(seg):
+    # a scalogram of two signals x two scales (four rows of different lengths and scales, within
+    # the eight rows the schedule takes), every row cut on its own
+    import paper_2110_11866_amd as M
+    _announce("segments-scalogram", seg)
+    lengths = [250_000, 131_071]
+    sigmas = [30.0, 300.0]
+    xis = [6.0 / s for s in sigmas]
+    x = np.random.default_rng(11).standard_normal(sum(lengths)).astype(np.float32)
+    plan = M.ScalogramPlan(lengths, sigmas, xis, 5, 0.0, mode="asft")
+    plan.set_tile(4).set_schedule("segments").set_segments(seg)
+    xt = torch.from_numpy(x).cuda()
+    W = plan.forward(xt).cpu().numpy()
+    ref = plan.set_schedule("tiles").forward(xt).cpu().numpy()
+    assert rel_l2(W, ref) <= 1e-6, rel_l2(W, ref)
+    offs = np.concatenate([[0], np.cumsum(lengths)])
+    for s in range(len(sigmas)):
+        info = plan.scale_info(s)
+        p = O.plan_morlet(sigmas[s], xis[s], 5, info["L"], mode="asft", n0=info["n0"])
+        assert p.P_S == info["P_S"]
+        for b in range(len(lengths)):
+            o = plan.out_offset(b, s)
+            want = O.forward(x[offs[b]:offs[b + 1]].astype(np.float64), p)
+            got = W[o:o + lengths[b]]
+            assert rel_l2(got, want) <= 1e-5, (b, s, rel_l2(got, want))
+
+
+@pytest.mark.parametrize("seg", [2, 0])
+def test_multiply_segments(seg):
+    # the multiplication method's three Gaussian rows under the segments schedule, against the
+    # tiles schedule and the oracle
+    import paper_2110_11866_amd as M
+    _announce("segments-multiply", seg)
+    N, sigma, PM = 400_000, 48.0, 2
+    x = np.random.default_rng(13).standard_normal(N).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    plan = M.MultiplyPlan(N, sigma, 6.0 / sigma, PM)
+    plan.set_tile(4).set_schedule("segments").set_segments(seg)
+    got = plan.forward(xt).cpu().numpy()
+    ref = plan.set_schedule("tiles").forward(xt).cpu().numpy()
+    assert rel_l2(got, ref) <= 1e-6, rel_l2(got, ref)
+    info = plan.info()
+    p = O.plan_multiply(sigma, 6.0 / sigma, PM, info["L"])
+    want = O.forward(x.astype(np.float64), p)
+    assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
