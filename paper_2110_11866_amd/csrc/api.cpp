@@ -412,9 +412,9 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
     for (int r = 0; r < a.nrows; ++r) {
       const int64_t nt = a.nrows == 1 ? a.row0.ntiles : (int64_t)plan->rows[r].ntiles;
       nseg += (nt + len - 1) / len;
-      a.seg_start[r + 1] = (int32_t)nseg;
+      a.seg_start[r + 1] = (int32_t)std::min<int64_t>(nseg, INT32_MAX);
     }
-    if (nseg > 0) {
+    if (nseg > 0 && nseg <= INT32_MAX) {
       a.seg_len = (int)len;
       a.nseg = nseg;
       a.serial = 1;
