@@ -317,8 +317,9 @@ typedef enum {
 morlet_status morlet_plan_set_schedule(morlet_plan_t plan, morlet_schedule schedule);
 
 /* Segments schedule: tiles per segment, 1..4096, or 0 (default) for the automatic length
- * ceil(tiles / (2 x resident blocks)). The length sets the float64 rounding of the carried
- * states, not the result otherwise. Host-only; MORLET_ERR_INVALID_ARG outside [0, 4096]. */
+ * max(ceil(tiles / (2 x resident blocks)), ceil(longest row's tiles / 1024)). The length sets
+ * the float64 rounding of the carried states, not the result otherwise. Host-only;
+ * MORLET_ERR_INVALID_ARG outside [0, 4096]. */
 morlet_status morlet_plan_set_segments(morlet_plan_t plan, int32_t tiles_per_segment);
 
 /* Autotuner: times this plan's forward launch on the caller's input x (device, dtype) for each

@@ -405,7 +405,15 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   a.nseg = 0;
   if (variant == mk::kVarForward && !a.serial && a.nrows >= 1 && a.nrows <= mk::kQueues && ntiles >= 2 &&
       (plan->row_serial == 2 || (plan->row_serial == -1 && ntiles >= 2 * cap))) {
-    int64_t len = plan->seg_tiles > 0 ? plan->seg_tiles : (ntiles + 2 * cap - 1) / (2 * cap);
+    // automatic length: about two segments per resident block, and at most 1024 segments per row
+    // (one round of the combination, which runs on one CU per row)
+    int64_t len = plan->seg_tiles;
+    if (len <= 0) {
+      int64_t longest = 0;
+      for (int r = 0; r < a.nrows; ++r)
+        longest = std::max<int64_t>(longest, a.nrows == 1 ? a.row0.ntiles : (int64_t)plan->rows[r].ntiles);
+      len = std::max<int64_t>((ntiles + 2 * cap - 1) / (2 * cap), (longest + 1023) / 1024);
+    }
     if (len > (int64_t)mk::kLookback * mk::kLookback) len = (int64_t)mk::kLookback * mk::kLookback;
     int64_t nseg = 0;
     a.seg_start[0] = 0;
