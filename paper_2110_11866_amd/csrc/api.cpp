@@ -164,11 +164,20 @@ void build_row_queues(morlet_plan_s* p) {
   p->row_order.clear();
   p->max_row_tiles = 0;
   for (int i = 0; i < nq; ++i) {
-    std::stable_sort(q[i].begin(), q[i].end(),
-                     [&](int32_t a, int32_t b) { return p->rows[a].ntiles > p->rows[b].ntiles; });
+    // whole signals: in the order they were dealt (most work first), each signal's rows
+    // together, longest first, so that the blocks running at once on the queue's XCD share few
+    // signals and find them in its L2; single rows: longest first
+    if (by_signal) {   // the queue holds whole signals, S consecutive rows each
+      for (size_t k = 0; k + (size_t)S <= q[i].size(); k += (size_t)S)
+        std::stable_sort(q[i].begin() + k, q[i].begin() + k + S,
+                         [&](int32_t a, int32_t b) { return p->rows[a].ntiles > p->rows[b].ntiles; });
+    } else {
+      std::stable_sort(q[i].begin(), q[i].end(),
+                       [&](int32_t a, int32_t b) { return p->rows[a].ntiles > p->rows[b].ntiles; });
+    }
     p->qstart[i] = (int32_t)p->row_order.size();
     p->row_order.insert(p->row_order.end(), q[i].begin(), q[i].end());
-    if (!q[i].empty()) p->max_row_tiles = std::max<int64_t>(p->max_row_tiles, p->rows[q[i][0]].ntiles);
+    for (int32_t r : q[i]) p->max_row_tiles = std::max<int64_t>(p->max_row_tiles, p->rows[r].ntiles);
   }
   p->qstart[nq] = (int32_t)p->row_order.size();
 }
