@@ -65,6 +65,23 @@ def test_graph_forward_single(mode):
     _replays(lambda: (plan.forward(xt, out=out, ws=ws),), xt, fresh)
 
 
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_graph_forward_segments(mode):
+    # the segments schedule's three launches (segment sums, combination, scan with outputs)
+    # captured together: 300 000 samples at R = 4, segments of 3 tiles
+    import paper_2110_11866_amd as M
+    _announce("graph-segments", mode)
+    N = 300_000
+    rng = np.random.default_rng(23)
+    xt = torch.from_numpy(rng.standard_normal(N).astype(np.float32)).cuda()
+    plan = M.MorletPlan(N, 64.0, 6 / 64.0, 5, 256, mode=mode)
+    plan.set_tile(4).set_schedule("segments").set_segments(3)
+    ws = plan.workspace(xt.device)
+    out = torch.empty(N, dtype=torch.complex64, device=xt.device)
+    fresh = lambda k: torch.from_numpy(np.random.default_rng(200 + k).standard_normal(N).astype(np.float32)).cuda()
+    _replays(lambda: (plan.forward(xt, out=out, ws=ws),), xt, fresh)
+
+
 @pytest.mark.parametrize("schedule", ["tiles", "rows"])
 def test_graph_forward_scalogram(schedule):
     import paper_2110_11866_amd as M
