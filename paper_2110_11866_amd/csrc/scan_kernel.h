@@ -518,23 +518,41 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
       //     (lane i owns state i, the E_w vector lives in the wave's own s_e slot); wave 0
       //     advances the running state to Op(T) P + A, A = sum_w Op(64 R (W-1-w)) agg_w.
       const double* cin = &s_c[ti & 1][0];
-      if (lane < KS) { s_e[wid][2 * lane] = 0; s_e[wid][2 * lane + 1] = 0; }
-      wave_lds_sync();
-      for (int w = 0; w < wid; ++w) {
-        double cr = 0, ci = 0;
-        if (lane < KS) op_c(5, lay.eWV(1), &s_e[wid][0], cr, ci);
-        wave_lds_sync();
+      if constexpr (!MOM) {
+        // without moment states Op acts on each state alone, so lane i forms its state of
+        // E_w = sum_{k < w} Op(64 R k) agg_{w-1-k} directly, the terms independent of each other
         if (lane < KS) {
-          s_e[wid][2 * lane] = cr + s_wagg[par][w][2 * lane];
-          s_e[wid][2 * lane + 1] = ci + s_wagg[par][w][2 * lane + 1];
+          double er = 0, ei = 0;
+          for (int k = 0; k < wid; ++k) {
+            double cr, ci;
+            op_c(4 + k, lay.eWV(k), &s_wagg[par][wid - 1 - k][0], cr, ci);
+            er += cr;
+            ei += ci;
+          }
+          double cr = 0, ci = 0;
+          if (ti > 0) op_c(4 + wid, lay.eWV(wid), cin, cr, ci);
+          s_xw[wid][2 * lane] = er + cr;
+          s_xw[wid][2 * lane + 1] = ei + ci;
         }
+      } else {
+        if (lane < KS) { s_e[wid][2 * lane] = 0; s_e[wid][2 * lane + 1] = 0; }
         wave_lds_sync();
-      }
-      if (lane < KS) {
-        double cr = 0, ci = 0;
-        if (ti > 0) op_c(4 + wid, lay.eWV(wid), cin, cr, ci);
-        s_xw[wid][2 * lane] = s_e[wid][2 * lane] + cr;
-        s_xw[wid][2 * lane + 1] = s_e[wid][2 * lane + 1] + ci;
+        for (int w = 0; w < wid; ++w) {
+          double cr = 0, ci = 0;
+          if (lane < KS) op_c(5, lay.eWV(1), &s_e[wid][0], cr, ci);
+          wave_lds_sync();
+          if (lane < KS) {
+            s_e[wid][2 * lane] = cr + s_wagg[par][w][2 * lane];
+            s_e[wid][2 * lane + 1] = ci + s_wagg[par][w][2 * lane + 1];
+          }
+          wave_lds_sync();
+        }
+        if (lane < KS) {
+          double cr = 0, ci = 0;
+          if (ti > 0) op_c(4 + wid, lay.eWV(wid), cin, cr, ci);
+          s_xw[wid][2 * lane] = s_e[wid][2 * lane] + cr;
+          s_xw[wid][2 * lane + 1] = s_e[wid][2 * lane + 1] + ci;
+        }
       }
       if (wid == 0 && lane < KS) {
         double Ar = 0, Ai = 0;
@@ -709,14 +727,34 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
         for (int t = 0; t < K; ++t) { kcr[t] = tabd.re(e, t); kci[t] = tabd.im(e, t); }
       }
       // Z_{r+1} overwrites T_r in place (each lane rewrites only its own state of it)
+      if constexpr (!MOM && KCACHE) {
+        // each state on its own: lane i carries its Z in registers, one LDS round at the end
+        if (P.serial && lane < KS) {
+          const double ar = s_k[1][2 * (lane % K)], ai = s_k[1][2 * (lane % K) + 1];
+          double zr = s_xw[wid][2 * lane], zi = s_xw[wid][2 * lane + 1];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        if (lane < KS) {
-          double cr, ci;
-          op_c(1, lay.eLANE(16), r == 0 ? &s_xw[wid][0] : &s_rt[wid][r - 1][0], cr, ci);
-          s_rt[wid][r][2 * lane] += cr;
-          s_rt[wid][r][2 * lane + 1] += ci;
+          for (int r = 0; r < 3; ++r) {
+            double cr = 0, ci = 0;
+            cmac(cr, ci, ar, ai, zr, zi);
+            zr = s_rt[wid][r][2 * lane] + cr;
+            zi = s_rt[wid][r][2 * lane + 1] + ci;
+            s_rt[wid][r][2 * lane] = zr;
+            s_rt[wid][r][2 * lane + 1] = zi;
+          }
         }
+      }
+      if (!(!MOM && KCACHE) || !P.serial) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          if (lane < KS) {
+            double cr, ci;
+            op_c(1, lay.eLANE(16), r == 0 ? &s_xw[wid][0] : &s_rt[wid][r - 1][0], cr, ci);
+            s_rt[wid][r][2 * lane] += cr;
+            s_rt[wid][r][2 * lane + 1] += ci;
+          }
+          wave_lds_sync();
+        }
+      } else {
         wave_lds_sync();
       }
       const double* z = rw == 0 ? &s_xw[wid][0] : &s_rt[wid][rw - 1][0];
