@@ -351,13 +351,16 @@ morlet_status make_launch(morlet_plan_t plan, mk::ScanLaunch& a, void* ws, int v
   a.K = plan->K;
   a.R = plan->R;
   // the gradient pass always accumulates in float64: the chain rule through the fitted
-  // coefficients cancels the per-term sums by orders of magnitude; the adjoint runs the
-  // float64 or the mixed scan (the float32 tile scan is built for the forward)
+  // coefficients cancels the per-term sums by orders of magnitude; the adjoint runs the float64
+  // scan, the float32 tile scan under ASFT (whose attenuation bounds what float32 rounding
+  // leaves in the state, as in the forward), else the mixed scan
   const int accum = plan->accum == MORLET_ACC_AUTO
                         ? (plan->mode == 1 && !recompute ? MORLET_ACC_F32 : MORLET_ACC_MIXED)
                         : plan->accum;
   a.acc = variant == mk::kVarParamGrad ? mk::kAccF64
-          : variant == mk::kVarAdjoint ? (accum == MORLET_ACC_F64 ? mk::kAccF64 : mk::kAccMixed)
+          : variant == mk::kVarAdjoint ? (accum == MORLET_ACC_F64                            ? mk::kAccF64
+                                          : (accum == MORLET_ACC_F32 && plan->mode == 1) ? mk::kAccF32
+                                                                                          : mk::kAccMixed)
           : accum == MORLET_ACC_KAHAN  ? mk::kAccKahan
                                        : accum;
   // differentials: 2 real output from the sines (SFT, first), 1 from the cosines (SFT,

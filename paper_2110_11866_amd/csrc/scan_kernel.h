@@ -96,7 +96,7 @@ __device__ __forceinline__ void cmac(T& zr, T& zi, T cr, T ci, T xr, T xi) {  //
 // ACC: arithmetic of the scan (the library's morlet_accum values)
 //   kAccF32   : float32 for the per-thread work (chunk sums, 16-lane wave scan, recurrence,
 //               combination); float64 only for the carries between rows of a wave, waves and
-//               tiles (forward only).
+//               tiles (forward and adjoint).
 //   kAccF64   : float64 scan state, carries and combination.
 //   kAccMixed : float64 chunk sums and wave scan, float32 recurrence and combination.
 //   kAccKahan : the per-thread work of kAccF32 (chunk sums, wave scan, recurrence, combination)
@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
   constexpr bool WIDE = ACC == kAccF64;
   constexpr bool F32T = ACC == kAccF32;                  // float32 tile scan
   constexpr bool KAHAN = ACC == kAccKahan;               // compensated float32 tile scan
-  static_assert(!(F32T || KAHAN) || VAR == kFwd, "the float32 tile scans are built for the forward");
+  static_assert(!KAHAN || VAR == kFwd, "the compensated tile scan is built for the forward");
+  static_assert(!F32T || VAR != kPg, "the float32 tile scan is not built for the gradient pass");
   // recurrence and combination; chunk sums and wave scan
   using acc_t = typename std::conditional<WIDE, double, typename std::conditional<KAHAN, ff, float>::type>::type;
   using sc_t = typename std::conditional<F32T, float, typename std::conditional<KAHAN, ff, double>::type>::type;
@@ -1241,6 +1242,7 @@ KernelFn pick_scan(int var, int acc, int gauss, int mom, int dt) {
   // the compensated scan (a precision reference): Morlet and Gaussian smoothing, one tile shape
   if constexpr (R == 16) { MK_PICK_DT(kFwd, kAccKahan, 0, 0) MK_PICK_DT(kFwd, kAccKahan, 1, 0) }
   MK_PICK(kAdj, kAccMixed, 0, 0, 0) MK_PICK(kAdj, kAccMixed, 1, 0, 0) MK_PICK(kAdj, kAccF64, 0, 0, 0) MK_PICK(kAdj, kAccF64, 1, 0, 0)
+  MK_PICK(kAdj, kAccF32, 0, 0, 0) MK_PICK(kAdj, kAccF32, 1, 0, 0)
   MK_PICK_DT(kPg, kAccF64, 0, 0) MK_PICK_DT(kPg, kAccF64, 1, 0) MK_PICK_DT(kPg, kAccF64, 0, 1) MK_PICK_DT(kPg, kAccF64, 1, 1)
   // the segments schedule's pass without outputs (one per input type)
   if (var == kSegSum) return dt == 0 ? (KernelFn)seg_sum_kernel<K, R, 0> : dt == 1 ? (KernelFn)seg_sum_kernel<K, R, 1>
