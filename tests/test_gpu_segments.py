@@ -174,3 +174,46 @@ def test_multiply_segments(seg):
     p = O.plan_multiply(sigma, 6.0 / sigma, PM, info["L"])
     want = O.forward(x.astype(np.float64), p)
     assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_half_inputs_segments(dtype, mode):
+    # 16-bit stored inputs through the segment sums' 16-bit loads and the scan with outputs;
+    # the oracle sees the stored values (a random walk plus noise, 196 tiles in segments of 3)
+    import paper_2110_11866_amd as M
+    _announce("segments-half", dtype, mode)
+    N, sigma, K, L = 200_000, 64.0, 5, 256
+    x = (np.cumsum(np.random.default_rng(29).standard_normal(N)) / 30).astype(np.float32)
+    xt = torch.from_numpy(x).cuda().to(dtype)
+    plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, L, mode=mode)
+    plan.set_tile(4).set_schedule("segments").set_segments(3)
+    got = plan.forward(xt).cpu().numpy()
+    info = plan.info()
+    p = O.plan_morlet(sigma, 6.0 / sigma, K, info["L"], mode=mode, n0=info["n0"] if mode == "asft" else None)
+    want = O.forward(xt.double().cpu().numpy(), p)
+    assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
+
+
+@pytest.mark.parametrize("kind", ["morlet", "gauss"])
+@pytest.mark.parametrize("mode", ["sft", "asft"])
+def test_edge_extension_segments(kind, mode):
+    # edge extension (the padded copy in the workspace) followed by the segments schedule
+    import paper_2110_11866_amd as M
+    _announce("segments-edge", kind, mode)
+    N, sigma, K = 150_000, 40.0, 5
+    x = (np.random.default_rng(31).standard_normal(N) + 2.0).astype(np.float32)
+    xt = torch.from_numpy(x).cuda()
+    if kind == "morlet":
+        plan = M.MorletPlan(N, sigma, 6.0 / sigma, K, 160, mode=mode)
+    else:
+        plan = M.GaussPlan(N, sigma, K, 160, mode=mode)
+    plan.set_boundary("edge")
+    plan.set_tile(4).set_schedule("segments").set_segments(2)
+    got = plan.forward(xt).cpu().numpy()
+    info = plan.info()
+    n0 = info["n0"] if mode == "asft" else None
+    p = (O.plan_morlet(sigma, 6.0 / sigma, K, info["L"], mode=mode, n0=n0) if kind == "morlet"
+         else O.plan_gauss(sigma, K, info["L"], mode=mode, n0=n0))
+    want = O.forward_edge(x.astype(np.float64), p)
+    assert rel_l2(got, want) <= 1e-5, rel_l2(got, want)
