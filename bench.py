@@ -543,7 +543,7 @@ def bench_paper_scale(args, torch, M):
 def main():
     args = _parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU: the scans shard across signals and scales without communication, and only the one-GPU share is measured; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
